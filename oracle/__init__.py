@@ -1,0 +1,18 @@
+"""FP64 CPU oracle of distributed FastMNMF -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
+leg may import anything under ``oracle/``.  The library product path never
+does, and has no CPU fallback.
+
+* ``oracle.dfmnmf``       -- the method itself: eqs. (2), (8)-(10), (13)-(16),
+  the iteration schedule and the per-subarray multichannel Wiener filter.
+* ``oracle.conventional`` -- conventional FastMNMF, eqs. (4)-(7) with (8)-(10),
+  written separately in the paper's notation (pin for L = 1 and per-block IP).
+* ``oracle.fullcov``      -- brute force from the full covariance of eq. (1) and
+  the appendix theorem's commutator test.
+
+Every function is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_pins.py``
+(brute force, closed forms, special cases, finite-difference identities,
+monotonicity); none is "parity unpinned".
+"""
+from . import conventional, dfmnmf, fullcov  # noqa: F401
