@@ -1,0 +1,147 @@
+/*
+ * dfmnmf.h -- C ABI of distributed FastMNMF on AMD MI355X (gfx950).
+ *
+ * Distributed FastMNMF (Sec. III-B of the paper) separates N sources from a
+ * multichannel STFT observed by L subarrays.  The source spatial covariances
+ * are block-diagonal over the subarray partition (eq. (11)) and jointly
+ * diagonalised within each block (eq. (12)); the source power spectrograms
+ * are an NMF with K bases per source (eq. (2)), shared by all subarrays.
+ * One iteration updates, in this order (Sec. III-B):
+ *   - every subarray's transformation Q_fl by iterative projection,
+ *     eqs. (14)-(16), rows in ascending order;
+ *   - the bases W (eq. (8)), activations H (eq. (9)) and diagonal SCMs g
+ *     (eq. (10)), the model variance refreshed after each.
+ *
+ * Symbols (paper -> this ABI): frequency i -> f (F bins), frame j -> t
+ * (T frames), W_i^(l)H -> Q_fl (row mu is w_mu^H), t_ikn -> W[n][f][k],
+ * v_kjn -> H[n][k][t], [Lambda_in]_mm -> g[f][n][m].
+ *
+ * Every device buffer is owned by the caller.  The library never allocates
+ * device memory: its temporaries live in the caller's workspace.  All
+ * pointers below are device pointers unless stated otherwise; "stream" is a
+ * hipStream_t passed as void* (NULL = the default stream).  Calls are
+ * asynchronous on that stream unless stated otherwise.  A plan is used by one
+ * stream at a time; plans are independent of each other.
+ *
+ * Errors: every call returns a dfm_status; nothing else crosses the ABI.
+ * Argument and shape errors are found on the host before anything is
+ * launched.  Conditions found on the device (a singular IP system, a
+ * non-finite parameter) are recorded in a sticky word in the workspace and
+ * returned by the next synchronising call (dfm_nll, dfm_sync_status).
+ */
+#ifndef DFMNMF_H
+#define DFMNMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DFM_MAX_SUBARRAYS 64   /* L <= 64 */
+#define DFM_MAX_MICS 64        /* M = sum_l M_l <= 64 */
+#define DFM_MAX_SUBARRAY_MICS 16 /* M_l <= 16 */
+#define DFM_MAX_SOURCES 16     /* N <= 16 */
+#define DFM_MAX_BASES 64       /* K <= 64 */
+
+typedef enum {
+  DFM_C64 = 0,   /* complex64 observations and Q; float32 g, W, H */
+  DFM_C128 = 1   /* complex128 observations and Q; float64 g, W, H */
+} dfm_dtype;
+
+typedef enum {
+  DFM_OK = 0,
+  DFM_E_ARG = 1,        /* null pointer, bad enum, n_iter < 0, eps <= 0 */
+  DFM_E_SHAPE = 2,      /* F, T, N, K, L or a subarray size out of range */
+  DFM_E_WORKSPACE = 3,  /* workspace smaller than dfm_workspace_size() */
+  DFM_E_HIP = 4,        /* a HIP runtime call or kernel launch failed */
+  DFM_E_NONFINITE = 5,  /* a parameter became NaN or Inf on the device */
+  DFM_E_SINGULAR = 6    /* an IP system (Q_fl V_flmu) had a zero pivot */
+} dfm_status;
+
+/* Sub-steps of one iteration, for dfm_substep (in this order). */
+typedef enum {
+  DFM_STAGE_IP = 0,  /* V by eq. (14) from the current W,H,g; IP sweep, eqs. (15)-(16) */
+  DFM_STAGE_W = 1,   /* P = |Q x|^2 for the current Q; bases update, eq. (8) */
+  DFM_STAGE_H = 2,   /* activations update, eq. (9) (uses P from DFM_STAGE_W) */
+  DFM_STAGE_G = 3    /* diagonal SCM update, eq. (10) (uses P from DFM_STAGE_W) */
+} dfm_stage;
+
+typedef struct {
+  int32_t F;                        /* frequency bins, >= 1 */
+  int32_t T;                        /* frames, >= 1 */
+  int32_t N;                        /* sources, 1..DFM_MAX_SOURCES */
+  int32_t K;                        /* NMF bases per source, 1..DFM_MAX_BASES */
+  int32_t L;                        /* subarrays, 1..DFM_MAX_SUBARRAYS */
+  int32_t mics[DFM_MAX_SUBARRAYS];  /* M_l in 1..DFM_MAX_SUBARRAY_MICS; subarray l
+                                       owns X columns o_l .. o_l+M_l-1, o_l = sum_{l'<l} M_l' */
+  int32_t dtype;                    /* dfm_dtype */
+  double eps;                       /* floor on the model variance, the MM denominators
+                                       and the IP normaliser (1e-6 in Sec. IV-A); > 0 */
+  uint32_t flags;                   /* reserved, must be 0 */
+} dfm_problem;
+
+typedef struct dfm_plan dfm_plan;   /* opaque host-side handle */
+
+/* Bytes of device workspace a plan for *p needs (host-only call).
+ * Returns DFM_E_ARG / DFM_E_SHAPE for an invalid problem. */
+dfm_status dfm_workspace_size(const dfm_problem* p, size_t* bytes);
+
+/* Create a plan bound to caller-owned device buffers (all borrowed for the
+ * plan's lifetime, none copied):
+ *   X [F][T][M] complex, interleaved (re, im); read-only.  The STFT x_ft of
+ *     Sec. II-A with the mics of one subarray contiguous (Sec. III-B).
+ *   Q [F][sum_l M_l^2] complex; block l is M_l x M_l row-major at offset
+ *     sum_{l'<l} M_l'^2; row mu is w_mu^H.  Must be nonsingular (Sec. IV-A).
+ *   g [F][N][M] real > 0;  W [N][F][K] real > 0;  H [N][K][T] real > 0.
+ *   Q, g, W, H are the state: read and updated in place by dfm_step.
+ *   workspace: >= dfm_workspace_size() bytes, 256-byte aligned.
+ * Launches a small initialisation kernel on `stream`.
+ * On success *out receives the plan; release it with dfm_destroy. */
+dfm_status dfm_init(dfm_plan** out, const dfm_problem* p,
+                    const void* X, void* Q, void* g, void* W, void* H,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Run n_iter >= 0 full iterations (IP sweep, then eqs. (8), (9), (10)),
+ * updating Q, g, W, H in place.  Asynchronous. */
+dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream);
+
+/* Run one sub-step of an iteration (dfm_stage).  Asynchronous.  A full
+ * iteration is exactly IP, W, H, G in this order; H and G read the powers
+ * computed by the latest W sub-step. */
+dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream);
+
+/* Cost (13) of the current state: sum_{f,t,m} (|Q x|^2 / y + ln y)
+ * - 2T sum_{f,l} ln|det Q_fl|, terms in the plan's precision and the sum
+ * in FP64.  Synchronises `stream`; *out is a host pointer.  Also returns
+ * any sticky device error. */
+dfm_status dfm_nll(dfm_plan* plan, double* out, void* stream);
+
+/* Source images at every subarray by the multichannel Wiener filter
+ * (Sec. III-B, last paragraph): for each subarray l,
+ *   S_n^(l)[f][t] = Q_fl^{-1} diag(lambda_ftn g_fn / y_ft) Q_fl x_ft^(l)
+ * with lambda = W_n H_n (eq. (2)) and y = max(sum_n lambda g, eps).
+ * S [N][F][T][M] complex, caller-owned, written entirely.  Asynchronous. */
+dfm_status dfm_separate(dfm_plan* plan, void* S, void* stream);
+
+/* Weighted covariances of eq. (14) for the current W, H, g, written as
+ * V [F][sum_l M_l^3] complex: block l at offset sum_{l'<l} M_l'^3, laid out
+ * [mu][a][b] = V_flmu[a][b] (full Hermitian matrices).  Diagnostic; does
+ * not change the state.  Asynchronous. */
+dfm_status dfm_covariances(dfm_plan* plan, void* V, void* stream);
+
+/* Wait for `stream` and return the sticky device status (DFM_OK,
+ * DFM_E_SINGULAR or DFM_E_NONFINITE); clears it. */
+dfm_status dfm_sync_status(dfm_plan* plan, void* stream);
+
+/* Free the host-side plan.  Does not touch the caller's device buffers. */
+void dfm_destroy(dfm_plan* plan);
+
+/* Static English description of a status code. */
+const char* dfm_status_string(dfm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFMNMF_H */

@@ -1,0 +1,221 @@
+"""ctypes binding of the C ABI in ``include/dfmnmf.h``.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libdfmnmf.so``.  PyTorch provides device memory (the state tensors and
+the workspace) and the current HIP stream.  There is no CPU fallback: if the
+library is missing or no GPU is present, constructing a plan raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdfmnmf.so")
+
+MAX_SUBARRAYS = 64
+DFM_C64, DFM_C128 = 0, 1
+STAGES = {"ip": 0, "W": 1, "H": 2, "g": 3}
+STATUS = {0: "DFM_OK", 1: "DFM_E_ARG", 2: "DFM_E_SHAPE", 3: "DFM_E_WORKSPACE", 4: "DFM_E_HIP",
+          5: "DFM_E_NONFINITE", 6: "DFM_E_SINGULAR"}
+
+
+class DFMError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = int(status)
+        msg = STATUS.get(self.status, f"status {status}")
+        if _lib is not None:
+            msg += ": " + _lib.dfm_status_string(self.status).decode()
+        super().__init__(f"{where}: {msg}" if where else msg)
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_int32), ("T", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("mics", ctypes.c_int32 * MAX_SUBARRAYS), ("dtype", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+EXPORTS = ("dfm_workspace_size", "dfm_init", "dfm_step", "dfm_substep", "dfm_nll", "dfm_separate",
+           "dfm_covariances", "dfm_sync_status", "dfm_destroy", "dfm_status_string")
+
+
+def load(path: str = LIB_PATH):
+    """Load libdfmnmf.so and declare its signatures.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise DFMError(4, f"{path} is missing; build it with `python -m paper_2605_19388_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+    P = ctypes.POINTER(Problem)
+    lib.dfm_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.dfm_init.argtypes = [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.dfm_step.argtypes = [vp, i32, vp]
+    lib.dfm_substep.argtypes = [vp, i32, vp]
+    lib.dfm_nll.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.dfm_separate.argtypes = [vp, vp, vp]
+    lib.dfm_covariances.argtypes = [vp, vp, vp]
+    lib.dfm_sync_status.argtypes = [vp, vp]
+    lib.dfm_destroy.argtypes = [vp]
+    lib.dfm_destroy.restype = None
+    lib.dfm_status_string.argtypes = [st]
+    lib.dfm_status_string.restype = ctypes.c_char_p
+    for name in EXPORTS[:-2]:
+        getattr(lib, name).restype = st
+    _lib = lib
+    return lib
+
+
+def lib():
+    return load()
+
+
+def make_problem(F, T, mics, N, K, dtype=DFM_C64, eps=1e-6, flags=0) -> Problem:
+    p = Problem()
+    p.F, p.T, p.N, p.K, p.L = int(F), int(T), int(N), int(K), len(mics)
+    if len(mics) > MAX_SUBARRAYS:
+        raise DFMError(2, "too many subarrays")
+    for i, m in enumerate(mics):
+        p.mics[i] = int(m)
+    p.dtype = int(dtype)
+    p.eps = float(eps)
+    p.flags = int(flags)
+    return p
+
+
+def workspace_size(problem: Problem) -> int:
+    n = ctypes.c_size_t(0)
+    st = load().dfm_workspace_size(ctypes.byref(problem), ctypes.byref(n))
+    if st:
+        raise DFMError(st, "dfm_workspace_size")
+    return int(n.value)
+
+
+def _check(st, where):
+    if st:
+        raise DFMError(st, where)
+
+
+class DistributedFastMNMF:
+    """Distributed FastMNMF plan on one GPU.
+
+    X: [F, T, M] complex (numpy array or torch tensor); complex64 runs the FP32
+    path, complex128 the FP64 path.  mics: subarray sizes (contiguous columns of X).
+    W [N, F, K] and H [N, K, T] are required (the library draws no random numbers);
+    Q defaults to the block identity and g to ones.  All state lives in device
+    tensors owned by this object and is updated in place by ``step``.
+    """
+
+    def __init__(self, X, mics, n_src, n_basis, W, H, Q=None, g=None, eps=1e-6, device="cuda"):
+        import torch
+
+        self._torch = torch
+        lib_ = load()
+        if not torch.cuda.is_available():
+            raise DFMError(4, "no GPU visible to HIP")
+        dev = torch.device(device)
+        Xt = torch.as_tensor(X)
+        if Xt.dtype not in (torch.complex64, torch.complex128):
+            raise DFMError(1, "X must be complex64 or complex128")
+        self.dtype = DFM_C64 if Xt.dtype == torch.complex64 else DFM_C128
+        cdt = Xt.dtype
+        rdt = torch.float32 if self.dtype == DFM_C64 else torch.float64
+        F, T, M = Xt.shape
+        self.mics = tuple(int(m) for m in mics)
+        if sum(self.mics) != M:
+            raise DFMError(2, "sum(mics) != X.shape[2]")
+        self.F, self.T, self.M, self.N, self.K = int(F), int(T), int(M), int(n_src), int(n_basis)
+        self.X = Xt.to(dev).contiguous()
+        qf = sum(m * m for m in self.mics)
+        if Q is None:
+            Q = np.zeros((F, qf), dtype=np.complex128)
+            o = 0
+            for m in self.mics:
+                Q[:, o:o + m * m] = np.eye(m).ravel()
+                o += m * m
+        if g is None:
+            g = np.ones((F, self.N, M))
+        self.Q = torch.as_tensor(Q).to(device=dev, dtype=cdt).contiguous().clone()
+        self.g = torch.as_tensor(g).to(device=dev, dtype=rdt).contiguous().clone()
+        self.W = torch.as_tensor(W).to(device=dev, dtype=rdt).contiguous().clone()
+        self.H = torch.as_tensor(H).to(device=dev, dtype=rdt).contiguous().clone()
+        for name, t, shp in (("Q", self.Q, (F, qf)), ("g", self.g, (F, self.N, M)),
+                             ("W", self.W, (self.N, F, self.K)), ("H", self.H, (self.N, self.K, T))):
+            if tuple(t.shape) != shp:
+                raise DFMError(2, f"{name} has shape {tuple(t.shape)}, expected {shp}")
+        self.problem = make_problem(F, T, self.mics, self.N, self.K, self.dtype, eps)
+        nbytes = workspace_size(self.problem)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self._ws.data_ptr()) % 256
+        self._ws_ptr = self._ws.data_ptr() + off
+        self._ws_bytes = nbytes
+        self.device = dev
+        self._plan = ctypes.c_void_p()
+        st = lib_.dfm_init(ctypes.byref(self._plan), ctypes.byref(self.problem),
+                           self.X.data_ptr(), self.Q.data_ptr(), self.g.data_ptr(), self.W.data_ptr(),
+                           self.H.data_ptr(), self._ws_ptr, self._ws_bytes, self._stream())
+        _check(st, "dfm_init")
+
+    def _stream(self):
+        return self._torch.cuda.current_stream(self.device).cuda_stream
+
+    def step(self, n_iter: int = 1):
+        _check(load().dfm_step(self._plan, int(n_iter), self._stream()), "dfm_step")
+        return self
+
+    def substep(self, stage):
+        stage = STAGES[stage] if isinstance(stage, str) else int(stage)
+        _check(load().dfm_substep(self._plan, stage, self._stream()), "dfm_substep")
+        return self
+
+    def nll(self) -> float:
+        out = ctypes.c_double(0.0)
+        _check(load().dfm_nll(self._plan, ctypes.byref(out), self._stream()), "dfm_nll")
+        return float(out.value)
+
+    def separate(self, out=None):
+        torch = self._torch
+        if out is None:
+            out = torch.empty((self.N, self.F, self.T, self.M), dtype=self.X.dtype, device=self.device)
+        _check(load().dfm_separate(self._plan, out.data_ptr(), self._stream()), "dfm_separate")
+        return out
+
+    def covariances(self):
+        torch = self._torch
+        vc = sum(m ** 3 for m in self.mics)
+        out = torch.empty((self.F, vc), dtype=self.X.dtype, device=self.device)
+        _check(load().dfm_covariances(self._plan, out.data_ptr(), self._stream()), "dfm_covariances")
+        return out
+
+    def sync_status(self):
+        _check(load().dfm_sync_status(self._plan, self._stream()), "dfm_sync_status")
+
+    def load_state(self, Q=None, g=None, W=None, H=None):
+        """Copy new values into the state tensors in place (the plan keeps their addresses)."""
+        torch = self._torch
+        for name, v in (("Q", Q), ("g", g), ("W", W), ("H", H)):
+            if v is not None:
+                t = getattr(self, name)
+                t.copy_(torch.as_tensor(v).to(device=self.device, dtype=t.dtype).reshape(t.shape))
+        return self
+
+    def state(self):
+        """Host copies (numpy) of Q, g, W, H."""
+        self._torch.cuda.synchronize(self.device)
+        return {k: getattr(self, k).cpu().numpy() for k in ("Q", "g", "W", "H")}
+
+    def close(self):
+        if getattr(self, "_plan", None) and self._plan.value:
+            load().dfm_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,237 @@
+// C ABI of distributed FastMNMF: validation, workspace layout, launch sequencing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dfm_internal.h"
+#include "dfmnmf.h"
+
+using dfm::Buffers;
+using dfm::Dims;
+
+struct dfm_plan {
+  Dims d;
+  Buffers b;
+  int dtype;
+};
+
+namespace dfm {
+
+static size_t real_size(int dtype) { return dtype == DFM_C64 ? 4 : 8; }
+static size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// Frames per streaming slice: as many as fit the LDS budget of every tile kernel, at most 128.
+static void choose_tiles(Dims& d, int dtype) {
+  const size_t r = real_size(dtype), c = 2 * r;
+  const size_t budget = 48 * 1024;
+  int sl = 128;
+  for (; sl > 8; sl /= 2) {
+    const size_t gram = r * (d.N * d.K + d.N * d.M + sl * d.M) + 16 + c * sl * d.M;
+    const size_t pw = c * d.QF + 16 + r * (d.N * d.K + d.N * d.M + sl * d.N * 2);
+    const size_t gg = r * (d.N * d.K + d.N * d.M + sl * d.N + sl * d.M * 2);
+    if (gram <= budget && pw <= budget && gg <= budget) break;
+  }
+  d.S = (d.T + sl - 1) / sl;
+  d.SL = (d.T + d.S - 1) / d.S;
+  d.TB = 16;
+  d.FB = 16;
+  while (d.FB > 1 && r * d.FB * d.TB * d.N * 2 > budget) d.FB /= 2;
+  d.FS = (d.F + d.FB - 1) / d.FB;
+  d.TBN = (d.T + d.TB - 1) / d.TB;
+}
+
+static dfm_status make_dims(const dfm_problem* p, Dims& d) {
+  if (!p) return DFM_E_ARG;
+  if (p->dtype != DFM_C64 && p->dtype != DFM_C128) return DFM_E_ARG;
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps) || p->flags != 0) return DFM_E_ARG;
+  if (p->F < 1 || p->T < 1 || p->N < 1 || p->N > kMaxN || p->K < 1 || p->K > kMaxK || p->L < 1 || p->L > kMaxL)
+    return DFM_E_SHAPE;
+  std::memset(&d, 0, sizeof(d));
+  d.F = p->F;
+  d.T = p->T;
+  d.N = p->N;
+  d.K = p->K;
+  d.L = p->L;
+  d.eps = p->eps;
+  int m = 0, q = 0, v = 0;
+  for (int l = 0; l < p->L; ++l) {
+    const int ml = p->mics[l];
+    if (ml < 1 || ml > kMaxMl || m + ml > kMaxM) return DFM_E_SHAPE;
+    d.mics[l] = ml;
+    d.moff[l] = m;
+    d.qoff[l] = q;
+    d.voff[l] = v;
+    for (int i = 0; i < ml; ++i) d.msub[m + i] = l;
+    m += ml;
+    q += ml * ml;
+    v += ml * ml * ml;
+  }
+  d.M = m;
+  d.QF = q;
+  d.VF = v;
+  d.VC = v;
+  // 32-bit indexing inside kernels: keep every per-buffer element count below 2^31.
+  const double big = (double)d.F * d.T * d.M * 2 * (p->N > 1 ? p->N : 1);
+  if (big >= 2147483647.0) return DFM_E_SHAPE;
+  choose_tiles(d, p->dtype);
+  return DFM_OK;
+}
+
+size_t workspace_bytes(const Dims& d, int dtype) {
+  const size_t r = real_size(dtype);
+  size_t n = 0;
+  n += al(r * d.F * d.T * d.M);                        // P
+  n += al(r * d.F * d.S * d.VF);                       // Vpart
+  n += al(r * d.F * d.S * d.N * d.K * 2);              // Wpart
+  n += al(r * (size_t)d.FS * d.N * d.K * d.T * 2);     // Hpart
+  n += al(r * d.F * d.S * d.N * d.M * 2);              // gpart
+  n += al(8 * d.F * d.L);                              // logdet
+  n += al(8 * d.F * d.S);                              // nllpart
+  n += al(16 * d.F * d.QF);                            // Qinv
+  n += al(64);                                         // status
+  return n;
+}
+
+void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
+  const size_t r = real_size(dtype);
+  char* p = ws;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += al(bytes);
+    return q;
+  };
+  b.P = take(r * d.F * d.T * d.M);
+  b.Vpart = take(r * d.F * d.S * d.VF);
+  b.Wpart = take(r * d.F * d.S * d.N * d.K * 2);
+  b.Hpart = take(r * (size_t)d.FS * d.N * d.K * d.T * 2);
+  b.gpart = take(r * d.F * d.S * d.N * d.M * 2);
+  b.logdet = reinterpret_cast<double*>(take(8 * d.F * d.L));
+  b.nllpart = reinterpret_cast<double*>(take(8 * d.F * d.S));
+  b.Qinv = take(16 * d.F * d.QF);
+  b.status = reinterpret_cast<int*>(take(64));
+}
+
+static dfm_status read_status(dfm_plan* plan, hipStream_t s, bool clear) {
+  int st = 0;
+  if (hipMemcpyAsync(&st, plan->b.status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return DFM_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return DFM_E_HIP;
+  if (clear && st != 0 && launch_init(plan->d, plan->b, s) != hipSuccess) return DFM_E_HIP;
+  if (st & kStSingular) return DFM_E_SINGULAR;
+  if (st & kStNonFinite) return DFM_E_NONFINITE;
+  return DFM_OK;
+}
+
+}  // namespace dfm
+
+extern "C" {
+
+dfm_status dfm_workspace_size(const dfm_problem* p, size_t* bytes) {
+  if (!bytes) return DFM_E_ARG;
+  Dims d;
+  const dfm_status st = dfm::make_dims(p, d);
+  if (st != DFM_OK) return st;
+  *bytes = dfm::workspace_bytes(d, p->dtype);
+  return DFM_OK;
+}
+
+dfm_status dfm_init(dfm_plan** out, const dfm_problem* p, const void* X, void* Q, void* g, void* W, void* H,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  if (!out) return DFM_E_ARG;
+  *out = nullptr;
+  Dims d;
+  const dfm_status st = dfm::make_dims(p, d);
+  if (st != DFM_OK) return st;
+  if (!X || !Q || !g || !W || !H || !workspace) return DFM_E_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return DFM_E_WORKSPACE;
+  if (workspace_bytes < dfm::workspace_bytes(d, p->dtype)) return DFM_E_WORKSPACE;
+  dfm_plan* plan = new (std::nothrow) dfm_plan;
+  if (!plan) return DFM_E_ARG;
+  plan->d = d;
+  plan->dtype = p->dtype;
+  std::memset(&plan->b, 0, sizeof(plan->b));
+  plan->b.X = X;
+  plan->b.Q = Q;
+  plan->b.g = g;
+  plan->b.W = W;
+  plan->b.H = H;
+  dfm::carve(d, p->dtype, static_cast<char*>(workspace), plan->b);
+  if (dfm::launch_init(d, plan->b, static_cast<hipStream_t>(stream)) != hipSuccess) {
+    delete plan;
+    return DFM_E_HIP;
+  }
+  *out = plan;
+  return DFM_OK;
+}
+
+dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream) {
+  if (!plan || n_iter < 0) return DFM_E_ARG;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int it = 0; it < n_iter; ++it)
+    for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G; ++stage)
+      if (dfm::launch_stage(plan->d, plan->b, plan->dtype, stage, s) != hipSuccess) return DFM_E_HIP;
+  return DFM_OK;
+}
+
+dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream) {
+  if (!plan || stage < DFM_STAGE_IP || stage > DFM_STAGE_G) return DFM_E_ARG;
+  if (dfm::launch_stage(plan->d, plan->b, plan->dtype, stage, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return DFM_E_HIP;
+  return DFM_OK;
+}
+
+dfm_status dfm_nll(dfm_plan* plan, double* out, void* stream) {
+  if (!plan || !out) return DFM_E_ARG;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const Dims& d = plan->d;
+  if (dfm::launch_nll(d, plan->b, plan->dtype, s) != hipSuccess) return DFM_E_HIP;
+  std::vector<double> part((size_t)d.F * d.S), ld((size_t)d.F * d.L);
+  if (hipMemcpyAsync(part.data(), plan->b.nllpart, part.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(ld.data(), plan->b.logdet, ld.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return DFM_E_HIP;
+  const dfm_status st = dfm::read_status(plan, s, false);
+  if (st == DFM_E_HIP) return st;
+  double data = 0.0, logdet = 0.0;
+  for (double v : part) data += v;
+  for (double v : ld) logdet += v;
+  *out = data - 2.0 * d.T * logdet;
+  return st;
+}
+
+dfm_status dfm_separate(dfm_plan* plan, void* S, void* stream) {
+  if (!plan || !S) return DFM_E_ARG;
+  if (dfm::launch_separate(plan->d, plan->b, plan->dtype, S, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return DFM_E_HIP;
+  return DFM_OK;
+}
+
+dfm_status dfm_covariances(dfm_plan* plan, void* V, void* stream) {
+  if (!plan || !V) return DFM_E_ARG;
+  if (dfm::launch_covariances(plan->d, plan->b, plan->dtype, V, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return DFM_E_HIP;
+  return DFM_OK;
+}
+
+dfm_status dfm_sync_status(dfm_plan* plan, void* stream) {
+  if (!plan) return DFM_E_ARG;
+  return dfm::read_status(plan, static_cast<hipStream_t>(stream), true);
+}
+
+void dfm_destroy(dfm_plan* plan) { delete plan; }
+
+const char* dfm_status_string(dfm_status s) {
+  switch (s) {
+    case DFM_OK: return "ok";
+    case DFM_E_ARG: return "invalid argument";
+    case DFM_E_SHAPE: return "shape or partition out of range";
+    case DFM_E_WORKSPACE: return "workspace too small or misaligned";
+    case DFM_E_HIP: return "HIP runtime error";
+    case DFM_E_NONFINITE: return "a parameter became non-finite";
+    case DFM_E_SINGULAR: return "singular iterative-projection system";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

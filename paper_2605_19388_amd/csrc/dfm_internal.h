@@ -1,0 +1,67 @@
+// Internal interface between the C ABI (dfm_api.cpp) and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "dfmnmf.h"
+
+namespace dfm {
+
+constexpr int kMaxL = DFM_MAX_SUBARRAYS;
+constexpr int kMaxM = DFM_MAX_MICS;
+constexpr int kMaxMl = DFM_MAX_SUBARRAY_MICS;
+constexpr int kMaxN = DFM_MAX_SOURCES;
+constexpr int kMaxK = DFM_MAX_BASES;
+constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
+
+// Sticky device status bits (workspace word).
+constexpr int kStSingular = 1;
+constexpr int kStNonFinite = 2;
+
+// Problem geometry, passed by value to every kernel.
+struct Dims {
+  int F, T, N, K, L, M;
+  int QF;  // complex entries of Q per frequency: sum_l M_l^2
+  int VF;  // reals of the packed covariances per frequency: sum_l M_l^3
+  int VC;  // complex entries of the full covariances per frequency: sum_l M_l^3
+  int S, SL;    // time slices per frequency and frames per slice (streaming tiles)
+  int FB, FS;   // frequencies per tile and number of frequency tiles (activation update)
+  int TB, TBN;  // frames per tile and number of frame tiles (activation update)
+  double eps;
+  int mics[kMaxL];  // M_l
+  int moff[kMaxL];  // first mic of subarray l
+  int qoff[kMaxL];  // offset of block l in a frequency's packed Q (complex units)
+  int voff[kMaxL];  // offset of block l in a frequency's covariances (sum_{l'<l} M_l'^3)
+  int msub[kMaxM];  // subarray of each mic
+};
+
+// Device buffers of one plan (all carved from the caller's workspace except the state).
+struct Buffers {
+  const void* X;
+  void* Q;
+  void* g;
+  void* W;
+  void* H;
+  void* P;       // [F][T][M] real: |Q x|^2 of the latest W sub-step
+  void* Vpart;   // [F][S][VF] real: per-slice packed covariance sums
+  void* Wpart;   // [F][S][N][K][2] real
+  void* Hpart;   // [FS][N][K][T][2] real
+  void* gpart;   // [F][S][N][M][2] real
+  double* logdet;   // [F][L]
+  double* nllpart;  // [F][S]
+  void* Qinv;       // [F][QF] complex double
+  int* status;      // sticky status word
+};
+
+size_t workspace_bytes(const Dims& d, int dtype);
+void carve(const Dims& d, int dtype, char* ws, Buffers& b);
+
+// Launchers (return hipSuccess or the first launch error).
+hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s);
+hipError_t launch_stage(const Dims& d, const Buffers& b, int dtype, int stage, hipStream_t s);
+hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s);
+hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
+hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);
+
+}  // namespace dfm

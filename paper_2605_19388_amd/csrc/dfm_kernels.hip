@@ -1,0 +1,804 @@
+// HIP kernels of distributed FastMNMF for gfx950.
+//
+// Data layout in HBM (all row-major, caller-owned unless noted):
+//   X [F][T][M] complex, Q [F][sum M_l^2] complex, g [F][N][M], W [N][F][K], H [N][K][T]
+//   P [F][T][M] real (workspace): powers |(Q_fl x_ft^(l))_mu|^2 of the latest W sub-step.
+//
+// Streaming kernels work on tiles (f, time slice) of d.SL frames with 256 threads:
+// phase 1 puts one frame per thread and writes per-frame quantities to LDS; phase 2
+// puts one output per thread and contracts over the slice's frames from LDS, so no
+// cross-lane reductions are needed.  Per-frequency sums over slices (and the
+// activation update's sum over frequency tiles) are finished by small "apply"
+// kernels in a fixed order, so every result is deterministic run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dfm_internal.h"
+
+namespace dfm {
+
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+struct cd {
+  double re, im;
+};
+
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd cconj(cd a) { return {a.re, -a.im}; }
+__device__ __forceinline__ double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ cd cinv(cd a) {
+  const double s = 1.0 / cabs2(a);
+  return {a.re * s, -a.im * s};
+}
+
+template <typename R>
+__device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------------------------------
+// Packed Hermitian index j in [0, M_l^2): j < M_l is the diagonal entry (j, j) (real);
+// otherwise pair p = (j - M_l) / 2 of the strict upper triangle in row-major order,
+// part (j - M_l) % 2 = 0 for the real and 1 for the imaginary part of V[a][b], a < b.
+__device__ __forceinline__ void packed_pair(int Ml, int j, int& a, int& b, int& part) {
+  if (j < Ml) {
+    a = j;
+    b = j;
+    part = 0;
+    return;
+  }
+  int p = (j - Ml) >> 1;
+  part = (j - Ml) & 1;
+  int row = 0, cnt = Ml - 1;
+  while (p >= cnt) {
+    p -= cnt;
+    ++row;
+    --cnt;
+  }
+  a = row;
+  b = row + 1 + p;
+}
+
+__device__ __forceinline__ int subarray_of_vidx(const Dims& d, int idx) {
+  int l = 0;
+  while (l + 1 < d.L && idx >= d.voff[l + 1]) ++l;
+  return l;
+}
+
+// lambda_n = sum_k W[n][f][k] H[n][k][t] for every source (eq. (2)).
+// w points at W[0][f][0] and wsn is the stride between sources.
+template <typename R>
+__device__ __forceinline__ void source_psd(const Dims& d, const R* w, int wsn, const R* __restrict__ H, int t,
+                                           R (&lam)[kMaxN]) {
+#pragma unroll
+  for (int n = 0; n < kMaxN; ++n) {
+    R acc = 0;
+    if (n < d.N) {
+      const R* hn = H + (size_t)n * d.K * d.T + t;
+      const R* wn = w + (size_t)n * wsn;
+      for (int k = 0; k < d.K; ++k) acc += wn[k] * hn[(size_t)k * d.T];
+    }
+    lam[n] = acc;
+  }
+}
+
+// y_m = max(sum_n lambda_n g[n][m], eps) with gf = g[f][0][0].
+template <typename R>
+__device__ __forceinline__ R model_var(const Dims& d, const R (&lam)[kMaxN], const R* gf, int m) {
+  R acc = 0;
+#pragma unroll
+  for (int n = 0; n < kMaxN; ++n)
+    if (n < d.N) acc += lam[n] * gf[n * d.M + m];
+  return rmax(acc, (R)d.eps);
+}
+
+__host__ __device__ __forceinline__ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------------------
+// Weighted covariances, eq. (14): per tile (f, slice) the packed sums
+//   sum_t x_ta conj(x_tb) / y_{t, o_l + mu}   for every (l, mu, a <= b).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_gram(Dims d, const cx<R>* __restrict__ X, const R* __restrict__ W,
+                                                 const R* __restrict__ H, const R* __restrict__ g,
+                                                 R* __restrict__ Vpart) {
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int t0 = s * d.SL;
+  const int nt = min(d.SL, d.T - t0);
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* sW = reinterpret_cast<R*>(smem);
+  R* sg = sW + d.N * d.K;
+  R* sinv = sg + d.N * d.M;
+  cx<R>* sx = reinterpret_cast<cx<R>*>(smem + align_up(sizeof(R) * (d.N * d.K + d.N * d.M + d.SL * d.M), 16));
+
+  for (int i = tid; i < d.N * d.K; i += kBlock) {
+    const int n = i / d.K, k = i - n * d.K;
+    sW[i] = W[((size_t)n * d.F + f) * d.K + k];
+  }
+  for (int i = tid; i < d.N * d.M; i += kBlock) sg[i] = g[(size_t)f * d.N * d.M + i];
+  const cx<R>* xf = X + ((size_t)f * d.T + t0) * d.M;
+  for (int i = tid; i < nt * d.M; i += kBlock) sx[i] = xf[i];
+  __syncthreads();
+
+  for (int tl = tid; tl < nt; tl += kBlock) {
+    R lam[kMaxN];
+    source_psd(d, sW, d.K, H, t0 + tl, lam);
+    for (int m = 0; m < d.M; ++m) sinv[tl * d.M + m] = (R)1 / model_var(d, lam, sg, m);
+  }
+  __syncthreads();
+
+  R* out = Vpart + ((size_t)f * d.S + s) * d.VF;
+  for (int idx = tid; idx < d.VF; idx += kBlock) {
+    const int l = subarray_of_vidx(d, idx);
+    const int Ml = d.mics[l];
+    const int r = idx - d.voff[l];
+    const int mu = r / (Ml * Ml);
+    int a, b, part;
+    packed_pair(Ml, r - mu * Ml * Ml, a, b, part);
+    const int o = d.moff[l];
+    R acc = 0;
+    for (int tl = 0; tl < nt; ++tl) {
+      const R w = sinv[tl * d.M + o + mu];
+      const cx<R> xa = sx[tl * d.M + o + a];
+      const cx<R> xb = sx[tl * d.M + o + b];
+      const R v = part == 0 ? xa.re * xb.re + xa.im * xb.im : xa.im * xb.re - xa.re * xb.im;
+      acc += w * v;
+    }
+    out[idx] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// In-LDS Gaussian elimination with partial pivoting of the n x ncols row-major
+// matrix A (leading dimension ld), all threads cooperating.  Thread 0 searches the
+// pivot and swaps rows; the others update the trailing rows.  Returns, in thread 0,
+// sum_p ln|A_pp| of the eliminated matrix and whether a zero pivot appeared.
+__device__ void eliminate(cd* A, int ld, int n, int ncols, double* s_logabs, int* s_sing) {
+  const int tid = threadIdx.x, bd = blockDim.x;
+  if (tid == 0) {
+    *s_logabs = 0.0;
+    *s_sing = 0;
+  }
+  for (int p = 0; p < n; ++p) {
+    if (tid == 0) {
+      int piv = p;
+      double best = cabs2(A[p * ld + p]);
+      for (int r = p + 1; r < n; ++r) {
+        const double v = cabs2(A[r * ld + p]);
+        if (v > best) {
+          best = v;
+          piv = r;
+        }
+      }
+      if (piv != p)
+        for (int c = p; c < ncols; ++c) {
+          const cd tmp = A[p * ld + c];
+          A[p * ld + c] = A[piv * ld + c];
+          A[piv * ld + c] = tmp;
+        }
+      if (best == 0.0)
+        *s_sing = 1;
+      else
+        *s_logabs += 0.5 * log(best);
+    }
+    __syncthreads();
+    const cd pv = A[p * ld + p];
+    if (cabs2(pv) != 0.0) {
+      const cd inv = cinv(pv);
+      const int w = ncols - p - 1;
+      for (int i = tid; i < (n - p - 1) * w; i += bd) {
+        const int r = p + 1 + i / w, c = p + 1 + i % w;
+        const cd fac = cmul(A[r * ld + p], inv);
+        A[r * ld + c] = csub(A[r * ld + c], cmul(fac, A[p * ld + c]));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// IP sweep over the rows of one subarray block Q_fl, eqs. (15)-(16), in FP64.
+// Block (f, l).  For mu = 0..M_l-1: V_mu from the slice sums, A = Q V_mu,
+// solve A b = e_mu, b <- b / sqrt(max(Re b^H V_mu b, eps)), row mu of Q <- b^H.
+// Finally ln|det Q_fl| (used by the cost (13)).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_ip(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict__ Q,
+                                               double* __restrict__ logdet, int* __restrict__ status) {
+  const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, bd = blockDim.x;
+  const int Ml = d.mics[l];
+  const int ld = Ml + 1;
+  __shared__ cd sQ[kMaxMl * kMaxMl];
+  __shared__ cd sV[kMaxMl * kMaxMl];
+  __shared__ cd sA[kMaxMl * (kMaxMl + 1)];
+  __shared__ cd sb[kMaxMl];
+  __shared__ double s_logabs;
+  __shared__ int s_sing;
+
+  cx<R>* qb = Q + (size_t)f * d.QF + d.qoff[l];
+  for (int i = tid; i < Ml * Ml; i += bd) sQ[i] = {(double)qb[i].re, (double)qb[i].im};
+  const double invT = 1.0 / d.T;
+
+  for (int mu = 0; mu < Ml; ++mu) {
+    const R* vp = Vpart + (size_t)f * d.S * d.VF + d.voff[l] + mu * Ml * Ml;
+    for (int j = tid; j < Ml * Ml; j += bd) {
+      double acc = 0.0;
+      for (int s = 0; s < d.S; ++s) acc += (double)vp[(size_t)s * d.VF + j];
+      acc *= invT;
+      int a, b, part;
+      packed_pair(Ml, j, a, b, part);
+      if (a == b) {
+        sV[a * Ml + a] = {acc, 0.0};
+      } else if (part == 0) {
+        sV[a * Ml + b].re = acc;
+        sV[b * Ml + a].re = acc;
+      } else {
+        sV[a * Ml + b].im = acc;
+        sV[b * Ml + a].im = -acc;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < Ml * Ml; i += bd) {
+      const int r = i / Ml, c = i - r * Ml;
+      cd acc = {0.0, 0.0};
+      for (int j = 0; j < Ml; ++j) acc = cadd(acc, cmul(sQ[r * Ml + j], sV[j * Ml + c]));
+      sA[r * ld + c] = acc;
+    }
+    for (int r = tid; r < Ml; r += bd) sA[r * ld + Ml] = {r == mu ? 1.0 : 0.0, 0.0};
+    __syncthreads();
+    eliminate(sA, ld, Ml, Ml + 1, &s_logabs, &s_sing);
+    if (tid == 0) {
+      if (s_sing) {
+        atomicOr(status, kStSingular);  // row kept; the host reports DFM_E_SINGULAR
+      } else {
+        for (int r = Ml - 1; r >= 0; --r) {
+          cd acc = sA[r * ld + Ml];
+          for (int c = r + 1; c < Ml; ++c) acc = csub(acc, cmul(sA[r * ld + c], sb[c]));
+          sb[r] = cmul(acc, cinv(sA[r * ld + r]));
+        }
+        double sv = 0.0;
+        for (int a = 0; a < Ml; ++a) {
+          cd vb = {0.0, 0.0};
+          for (int b = 0; b < Ml; ++b) vb = cadd(vb, cmul(sV[a * Ml + b], sb[b]));
+          sv += sb[a].re * vb.re + sb[a].im * vb.im;
+        }
+        const double sc = 1.0 / sqrt(sv > d.eps ? sv : d.eps);
+        for (int c = 0; c < Ml; ++c) sQ[mu * Ml + c] = {sb[c].re * sc, -sb[c].im * sc};
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < Ml * Ml; i += bd) {
+    qb[i].re = (R)sQ[i].re;
+    qb[i].im = (R)sQ[i].im;
+    sA[(i / Ml) * Ml + i % Ml] = {(double)qb[i].re, (double)qb[i].im};
+  }
+  __syncthreads();
+  eliminate(sA, Ml, Ml, Ml, &s_logabs, &s_sing);
+  if (tid == 0) logdet[(size_t)f * d.L + l] = s_logabs;
+}
+
+// ---------------------------------------------------------------------------------------
+// Powers P = |Q x|^2 and the slice sums of eq. (8):
+//   num_W[n][k] = sum_t H[n][k][t] sum_m g P / y^2,  den_W[n][k] = sum_t H sum_m g / y.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pw(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+                                               const R* __restrict__ W, const R* __restrict__ H,
+                                               const R* __restrict__ g, R* __restrict__ P, R* __restrict__ Wpart) {
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int t0 = s * d.SL;
+  const int nt = min(d.SL, d.T - t0);
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<R>* sQ = reinterpret_cast<cx<R>*>(smem);
+  R* sW = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * d.QF, 16));
+  R* sg = sW + d.N * d.K;
+  R* sab = sg + d.N * d.M;  // [SL][N][2]
+
+  for (int i = tid; i < d.QF; i += kBlock) sQ[i] = Q[(size_t)f * d.QF + i];
+  for (int i = tid; i < d.N * d.K; i += kBlock) {
+    const int n = i / d.K, k = i - n * d.K;
+    sW[i] = W[((size_t)n * d.F + f) * d.K + k];
+  }
+  for (int i = tid; i < d.N * d.M; i += kBlock) sg[i] = g[(size_t)f * d.N * d.M + i];
+  __syncthreads();
+
+  for (int tl = tid; tl < nt; tl += kBlock) {
+    const int t = t0 + tl;
+    R lam[kMaxN], a[kMaxN], b[kMaxN];
+    source_psd(d, sW, d.K, H, t, lam);
+#pragma unroll
+    for (int n = 0; n < kMaxN; ++n) {
+      a[n] = 0;
+      b[n] = 0;
+    }
+    const cx<R>* xr = X + ((size_t)f * d.T + t) * d.M;
+    R* pr = P + ((size_t)f * d.T + t) * d.M;
+    for (int l = 0; l < d.L; ++l) {
+      const int Ml = d.mics[l], o = d.moff[l];
+      const cx<R>* qb = sQ + d.qoff[l];
+      for (int mu = 0; mu < Ml; ++mu) {
+        R zr = 0, zi = 0;
+        for (int c = 0; c < Ml; ++c) {
+          const cx<R> q = qb[mu * Ml + c];
+          const cx<R> x = xr[o + c];
+          zr += q.re * x.re - q.im * x.im;
+          zi += q.re * x.im + q.im * x.re;
+        }
+        const R p = zr * zr + zi * zi;
+        const int m = o + mu;
+        pr[m] = p;
+        const R iy = (R)1 / model_var(d, lam, sg, m);
+        const R piy2 = p * iy * iy;
+#pragma unroll
+        for (int n = 0; n < kMaxN; ++n)
+          if (n < d.N) {
+            a[n] += sg[n * d.M + m] * piy2;
+            b[n] += sg[n * d.M + m] * iy;
+          }
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < kMaxN; ++n)
+      if (n < d.N) {
+        sab[(tl * d.N + n) * 2 + 0] = a[n];
+        sab[(tl * d.N + n) * 2 + 1] = b[n];
+      }
+  }
+  __syncthreads();
+
+  R* out = Wpart + ((size_t)f * d.S + s) * d.N * d.K * 2;
+  for (int idx = tid; idx < d.N * d.K * 2; idx += kBlock) {
+    const int which = idx & 1, nk = idx >> 1;
+    const int n = nk / d.K;
+    const R* hr = H + (size_t)nk * d.T + t0;
+    R acc = 0;
+    for (int tl = 0; tl < nt; ++tl) acc += hr[tl] * sab[(tl * d.N + n) * 2 + which];
+    out[idx] = acc;
+  }
+}
+
+// W[n][f][k] <- W sqrt(num / max(den, eps)), sums over slices in order (eq. (8)).
+template <typename R>
+__global__ void k_wapply(Dims d, R* __restrict__ W, const R* __restrict__ Wpart, int* __restrict__ status) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.N * d.F * d.K) return;
+  const int k = idx % d.K, nf = idx / d.K, f = nf % d.F, n = nf / d.F;
+  R num = 0, den = 0;
+  for (int s = 0; s < d.S; ++s) {
+    const R* pp = Wpart + (((size_t)f * d.S + s) * d.N * d.K + n * d.K + k) * 2;
+    num += pp[0];
+    den += pp[1];
+  }
+  const R v = W[idx] * sqrt(num / rmax(den, (R)d.eps));
+  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  W[idx] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Activation update sums over a tile of FB frequencies x TB frames (eq. (9)):
+//   num_H[n][k][t] = sum_f W[n][f][k] sum_m g P / y^2,  den_H = sum_f W sum_m g / y.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_h(Dims d, const R* __restrict__ W, const R* __restrict__ H,
+                                              const R* __restrict__ g, const R* __restrict__ P,
+                                              R* __restrict__ Hpart) {
+  const int fs = blockIdx.x, tb = blockIdx.y, tid = threadIdx.x;
+  const int f0 = fs * d.FB, nf = min(d.FB, d.F - f0);
+  const int t0 = tb * d.TB, ntb = min(d.TB, d.T - t0);
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* sab = reinterpret_cast<R*>(smem);  // [FB][TB][N][2]
+
+  for (int i = tid; i < nf * ntb; i += kBlock) {
+    const int fl = i / ntb, tl = i - fl * ntb;
+    const int f = f0 + fl, t = t0 + tl;
+    R lam[kMaxN], a[kMaxN], b[kMaxN];
+    source_psd(d, W + (size_t)f * d.K, d.F * d.K, H, t, lam);
+#pragma unroll
+    for (int n = 0; n < kMaxN; ++n) {
+      a[n] = 0;
+      b[n] = 0;
+    }
+    const R* gf = g + (size_t)f * d.N * d.M;
+    const R* pr = P + ((size_t)f * d.T + t) * d.M;
+    for (int m = 0; m < d.M; ++m) {
+      const R iy = (R)1 / model_var(d, lam, gf, m);
+      const R piy2 = pr[m] * iy * iy;
+#pragma unroll
+      for (int n = 0; n < kMaxN; ++n)
+        if (n < d.N) {
+          a[n] += gf[n * d.M + m] * piy2;
+          b[n] += gf[n * d.M + m] * iy;
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < kMaxN; ++n)
+      if (n < d.N) {
+        sab[((fl * d.TB + tl) * d.N + n) * 2 + 0] = a[n];
+        sab[((fl * d.TB + tl) * d.N + n) * 2 + 1] = b[n];
+      }
+  }
+  __syncthreads();
+
+  for (int idx = tid; idx < d.N * d.K * ntb * 2; idx += kBlock) {
+    const int which = idx & 1;
+    const int rest = idx >> 1;
+    const int tl = rest % ntb, nk = rest / ntb;
+    const int n = nk / d.K, k = nk - n * d.K;
+    R acc = 0;
+    for (int fl = 0; fl < nf; ++fl)
+      acc += W[((size_t)n * d.F + f0 + fl) * d.K + k] * sab[((fl * d.TB + tl) * d.N + n) * 2 + which];
+    Hpart[((((size_t)fs * d.N + n) * d.K + k) * d.T + t0 + tl) * 2 + which] = acc;
+  }
+}
+
+template <typename R>
+__global__ void k_happly(Dims d, R* __restrict__ H, const R* __restrict__ Hpart, int* __restrict__ status) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = d.N * d.K * d.T;
+  if (idx >= total) return;
+  R num = 0, den = 0;
+  for (int fs = 0; fs < d.FS; ++fs) {
+    const R* pp = Hpart + ((size_t)fs * total + idx) * 2;
+    num += pp[0];
+    den += pp[1];
+  }
+  const R v = H[idx] * sqrt(num / rmax(den, (R)d.eps));
+  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  H[idx] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Diagonal SCM update slice sums (eq. (10)):
+//   num_g[n][m] = sum_t lambda_tn P_tm / y_tm^2,  den_g[n][m] = sum_t lambda_tn / y_tm.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_g(Dims d, const R* __restrict__ W, const R* __restrict__ H,
+                                              const R* __restrict__ g, const R* __restrict__ P,
+                                              R* __restrict__ gpart) {
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int t0 = s * d.SL;
+  const int nt = min(d.SL, d.T - t0);
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* sW = reinterpret_cast<R*>(smem);
+  R* sg = sW + d.N * d.K;
+  R* slam = sg + d.N * d.M;       // [SL][N]
+  R* sr = slam + d.SL * d.N;      // [SL][M][2]
+
+  for (int i = tid; i < d.N * d.K; i += kBlock) {
+    const int n = i / d.K, k = i - n * d.K;
+    sW[i] = W[((size_t)n * d.F + f) * d.K + k];
+  }
+  for (int i = tid; i < d.N * d.M; i += kBlock) sg[i] = g[(size_t)f * d.N * d.M + i];
+  __syncthreads();
+
+  for (int tl = tid; tl < nt; tl += kBlock) {
+    const int t = t0 + tl;
+    R lam[kMaxN];
+    source_psd(d, sW, d.K, H, t, lam);
+#pragma unroll
+    for (int n = 0; n < kMaxN; ++n)
+      if (n < d.N) slam[tl * d.N + n] = lam[n];
+    const R* pr = P + ((size_t)f * d.T + t) * d.M;
+    for (int m = 0; m < d.M; ++m) {
+      const R iy = (R)1 / model_var(d, lam, sg, m);
+      sr[(tl * d.M + m) * 2 + 0] = pr[m] * iy * iy;
+      sr[(tl * d.M + m) * 2 + 1] = iy;
+    }
+  }
+  __syncthreads();
+
+  R* out = gpart + ((size_t)f * d.S + s) * d.N * d.M * 2;
+  for (int idx = tid; idx < d.N * d.M * 2; idx += kBlock) {
+    const int which = idx & 1, nm = idx >> 1;
+    const int n = nm / d.M, m = nm - n * d.M;
+    R acc = 0;
+    for (int tl = 0; tl < nt; ++tl) acc += slam[tl * d.N + n] * sr[(tl * d.M + m) * 2 + which];
+    out[idx] = acc;
+  }
+}
+
+template <typename R>
+__global__ void k_gapply(Dims d, R* __restrict__ g, const R* __restrict__ gpart, int* __restrict__ status) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per_f = d.N * d.M;
+  if (idx >= d.F * per_f) return;
+  const int f = idx / per_f, nm = idx - f * per_f;
+  R num = 0, den = 0;
+  for (int s = 0; s < d.S; ++s) {
+    const R* pp = gpart + (((size_t)f * d.S + s) * per_f + nm) * 2;
+    num += pp[0];
+    den += pp[1];
+  }
+  const R v = g[idx] * sqrt(num / rmax(den, (R)d.eps));
+  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  g[idx] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Cost (13), data part: per tile the FP64 sum of |Q x|^2 / y + ln y.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_nll(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+                                                const R* __restrict__ W, const R* __restrict__ H,
+                                                const R* __restrict__ g, double* __restrict__ nllpart) {
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int t0 = s * d.SL;
+  const int nt = min(d.SL, d.T - t0);
+  __shared__ double red[kBlock];
+  const cx<R>* qf = Q + (size_t)f * d.QF;
+  const R* gf = g + (size_t)f * d.N * d.M;
+  double acc = 0.0;
+  for (int tl = tid; tl < nt; tl += kBlock) {
+    const int t = t0 + tl;
+    R lam[kMaxN];
+    source_psd(d, W + (size_t)f * d.K, d.F * d.K, H, t, lam);
+    const cx<R>* xr = X + ((size_t)f * d.T + t) * d.M;
+    for (int l = 0; l < d.L; ++l) {
+      const int Ml = d.mics[l], o = d.moff[l];
+      for (int mu = 0; mu < Ml; ++mu) {
+        R zr = 0, zi = 0;
+        for (int c = 0; c < Ml; ++c) {
+          const cx<R> q = qf[d.qoff[l] + mu * Ml + c];
+          const cx<R> x = xr[o + c];
+          zr += q.re * x.re - q.im * x.im;
+          zi += q.re * x.im + q.im * x.re;
+        }
+        const R y = model_var(d, lam, gf, o + mu);
+        acc += (double)((zr * zr + zi * zi) / y) + log((double)y);
+      }
+    }
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) nllpart[(size_t)f * d.S + s] = red[0];
+}
+
+// ln|det Q_fl| by elimination in FP64.  Block (f, l).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_logdet(Dims d, const cx<R>* __restrict__ Q, double* __restrict__ logdet) {
+  const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
+  const int Ml = d.mics[l];
+  __shared__ cd sA[kMaxMl * kMaxMl];
+  __shared__ double s_logabs;
+  __shared__ int s_sing;
+  const cx<R>* qb = Q + (size_t)f * d.QF + d.qoff[l];
+  for (int i = tid; i < Ml * Ml; i += blockDim.x) sA[i] = {(double)qb[i].re, (double)qb[i].im};
+  __syncthreads();
+  eliminate(sA, Ml, Ml, Ml, &s_logabs, &s_sing);
+  if (tid == 0) logdet[(size_t)f * d.L + l] = s_sing ? -INFINITY : s_logabs;
+}
+
+// Q_fl^{-1} in FP64 by Gauss-Jordan on [Q | I].  Block (f, l).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_qinv(Dims d, const cx<R>* __restrict__ Q, cd* __restrict__ Qinv,
+                                                 int* __restrict__ status) {
+  const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, bd = blockDim.x;
+  const int Ml = d.mics[l], ld = 2 * Ml;
+  __shared__ cd sA[kMaxMl * 2 * kMaxMl];
+  __shared__ double s_logabs;
+  __shared__ int s_sing;
+  const cx<R>* qb = Q + (size_t)f * d.QF + d.qoff[l];
+  for (int i = tid; i < Ml * ld; i += bd) {
+    const int r = i / ld, c = i - r * ld;
+    sA[i] = c < Ml ? cd{(double)qb[r * Ml + c].re, (double)qb[r * Ml + c].im} : cd{c - Ml == r ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  eliminate(sA, ld, Ml, ld, &s_logabs, &s_sing);
+  if (tid == 0 && s_sing) atomicOr(status, kStSingular);
+  // back substitution for all right-hand sides (one thread per column of the inverse)
+  cd* out = Qinv + (size_t)f * d.QF + d.qoff[l];
+  for (int c = tid; c < Ml; c += bd) {
+    for (int r = Ml - 1; r >= 0; --r) {
+      cd acc = sA[r * ld + Ml + c];
+      for (int j = r + 1; j < Ml; ++j) acc = csub(acc, cmul(sA[r * ld + j], out[j * Ml + c]));
+      out[r * Ml + c] = cmul(acc, cinv(sA[r * ld + r]));
+    }
+  }
+}
+
+// Multichannel Wiener filter per subarray; tile (f, slice), one frame per thread.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_sep(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+                                                const cd* __restrict__ Qinv, const R* __restrict__ W,
+                                                const R* __restrict__ H, const R* __restrict__ g,
+                                                cx<R>* __restrict__ S) {
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int t0 = s * d.SL;
+  const int nt = min(d.SL, d.T - t0);
+  const cx<R>* qf = Q + (size_t)f * d.QF;
+  const cd* qi = Qinv + (size_t)f * d.QF;
+  const R* gf = g + (size_t)f * d.N * d.M;
+  for (int tl = tid; tl < nt; tl += kBlock) {
+    const int t = t0 + tl;
+    R lam[kMaxN];
+    source_psd(d, W + (size_t)f * d.K, d.F * d.K, H, t, lam);
+    const cx<R>* xr = X + ((size_t)f * d.T + t) * d.M;
+    for (int l = 0; l < d.L; ++l) {
+      const int Ml = d.mics[l], o = d.moff[l];
+      R zr[kMaxMl], zi[kMaxMl], iy[kMaxMl];
+      for (int mu = 0; mu < Ml; ++mu) {
+        R ar = 0, ai = 0;
+        for (int c = 0; c < Ml; ++c) {
+          const cx<R> q = qf[d.qoff[l] + mu * Ml + c];
+          const cx<R> x = xr[o + c];
+          ar += q.re * x.re - q.im * x.im;
+          ai += q.re * x.im + q.im * x.re;
+        }
+        zr[mu] = ar;
+        zi[mu] = ai;
+        iy[mu] = (R)1 / model_var(d, lam, gf, o + mu);
+      }
+      for (int n = 0; n < d.N; ++n) {
+        cx<R>* sr = S + (((size_t)n * d.F + f) * d.T + t) * d.M + o;
+        for (int a = 0; a < Ml; ++a) {
+          R vr = 0, vi = 0;
+          for (int mu = 0; mu < Ml; ++mu) {
+            const R gain = lam[n] * gf[n * d.M + o + mu] * iy[mu];
+            const cd q = qi[d.qoff[l] + a * Ml + mu];
+            const R ur = gain * zr[mu], ui = gain * zi[mu];
+            vr += (R)q.re * ur - (R)q.im * ui;
+            vi += (R)q.re * ui + (R)q.im * ur;
+          }
+          sr[a].re = vr;
+          sr[a].im = vi;
+        }
+      }
+    }
+  }
+}
+
+// Full Hermitian covariances from the slice sums (diagnostic export of eq. (14)).
+template <typename R>
+__global__ void k_expand(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict__ V) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d.F * d.VF) return;
+  const int f = idx / d.VF, r = idx - f * d.VF;
+  const int l = subarray_of_vidx(d, r);
+  const int Ml = d.mics[l];
+  const int rl = r - d.voff[l];
+  const int mu = rl / (Ml * Ml);
+  int a, b, part;
+  packed_pair(Ml, rl - mu * Ml * Ml, a, b, part);
+  double acc = 0.0;
+  for (int s = 0; s < d.S; ++s) acc += (double)Vpart[((size_t)f * d.S + s) * d.VF + r];
+  const R v = (R)(acc / d.T);
+  cx<R>* vb = V + (size_t)f * d.VC + d.voff[l] + mu * Ml * Ml;
+  if (a == b) {
+    vb[a * Ml + a] = {v, (R)0};
+  } else if (part == 0) {
+    vb[a * Ml + b].re = v;
+    vb[b * Ml + a].re = v;
+  } else {
+    vb[a * Ml + b].im = v;
+    vb[b * Ml + a].im = -v;
+  }
+}
+
+__global__ void k_zero_int(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Host-side launchers.
+template <typename R>
+static size_t smem_gram(const Dims& d) {
+  return align_up(sizeof(R) * (d.N * d.K + d.N * d.M + d.SL * d.M), 16) + sizeof(cx<R>) * d.SL * d.M;
+}
+template <typename R>
+static size_t smem_pw(const Dims& d) {
+  return align_up(sizeof(cx<R>) * d.QF, 16) + sizeof(R) * (d.N * d.K + d.N * d.M + d.SL * d.N * 2);
+}
+template <typename R>
+static size_t smem_g(const Dims& d) {
+  return sizeof(R) * (d.N * d.K + d.N * d.M + d.SL * d.N + d.SL * d.M * 2);
+}
+template <typename R>
+static size_t smem_h(const Dims& d) {
+  return sizeof(R) * d.FB * d.TB * d.N * 2;
+}
+
+static int ip_threads(const Dims& d) {
+  int mx = 1;
+  for (int l = 0; l < d.L; ++l) mx = d.mics[l] > mx ? d.mics[l] : mx;
+  return mx * mx <= 64 ? 64 : kBlock;
+}
+
+static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <typename R>
+static hipError_t stage_impl(const Dims& d, const Buffers& b, int stage, hipStream_t s) {
+  const cx<R>* X = static_cast<const cx<R>*>(b.X);
+  cx<R>* Q = static_cast<cx<R>*>(b.Q);
+  R* g = static_cast<R*>(b.g);
+  R* W = static_cast<R*>(b.W);
+  R* H = static_cast<R*>(b.H);
+  R* P = static_cast<R*>(b.P);
+  const dim3 tiles(d.F, d.S);
+  switch (stage) {
+    case DFM_STAGE_IP:
+      hipLaunchKernelGGL(k_gram<R>, tiles, dim3(kBlock), smem_gram<R>(d), s, d, X, W, H, g,
+                         static_cast<R*>(b.Vpart));
+      hipLaunchKernelGGL(k_ip<R>, dim3(d.F, d.L), dim3(ip_threads(d)), 0, s, d,
+                         static_cast<const R*>(b.Vpart), Q, b.logdet, b.status);
+      break;
+    case DFM_STAGE_W:
+      hipLaunchKernelGGL(k_pw<R>, tiles, dim3(kBlock), smem_pw<R>(d), s, d, X, Q, W, H, g, P,
+                         static_cast<R*>(b.Wpart));
+      hipLaunchKernelGGL(k_wapply<R>, dim3(cdiv((size_t)d.N * d.F * d.K, kBlock)), dim3(kBlock), 0, s, d, W,
+                         static_cast<const R*>(b.Wpart), b.status);
+      break;
+    case DFM_STAGE_H:
+      hipLaunchKernelGGL(k_h<R>, dim3(d.FS, d.TBN), dim3(kBlock), smem_h<R>(d), s, d, W, H, g, P,
+                         static_cast<R*>(b.Hpart));
+      hipLaunchKernelGGL(k_happly<R>, dim3(cdiv((size_t)d.N * d.K * d.T, kBlock)), dim3(kBlock), 0, s, d, H,
+                         static_cast<const R*>(b.Hpart), b.status);
+      break;
+    case DFM_STAGE_G:
+      hipLaunchKernelGGL(k_g<R>, tiles, dim3(kBlock), smem_g<R>(d), s, d, W, H, g, P, static_cast<R*>(b.gpart));
+      hipLaunchKernelGGL(k_gapply<R>, dim3(cdiv((size_t)d.F * d.N * d.M, kBlock)), dim3(kBlock), 0, s, d, g,
+                         static_cast<const R*>(b.gpart), b.status);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t nll_impl(const Dims& d, const Buffers& b, hipStream_t s) {
+  const cx<R>* X = static_cast<const cx<R>*>(b.X);
+  const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
+  hipLaunchKernelGGL(k_nll<R>, dim3(d.F, d.S), dim3(kBlock), 0, s, d, X, Q, static_cast<const R*>(b.W),
+                     static_cast<const R*>(b.H), static_cast<const R*>(b.g), b.nllpart);
+  hipLaunchKernelGGL(k_logdet<R>, dim3(d.F, d.L), dim3(ip_threads(d)), 0, s, d, Q, b.logdet);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t sep_impl(const Dims& d, const Buffers& b, void* S, hipStream_t s) {
+  const cx<R>* X = static_cast<const cx<R>*>(b.X);
+  const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
+  hipLaunchKernelGGL(k_qinv<R>, dim3(d.F, d.L), dim3(ip_threads(d)), 0, s, d, Q, static_cast<cd*>(b.Qinv),
+                     b.status);
+  hipLaunchKernelGGL(k_sep<R>, dim3(d.F, d.S), dim3(kBlock), 0, s, d, X, Q, static_cast<const cd*>(b.Qinv),
+                     static_cast<const R*>(b.W), static_cast<const R*>(b.H), static_cast<const R*>(b.g),
+                     static_cast<cx<R>*>(S));
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t cov_impl(const Dims& d, const Buffers& b, void* V, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram<R>, dim3(d.F, d.S), dim3(kBlock), smem_gram<R>(d), s, d,
+                     static_cast<const cx<R>*>(b.X), static_cast<const R*>(b.W), static_cast<const R*>(b.H),
+                     static_cast<const R*>(b.g), static_cast<R*>(b.Vpart));
+  hipLaunchKernelGGL(k_expand<R>, dim3(cdiv((size_t)d.F * d.VF, kBlock)), dim3(kBlock), 0, s, d,
+                     static_cast<const R*>(b.Vpart), static_cast<cx<R>*>(V));
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s) {
+  (void)d;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.status, 16);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const Dims& d, const Buffers& b, int dtype, int stage, hipStream_t s) {
+  return dtype == DFM_C64 ? stage_impl<float>(d, b, stage, s) : stage_impl<double>(d, b, stage, s);
+}
+
+hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s) {
+  return dtype == DFM_C64 ? nll_impl<float>(d, b, s) : nll_impl<double>(d, b, s);
+}
+
+hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s) {
+  return dtype == DFM_C64 ? sep_impl<float>(d, b, S, s) : sep_impl<double>(d, b, S, s);
+}
+
+hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s) {
+  return dtype == DFM_C64 ? cov_impl<float>(d, b, V, s) : cov_impl<double>(d, b, V, s);
+}
+
+}  // namespace dfm
