@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of distributed FastMNMF on one MI355X, as one JSON line.
+
+A step is one whole job on one synthetic mixture already resident in HBM:
+reset the state to its initial values, run the workload's iterations
+(IP sweep + eqs. (8), (9), (10) each), evaluate the cost (13) and separate the
+sources with the per-subarray Wiener filter.  The reported value is
+iterations per second over the timed steps (whole job, one GPU).
+
+Workload (default ``paper_4x4``): F=513 bins, T=625 frames, four subarrays of
+four mics (M=16), N=5 sources, K=16 bases, 100 iterations, complex64 with the
+IP solves in FP64.  Inputs are seeded synthetic mixtures (see
+``paper_2605_19388_amd/synth.py``).
+
+Extra objects on the line:
+* ``roofline`` -- the kernel with the largest share of an iteration: its
+  algorithmic HBM bytes per launch divided by its average duration, measured
+  with HIP events around each of its launches during the timed steps;
+* ``cpu_baseline`` -- the FP64 NumPy oracle timed on this host on a bounded
+  sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FastMNMF iterations/sec (F·T·M bins/s) at 4×4 mics N=5; % MFMA/HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per F*T*M bin for each streaming kernel of the FP32 path
+# (complex64 X = 8 B, FP32 P = 4 B).  One iteration's schedule reads X twice and
+# writes P once and reads it twice: 28 B per bin.
+BYTES_PER_BIN = {"k_gram": 8.0, "k_pw": 12.0, "k_h": 4.0, "k_g": 4.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="paper_4x4")
+    ap.add_argument("--iters", type=int, default=None, help="iterations per step (default: the workload's)")
+    ap.add_argument("--cpu-sample-iters", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, X64, W0, H0, n_iter):
+    """Time the FP64 oracle, unmodified, on n_iter iterations of the same full-size workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import dfmnmf as D
+
+    Q, g = w["Q"], w["g"]
+    st = D.iterate(X64, Q, g, W0, H0, w["mics"], 1)          # warm-up
+    t0 = time.perf_counter()
+    D.iterate(X64, *st, w["mics"], n_iter)
+    dt = time.perf_counter() - t0
+    threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    return {"value": n_iter / dt, "unit": "iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_iter} of {w['iters']} iterations of {w['name']} at full size "
+                      f"(F={w['F']}, T={w['T']}, M={w['M']}, N={w['N']}, K={w['K']}) after 1 warm-up "
+                      f"iteration, NumPy FP64, {dt:.1f} s",
+            "ms_per_iteration": 1e3 * dt / n_iter, "bins_per_s": n_iter * w["F"] * w["T"] * w["M"] / dt,
+            "cpu": _cpu_model(), "np_version": np.__version__}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the method is sharded across GPUs only by running independent mixtures).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2605_19388_amd import DistributedFastMNMF, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = synth.make(args.workload)
+    iters = args.iters or w["iters"]
+    F, T, M, N, K, mics = w["F"], w["T"], w["M"], w["N"], w["K"], w["mics"]
+    X32 = w["X"].astype(np.complex64)
+    W32, H32 = w["W"].astype(np.float32), w["H"].astype(np.float32)
+    dev = torch.device("cuda:0")
+    p = DistributedFastMNMF(X32, mics, N, K, W=W32, H=H32, Q=w["Q"].astype(np.complex64),
+                            g=w["g"].astype(np.float32), device=dev)
+    init = {k: getattr(p, k).clone() for k in ("Q", "g", "W", "H")}
+    S = torch.empty((N, F, T, M), dtype=torch.complex64, device=dev)
+
+    def reset():
+        for k, v in init.items():
+            getattr(p, k).copy_(v)
+
+    def one_step():
+        reset()
+        p.step(iters)
+        nll = p.nll()
+        p.separate(out=S)
+        return nll
+
+    log(f"[bench] workload {w['name']} F={F} T={T} mics={mics} N={N} K={K} iters/step={iters}")
+    # Per-kernel durations (outside the timed region) to find the dominant kernel.
+    reset()
+    p.step(2)
+    ktimes = p.kernel_times(reps=args.kernel_reps)
+    reset()
+    log("[bench] per-kernel average ms: " + ", ".join(f"{k}={v * 1e3:.1f}us" for k, v in ktimes.items()))
+    dominant = max(ktimes, key=ktimes.get)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    p.profile_kernel(dominant, max_launches=iters * args.steps + 8)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    nll = None
+    for _ in range(args.steps):
+        nll = one_step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dom_ms, dom_n = p.profile_read()
+    p.profile_kernel(None)
+    p.sync_status()
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    value = iters * args.steps / elapsed
+    bins = F * T * M
+    log(f"[bench] {args.steps} steps in {elapsed:.4f} s (events {gpu_ms:.2f} ms); nll={nll:.6e}; "
+        f"{dominant}: {dom_ms * 1e3:.1f} us avg over {dom_n} launches")
+
+    if dominant in BYTES_PER_BIN:
+        traffic_alg = BYTES_PER_BIN[dominant] * bins
+        achieved = traffic_alg / (dom_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
+                "avg_us": round(dom_ms * 1e3, 3), "launches": dom_n,
+                "algorithmic_bytes_per_launch": traffic_alg}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": dominant, "avg_us": round(dom_ms * 1e3, 3), "launches": dom_n}
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "iterations/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": w["name"], "F": F, "T": T, "mics": list(mics), "N": N, "K": K,
+                      "iterations_per_step": iters, "bins_per_iteration": bins,
+                      "step": "reset + iterations + cost (13) + Wiener separation"},
+           "bins_per_s": round(value * bins, 1),
+           "per_kernel_us": {k: round(v * 1e3, 2) for k, v in ktimes.items()},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(w, X32.astype(np.complex128), W32.astype(np.float64),
+                                           H32.astype(np.float64), args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -135,6 +135,24 @@ dfm_status dfm_covariances(dfm_plan* plan, void* V, void* stream);
  * DFM_E_SINGULAR or DFM_E_NONFINITE); clears it. */
 dfm_status dfm_sync_status(dfm_plan* plan, void* stream);
 
+/* ---- Measurement (not part of the method; used to price kernels against the roofline).
+ * Kernels of one iteration are numbered 0 .. dfm_kernel_count()-1 in launch order. */
+int32_t dfm_kernel_count(void);
+/* Static name of kernel i, or NULL if i is out of range. */
+const char* dfm_kernel_name(int32_t kernel);
+/* Launch each kernel `reps` >= 1 times back to back between two HIP events on
+ * `stream` and write its average duration in ms to avg_ms[i] (host array of
+ * dfm_kernel_count() doubles).  Synchronises.  Repeated launches of the
+ * update kernels change Q, g, W, H: save and restore the state around it. */
+dfm_status dfm_kernel_times(dfm_plan* plan, int32_t reps, double* avg_ms, void* stream);
+/* From now on bracket every launch of kernel `kernel` made by dfm_step /
+ * dfm_substep with a pair of HIP events on the launch stream, for at most
+ * max_launches launches; kernel = -1 stops and frees the events. */
+dfm_status dfm_profile_kernel(dfm_plan* plan, int32_t kernel, int32_t max_launches);
+/* Synchronise `stream`, return the average event-measured duration (ms) and
+ * the number of profiled launches since the last read, and reset the count. */
+dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, void* stream);
+
 /* Free the host-side plan.  Does not touch the caller's device buffers. */
 void dfm_destroy(dfm_plan* plan);
 

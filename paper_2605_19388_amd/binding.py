@@ -40,7 +40,8 @@ class Problem(ctypes.Structure):
 
 _lib = None
 EXPORTS = ("dfm_workspace_size", "dfm_init", "dfm_step", "dfm_substep", "dfm_nll", "dfm_separate",
-           "dfm_covariances", "dfm_sync_status", "dfm_destroy", "dfm_status_string")
+           "dfm_covariances", "dfm_sync_status", "dfm_kernel_times", "dfm_profile_kernel", "dfm_profile_read",
+           "dfm_kernel_count", "dfm_kernel_name", "dfm_destroy", "dfm_status_string")
 
 
 def load(path: str = LIB_PATH):
@@ -61,12 +62,20 @@ def load(path: str = LIB_PATH):
     lib.dfm_separate.argtypes = [vp, vp, vp]
     lib.dfm_covariances.argtypes = [vp, vp, vp]
     lib.dfm_sync_status.argtypes = [vp, vp]
+    lib.dfm_kernel_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), vp]
+    lib.dfm_profile_kernel.argtypes = [vp, i32, i32]
+    lib.dfm_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), vp]
+    lib.dfm_kernel_count.argtypes = []
+    lib.dfm_kernel_count.restype = i32
+    lib.dfm_kernel_name.argtypes = [i32]
+    lib.dfm_kernel_name.restype = ctypes.c_char_p
     lib.dfm_destroy.argtypes = [vp]
     lib.dfm_destroy.restype = None
     lib.dfm_status_string.argtypes = [st]
     lib.dfm_status_string.restype = ctypes.c_char_p
-    for name in EXPORTS[:-2]:
-        getattr(lib, name).restype = st
+    for name in EXPORTS:
+        if name not in ("dfm_kernel_count", "dfm_kernel_name", "dfm_destroy", "dfm_status_string"):
+            getattr(lib, name).restype = st
     _lib = lib
     return lib
 
@@ -191,6 +200,30 @@ class DistributedFastMNMF:
         out = torch.empty((self.F, vc), dtype=self.X.dtype, device=self.device)
         _check(load().dfm_covariances(self._plan, out.data_ptr(), self._stream()), "dfm_covariances")
         return out
+
+    def kernel_names(self):
+        lib_ = load()
+        return [lib_.dfm_kernel_name(i).decode() for i in range(lib_.dfm_kernel_count())]
+
+    def kernel_times(self, reps: int = 20):
+        """Average ms per launch of every kernel of one iteration (changes the state)."""
+        lib_ = load()
+        n = lib_.dfm_kernel_count()
+        out = (ctypes.c_double * n)()
+        _check(lib_.dfm_kernel_times(self._plan, int(reps), out, self._stream()), "dfm_kernel_times")
+        return dict(zip(self.kernel_names(), list(out)))
+
+    def profile_kernel(self, name_or_index, max_launches: int = 4096):
+        k = -1 if name_or_index is None else (
+            self.kernel_names().index(name_or_index) if isinstance(name_or_index, str) else int(name_or_index))
+        _check(load().dfm_profile_kernel(self._plan, k, int(max_launches)), "dfm_profile_kernel")
+
+    def profile_read(self):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(load().dfm_profile_read(self._plan, ctypes.byref(ms), ctypes.byref(n), self._stream()),
+               "dfm_profile_read")
+        return float(ms.value), int(n.value)
 
     def sync_status(self):
         _check(load().dfm_sync_status(self._plan, self._stream()), "dfm_sync_status")

@@ -16,6 +16,10 @@ struct dfm_plan {
   Dims d;
   Buffers b;
   int dtype;
+  // Event timing of one kernel during ordinary launches (dfm_profile_kernel).
+  int prof_kid = -1;
+  std::vector<hipEvent_t> prof_events;  // pairs (start, stop)
+  size_t prof_used = 0;
 };
 
 namespace dfm {
@@ -114,6 +118,35 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   b.status = reinterpret_cast<int*>(take(64));
 }
 
+static hipError_t run_kernel(dfm_plan* plan, int kid, hipStream_t s) {
+  const bool prof = plan->prof_kid == kid && plan->prof_used + 2 <= plan->prof_events.size();
+  if (prof && hipEventRecord(plan->prof_events[plan->prof_used], s) != hipSuccess) return hipErrorUnknown;
+  const hipError_t e = launch_kernel(plan->d, plan->b, plan->dtype, kid, s);
+  if (e != hipSuccess) return e;
+  if (prof) {
+    if (hipEventRecord(plan->prof_events[plan->prof_used + 1], s) != hipSuccess) return hipErrorUnknown;
+    plan->prof_used += 2;
+  }
+  return hipSuccess;
+}
+
+static hipError_t run_stage(dfm_plan* plan, int stage, hipStream_t s) {
+  int kids[8];
+  const int n = stage_kernels(stage, kids);
+  for (int i = 0; i < n; ++i) {
+    const hipError_t e = run_kernel(plan, kids[i], s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static void free_profile(dfm_plan* plan) {
+  for (hipEvent_t e : plan->prof_events) (void)hipEventDestroy(e);
+  plan->prof_events.clear();
+  plan->prof_used = 0;
+  plan->prof_kid = -1;
+}
+
 static dfm_status read_status(dfm_plan* plan, hipStream_t s, bool clear) {
   int st = 0;
   if (hipMemcpyAsync(&st, plan->b.status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return DFM_E_HIP;
@@ -171,14 +204,13 @@ dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
   for (int it = 0; it < n_iter; ++it)
     for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G; ++stage)
-      if (dfm::launch_stage(plan->d, plan->b, plan->dtype, stage, s) != hipSuccess) return DFM_E_HIP;
+      if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
   return DFM_OK;
 }
 
 dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream) {
   if (!plan || stage < DFM_STAGE_IP || stage > DFM_STAGE_G) return DFM_E_ARG;
-  if (dfm::launch_stage(plan->d, plan->b, plan->dtype, stage, static_cast<hipStream_t>(stream)) != hipSuccess)
-    return DFM_E_HIP;
+  if (dfm::run_stage(plan, stage, static_cast<hipStream_t>(stream)) != hipSuccess) return DFM_E_HIP;
   return DFM_OK;
 }
 
@@ -219,7 +251,72 @@ dfm_status dfm_sync_status(dfm_plan* plan, void* stream) {
   return dfm::read_status(plan, static_cast<hipStream_t>(stream), true);
 }
 
-void dfm_destroy(dfm_plan* plan) { delete plan; }
+int32_t dfm_kernel_count(void) { return dfm::kNumKernels; }
+
+const char* dfm_kernel_name(int32_t kernel) { return dfm::kernel_name(kernel); }
+
+dfm_status dfm_kernel_times(dfm_plan* plan, int32_t reps, double* avg_ms, void* stream) {
+  if (!plan || !avg_ms || reps < 1) return DFM_E_ARG;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return DFM_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DFM_E_HIP;
+  }
+  dfm_status st = DFM_OK;
+  for (int k = 0; k < dfm::kNumKernels && st == DFM_OK; ++k) {
+    float ms = 0.f;
+    if (hipEventRecord(e0, s) != hipSuccess) st = DFM_E_HIP;
+    for (int r = 0; r < reps && st == DFM_OK; ++r)
+      if (dfm::launch_kernel(plan->d, plan->b, plan->dtype, k, s) != hipSuccess) st = DFM_E_HIP;
+    if (st == DFM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = DFM_E_HIP;
+    avg_ms[k] = ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+dfm_status dfm_profile_kernel(dfm_plan* plan, int32_t kernel, int32_t max_launches) {
+  if (!plan || kernel >= dfm::kNumKernels || (kernel >= 0 && max_launches < 1)) return DFM_E_ARG;
+  dfm::free_profile(plan);
+  if (kernel < 0) return DFM_OK;
+  plan->prof_events.resize(2 * (size_t)max_launches);
+  for (size_t i = 0; i < plan->prof_events.size(); ++i)
+    if (hipEventCreate(&plan->prof_events[i]) != hipSuccess) {
+      plan->prof_events.resize(i);
+      dfm::free_profile(plan);
+      return DFM_E_HIP;
+    }
+  plan->prof_kid = kernel;
+  return DFM_OK;
+}
+
+dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, void* stream) {
+  if (!plan || !avg_ms || !launches) return DFM_E_ARG;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return DFM_E_HIP;
+  double total = 0.0;
+  const size_t n = plan->prof_used / 2;
+  for (size_t i = 0; i < n; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, plan->prof_events[2 * i], plan->prof_events[2 * i + 1]) != hipSuccess)
+      return DFM_E_HIP;
+    total += ms;
+  }
+  *launches = (int64_t)n;
+  *avg_ms = n ? total / n : 0.0;
+  plan->prof_used = 0;
+  return DFM_OK;
+}
+
+void dfm_destroy(dfm_plan* plan) {
+  if (!plan) return;
+  dfm::free_profile(plan);
+  delete plan;
+}
 
 const char* dfm_status_string(dfm_status s) {
   switch (s) {

@@ -57,9 +57,14 @@ struct Buffers {
 size_t workspace_bytes(const Dims& d, int dtype);
 void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 
+// Kernels of one iteration, in launch order.
+enum KernelId { kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply, kNumKernels };
+
 // Launchers (return hipSuccess or the first launch error).
 hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s);
-hipError_t launch_stage(const Dims& d, const Buffers& b, int dtype, int stage, hipStream_t s);
+hipError_t launch_kernel(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
+const char* kernel_name(int kid);
+int stage_kernels(int stage, int* kids);  // fills kids, returns count
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s);
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
 hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);

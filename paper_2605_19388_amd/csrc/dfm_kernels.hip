@@ -709,7 +709,7 @@ static int ip_threads(const Dims& d) {
 static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <typename R>
-static hipError_t stage_impl(const Dims& d, const Buffers& b, int stage, hipStream_t s) {
+static hipError_t kernel_impl(const Dims& d, const Buffers& b, int kid, hipStream_t s) {
   const cx<R>* X = static_cast<const cx<R>*>(b.X);
   cx<R>* Q = static_cast<cx<R>*>(b.Q);
   R* g = static_cast<R*>(b.g);
@@ -717,27 +717,35 @@ static hipError_t stage_impl(const Dims& d, const Buffers& b, int stage, hipStre
   R* H = static_cast<R*>(b.H);
   R* P = static_cast<R*>(b.P);
   const dim3 tiles(d.F, d.S);
-  switch (stage) {
-    case DFM_STAGE_IP:
+  switch (kid) {
+    case kKGram:
       hipLaunchKernelGGL(k_gram<R>, tiles, dim3(kBlock), smem_gram<R>(d), s, d, X, W, H, g,
                          static_cast<R*>(b.Vpart));
+      break;
+    case kKIp:
       hipLaunchKernelGGL(k_ip<R>, dim3(d.F, d.L), dim3(ip_threads(d)), 0, s, d,
                          static_cast<const R*>(b.Vpart), Q, b.logdet, b.status);
       break;
-    case DFM_STAGE_W:
+    case kKPw:
       hipLaunchKernelGGL(k_pw<R>, tiles, dim3(kBlock), smem_pw<R>(d), s, d, X, Q, W, H, g, P,
                          static_cast<R*>(b.Wpart));
+      break;
+    case kKWApply:
       hipLaunchKernelGGL(k_wapply<R>, dim3(cdiv((size_t)d.N * d.F * d.K, kBlock)), dim3(kBlock), 0, s, d, W,
                          static_cast<const R*>(b.Wpart), b.status);
       break;
-    case DFM_STAGE_H:
+    case kKH:
       hipLaunchKernelGGL(k_h<R>, dim3(d.FS, d.TBN), dim3(kBlock), smem_h<R>(d), s, d, W, H, g, P,
                          static_cast<R*>(b.Hpart));
+      break;
+    case kKHApply:
       hipLaunchKernelGGL(k_happly<R>, dim3(cdiv((size_t)d.N * d.K * d.T, kBlock)), dim3(kBlock), 0, s, d, H,
                          static_cast<const R*>(b.Hpart), b.status);
       break;
-    case DFM_STAGE_G:
+    case kKG:
       hipLaunchKernelGGL(k_g<R>, tiles, dim3(kBlock), smem_g<R>(d), s, d, W, H, g, P, static_cast<R*>(b.gpart));
+      break;
+    case kKGApply:
       hipLaunchKernelGGL(k_gapply<R>, dim3(cdiv((size_t)d.F * d.N * d.M, kBlock)), dim3(kBlock), 0, s, d, g,
                          static_cast<const R*>(b.gpart), b.status);
       break;
@@ -785,8 +793,24 @@ hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stage(const Dims& d, const Buffers& b, int dtype, int stage, hipStream_t s) {
-  return dtype == DFM_C64 ? stage_impl<float>(d, b, stage, s) : stage_impl<double>(d, b, stage, s);
+hipError_t launch_kernel(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s) {
+  return dtype == DFM_C64 ? kernel_impl<float>(d, b, kid, s) : kernel_impl<double>(d, b, kid, s);
+}
+
+const char* kernel_name(int kid) {
+  static const char* names[kNumKernels] = {"k_gram", "k_ip", "k_pw", "k_wapply", "k_h", "k_happly", "k_g", "k_gapply"};
+  return kid >= 0 && kid < kNumKernels ? names[kid] : nullptr;
+}
+
+// Kernels of each sub-step, in launch order.
+int stage_kernels(int stage, int* kids) {
+  switch (stage) {
+    case DFM_STAGE_IP: kids[0] = kKGram; kids[1] = kKIp; return 2;
+    case DFM_STAGE_W: kids[0] = kKPw; kids[1] = kKWApply; return 2;
+    case DFM_STAGE_H: kids[0] = kKH; kids[1] = kKHApply; return 2;
+    case DFM_STAGE_G: kids[0] = kKG; kids[1] = kKGApply; return 2;
+  }
+  return 0;
 }
 
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s) {

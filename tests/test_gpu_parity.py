@@ -6,9 +6,13 @@ the same seeded inputs.  Tolerances:
 
 * FP64 path: 1e-10 relative (rounding order only).
 * FP32 path, one stage: sums of positive terms in FP32 carry ~u*sqrt(n) relative
-  error (u = 6e-8, n <= a few thousand terms) -> 2e-5 for W, H, g; the FP32
-  covariances feed an FP64 solve whose conditioning amplifies that by the
-  condition number of Q V (<= ~50 on these inputs) -> 2e-4 for Q.
+  error (u = 6e-8, n <= a few thousand terms) -> 2e-5 for W, H, g.  The FP32
+  covariances (relative error ~u*sqrt(SL) <= ~1e-6 per slice of SL <= 128
+  frames) feed an FP64 solve that amplifies it by kappa = max(cond(Q V_mu),
+  cond(V_mu)), so Q is
+  held to max(2e-4, 2e-8 * kappa) with kappa measured by the oracle on the same
+  inputs; the cost after the sweep, which is flat to first order along the
+  ill-determined directions, is held to 1e-6.
 * FP32 end to end: 1e-4 relative on the cost and on each source's separated
   spectrogram, the bar the method is held to.
 """
@@ -43,6 +47,16 @@ def _problem(F, T, mics, N, K, seed, fp32, mixing="iid"):
     return X, Q, g, W, H
 
 
+def _ip_condition(X, mics, st):
+    """max over (f, l, mu) of cond(Q_fl V_flmu) and cond(V_flmu): the amplification of
+    covariance errors in the solve of eq. (15), (Q V) b = e  <=>  V b = Q^{-1} e."""
+    y = D.model_variance(D.source_psd(st["W"], st["H"]), st["g"])
+    V = D.weighted_covariances(X, y, mics)
+    Qb = D.q_blocks(st["Q"], mics)
+    return max(max(float(np.linalg.cond(Qb[l] @ V[l][:, mu]).max()), float(np.linalg.cond(V[l][:, mu]).max()))
+               for l in range(len(mics)) for mu in range(mics[l]))
+
+
 # ------------------------------------------------------------------ one-step parity per stage
 STAGE_CASES = [
     # (F, T, mics, N, K): several slices with a ragged tail, mixed subarray sizes
@@ -67,7 +81,13 @@ def test_one_step_parity_every_stage(case, fp32):
             want = oracle_stage(stage, X, mics, before)
             key = STAGE_KEY[stage]
             err = rel(got[key], want[key])
-            assert err < TOL_STAGE[fp32][key], (it, stage, err)
+            tol = TOL_STAGE[fp32][key]
+            if fp32 and stage == "ip":
+                tol = max(tol, 2e-8 * _ip_condition(X, mics, before))
+                c_got = D.nll(X, got["Q"], got["g"], got["W"], got["H"], mics)
+                c_want = D.nll(X, want["Q"], want["g"], want["W"], want["H"], mics)
+                assert abs(c_got - c_want) < 1e-6 * abs(c_want), (it, c_got, c_want)
+            assert err < tol, (it, stage, err, tol)
             for other in ("Q", "g", "W", "H"):
                 if other != key:
                     assert np.array_equal(got[other], before[other]), (stage, other)
