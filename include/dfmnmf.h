@@ -136,13 +136,15 @@ dfm_status dfm_covariances(dfm_plan* plan, void* V, void* stream);
 dfm_status dfm_sync_status(dfm_plan* plan, void* stream);
 
 /* ---- Measurement (not part of the method; used to price kernels against the roofline).
- * Kernels of one iteration are numbered 0 .. dfm_kernel_count()-1 in launch order. */
-int32_t dfm_kernel_count(void);
-/* Static name of kernel i, or NULL if i is out of range. */
-const char* dfm_kernel_name(int32_t kernel);
+ * The kernels of one iteration of a plan are numbered 0 .. dfm_kernel_count(plan)-1 in
+ * launch order (five for uniform partitions with a compiled (N, K, M_l) set, eight
+ * otherwise). */
+int32_t dfm_kernel_count(const dfm_plan* plan);
+/* Static name of kernel i of the plan's iteration, or NULL if out of range. */
+const char* dfm_kernel_name(const dfm_plan* plan, int32_t kernel);
 /* Launch each kernel `reps` >= 1 times back to back between two HIP events on
  * `stream` and write its average duration in ms to avg_ms[i] (host array of
- * dfm_kernel_count() doubles).  Synchronises.  Repeated launches of the
+ * dfm_kernel_count(plan) doubles).  Synchronises.  Repeated launches of the
  * update kernels change Q, g, W, H: save and restore the state around it. */
 dfm_status dfm_kernel_times(dfm_plan* plan, int32_t reps, double* avg_ms, void* stream);
 /* From now on bracket every launch of kernel `kernel` made by dfm_step /

@@ -65,9 +65,9 @@ def load(path: str = LIB_PATH):
     lib.dfm_kernel_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.dfm_profile_kernel.argtypes = [vp, i32, i32]
     lib.dfm_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), vp]
-    lib.dfm_kernel_count.argtypes = []
+    lib.dfm_kernel_count.argtypes = [vp]
     lib.dfm_kernel_count.restype = i32
-    lib.dfm_kernel_name.argtypes = [i32]
+    lib.dfm_kernel_name.argtypes = [vp, i32]
     lib.dfm_kernel_name.restype = ctypes.c_char_p
     lib.dfm_destroy.argtypes = [vp]
     lib.dfm_destroy.restype = None
@@ -203,12 +203,12 @@ class DistributedFastMNMF:
 
     def kernel_names(self):
         lib_ = load()
-        return [lib_.dfm_kernel_name(i).decode() for i in range(lib_.dfm_kernel_count())]
+        return [lib_.dfm_kernel_name(self._plan, i).decode() for i in range(lib_.dfm_kernel_count(self._plan))]
 
     def kernel_times(self, reps: int = 20):
         """Average ms per launch of every kernel of one iteration (changes the state)."""
         lib_ = load()
-        n = lib_.dfm_kernel_count()
+        n = lib_.dfm_kernel_count(self._plan)
         out = (ctypes.c_double * n)()
         _check(lib_.dfm_kernel_times(self._plan, int(reps), out, self._stream()), "dfm_kernel_times")
         return dict(zip(self.kernel_names(), list(out)))

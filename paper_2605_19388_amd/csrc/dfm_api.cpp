@@ -27,6 +27,31 @@ namespace dfm {
 static size_t real_size(int dtype) { return dtype == DFM_C64 ? 4 : 8; }
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
+// Specialised path: uniform partition with a compiled (N, K, M_l) set.  Frames per slice:
+// the largest of 128, 64, 32, 16 whose LDS needs fit 64 KB in every kernel.
+static bool choose_fast(Dims& d, int dtype) {
+  int ml = d.mics[0];
+  for (int l = 1; l < d.L; ++l)
+    if (d.mics[l] != ml) return false;
+  const int set = fast_set_index(d.N, d.K, ml);
+  if (set < 0) return false;
+  d.fast = set;
+  d.ML = ml;
+  for (int sl = 128; sl >= 16; sl /= 2) {
+    d.S = (d.T + sl - 1) / sl;
+    d.SL = (d.T + d.S - 1) / d.S;
+    d.SLP = ((d.SL + 3) & ~3) + 4;
+    d.TB = 16;
+    d.TBN = (d.T + 15) / 16;
+    const int hw = fast_h_waves(dtype);
+    d.FG = ((d.F + 15) / 16 + hw - 1) / hw;
+    if (fast_max_smem(d, dtype) <= 64 * 1024) return true;
+  }
+  d.fast = -1;
+  d.ML = 0;
+  return false;
+}
+
 // Frames per streaming slice: as many as fit the LDS budget of every tile kernel, at most 128.
 static void choose_tiles(Dims& d, int dtype) {
   const size_t r = real_size(dtype), c = 2 * r;
@@ -77,10 +102,11 @@ static dfm_status make_dims(const dfm_problem* p, Dims& d) {
   d.QF = q;
   d.VF = v;
   d.VC = v;
+  d.fast = -1;
   // 32-bit indexing inside kernels: keep every per-buffer element count below 2^31.
   const double big = (double)d.F * d.T * d.M * 2 * (p->N > 1 ? p->N : 1);
   if (big >= 2147483647.0) return DFM_E_SHAPE;
-  choose_tiles(d, p->dtype);
+  if (!choose_fast(d, p->dtype)) choose_tiles(d, p->dtype);
   return DFM_OK;
 }
 
@@ -90,12 +116,13 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   n += al(r * d.F * d.T * d.M);                        // P
   n += al(r * d.F * d.S * d.VF);                       // Vpart
   n += al(r * d.F * d.S * d.N * d.K * 2);              // Wpart
-  n += al(r * (size_t)d.FS * d.N * d.K * d.T * 2);     // Hpart
+  n += al(r * (size_t)(d.fast >= 0 ? d.FG : d.FS) * d.N * d.K * d.T * 2);  // Hpart
   n += al(r * d.F * d.S * d.N * d.M * 2);              // gpart
   n += al(8 * d.F * d.L);                              // logdet
   n += al(8 * d.F * d.S);                              // nllpart
   n += al(16 * d.F * d.QF);                            // Qinv
   n += al(64);                                         // status
+  n += al(4 * (3 * (size_t)d.F + d.TBN));              // counters
   return n;
 }
 
@@ -110,12 +137,13 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   b.P = take(r * d.F * d.T * d.M);
   b.Vpart = take(r * d.F * d.S * d.VF);
   b.Wpart = take(r * d.F * d.S * d.N * d.K * 2);
-  b.Hpart = take(r * (size_t)d.FS * d.N * d.K * d.T * 2);
+  b.Hpart = take(r * (size_t)(d.fast >= 0 ? d.FG : d.FS) * d.N * d.K * d.T * 2);
   b.gpart = take(r * d.F * d.S * d.N * d.M * 2);
   b.logdet = reinterpret_cast<double*>(take(8 * d.F * d.L));
   b.nllpart = reinterpret_cast<double*>(take(8 * d.F * d.S));
   b.Qinv = take(16 * d.F * d.QF);
   b.status = reinterpret_cast<int*>(take(64));
+  b.counters = reinterpret_cast<unsigned*>(take(4 * (3 * (size_t)d.F + d.TBN)));
 }
 
 static hipError_t run_kernel(dfm_plan* plan, int kid, hipStream_t s) {
@@ -132,7 +160,7 @@ static hipError_t run_kernel(dfm_plan* plan, int kid, hipStream_t s) {
 
 static hipError_t run_stage(dfm_plan* plan, int stage, hipStream_t s) {
   int kids[8];
-  const int n = stage_kernels(stage, kids);
+  const int n = stage_kernels(plan->d, stage, kids);
   for (int i = 0; i < n; ++i) {
     const hipError_t e = run_kernel(plan, kids[i], s);
     if (e != hipSuccess) return e;
@@ -251,9 +279,18 @@ dfm_status dfm_sync_status(dfm_plan* plan, void* stream) {
   return dfm::read_status(plan, static_cast<hipStream_t>(stream), true);
 }
 
-int32_t dfm_kernel_count(void) { return dfm::kNumKernels; }
+int32_t dfm_kernel_count(const dfm_plan* plan) {
+  if (!plan) return 0;
+  int kids[16];
+  return dfm::iteration_kernels(plan->d, kids);
+}
 
-const char* dfm_kernel_name(int32_t kernel) { return dfm::kernel_name(kernel); }
+const char* dfm_kernel_name(const dfm_plan* plan, int32_t kernel) {
+  if (!plan) return nullptr;
+  int kids[16];
+  const int n = dfm::iteration_kernels(plan->d, kids);
+  return kernel >= 0 && kernel < n ? dfm::kernel_name(kids[kernel]) : nullptr;
+}
 
 dfm_status dfm_kernel_times(dfm_plan* plan, int32_t reps, double* avg_ms, void* stream) {
   if (!plan || !avg_ms || reps < 1) return DFM_E_ARG;
@@ -265,11 +302,13 @@ dfm_status dfm_kernel_times(dfm_plan* plan, int32_t reps, double* avg_ms, void* 
     return DFM_E_HIP;
   }
   dfm_status st = DFM_OK;
-  for (int k = 0; k < dfm::kNumKernels && st == DFM_OK; ++k) {
+  int kids[16];
+  const int nk = dfm::iteration_kernels(plan->d, kids);
+  for (int k = 0; k < nk && st == DFM_OK; ++k) {
     float ms = 0.f;
     if (hipEventRecord(e0, s) != hipSuccess) st = DFM_E_HIP;
     for (int r = 0; r < reps && st == DFM_OK; ++r)
-      if (dfm::launch_kernel(plan->d, plan->b, plan->dtype, k, s) != hipSuccess) st = DFM_E_HIP;
+      if (dfm::launch_kernel(plan->d, plan->b, plan->dtype, kids[k], s) != hipSuccess) st = DFM_E_HIP;
     if (st == DFM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
       st = DFM_E_HIP;
@@ -281,9 +320,12 @@ dfm_status dfm_kernel_times(dfm_plan* plan, int32_t reps, double* avg_ms, void* 
 }
 
 dfm_status dfm_profile_kernel(dfm_plan* plan, int32_t kernel, int32_t max_launches) {
-  if (!plan || kernel >= dfm::kNumKernels || (kernel >= 0 && max_launches < 1)) return DFM_E_ARG;
+  if (!plan || kernel >= dfm_kernel_count(plan) || (kernel >= 0 && max_launches < 1)) return DFM_E_ARG;
   dfm::free_profile(plan);
   if (kernel < 0) return DFM_OK;
+  int kids[16];
+  dfm::iteration_kernels(plan->d, kids);
+  kernel = kids[kernel];
   plan->prof_events.resize(2 * (size_t)max_launches);
   for (size_t i = 0; i < plan->prof_events.size(); ++i)
     if (hipEventCreate(&plan->prof_events[i]) != hipSuccess) {

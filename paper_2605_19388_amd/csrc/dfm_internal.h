@@ -29,6 +29,10 @@ struct Dims {
   int FB, FS;   // frequencies per tile and number of frequency tiles (activation update)
   int TB, TBN;  // frames per tile and number of frame tiles (activation update)
   double eps;
+  int fast;  // index of the shape-specialised kernel set, or -1 for the generic kernels
+  int ML;    // common subarray size when the partition is uniform, else 0
+  int SLP;   // LDS row stride (elements) of per-frame arrays in the specialised kernels
+  int FG;    // frequency groups of the specialised activation kernel
   int mics[kMaxL];  // M_l
   int moff[kMaxL];  // first mic of subarray l
   int qoff[kMaxL];  // offset of block l in a frequency's packed Q (complex units)
@@ -52,19 +56,30 @@ struct Buffers {
   double* nllpart;  // [F][S]
   void* Qinv;       // [F][QF] complex double
   int* status;      // sticky status word
+  unsigned* counters;  // last-arrival counters of the specialised kernels: [F] [F] [TBN] [F]
 };
 
 size_t workspace_bytes(const Dims& d, int dtype);
 void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 
-// Kernels of one iteration, in launch order.
-enum KernelId { kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply, kNumKernels };
+// Kernels.  Generic path: eight per iteration; specialised path: five (kF*).
+enum KernelId {
+  kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply,
+  kFGram, kFIp, kFPw, kFH, kFG, kNumKernels
+};
 
 // Launchers (return hipSuccess or the first launch error).
 hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s);
 hipError_t launch_kernel(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
 const char* kernel_name(int kid);
-int stage_kernels(int stage, int* kids);  // fills kids, returns count
+int stage_kernels(const Dims& d, int stage, int* kids);  // fills kids, returns count
+int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns count
+
+// Shape-specialised kernel sets (dfm_fast.hip).
+int fast_set_index(int N, int K, int ML);
+size_t fast_max_smem(const Dims& d, int dtype);
+int fast_h_waves(int dtype);
+hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s);
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
 hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);

@@ -14,89 +14,9 @@
 
 #include <cmath>
 
-#include "dfm_internal.h"
+#include "dfm_device.h"
 
 namespace dfm {
-
-template <typename R>
-struct cx {
-  R re, im;
-};
-
-struct cd {
-  double re, im;
-};
-
-__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-__device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cd cconj(cd a) { return {a.re, -a.im}; }
-__device__ __forceinline__ double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
-__device__ __forceinline__ cd cinv(cd a) {
-  const double s = 1.0 / cabs2(a);
-  return {a.re * s, -a.im * s};
-}
-
-template <typename R>
-__device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
-
-// ---------------------------------------------------------------------------------------
-// Packed Hermitian index j in [0, M_l^2): j < M_l is the diagonal entry (j, j) (real);
-// otherwise pair p = (j - M_l) / 2 of the strict upper triangle in row-major order,
-// part (j - M_l) % 2 = 0 for the real and 1 for the imaginary part of V[a][b], a < b.
-__device__ __forceinline__ void packed_pair(int Ml, int j, int& a, int& b, int& part) {
-  if (j < Ml) {
-    a = j;
-    b = j;
-    part = 0;
-    return;
-  }
-  int p = (j - Ml) >> 1;
-  part = (j - Ml) & 1;
-  int row = 0, cnt = Ml - 1;
-  while (p >= cnt) {
-    p -= cnt;
-    ++row;
-    --cnt;
-  }
-  a = row;
-  b = row + 1 + p;
-}
-
-__device__ __forceinline__ int subarray_of_vidx(const Dims& d, int idx) {
-  int l = 0;
-  while (l + 1 < d.L && idx >= d.voff[l + 1]) ++l;
-  return l;
-}
-
-// lambda_n = sum_k W[n][f][k] H[n][k][t] for every source (eq. (2)).
-// w points at W[0][f][0] and wsn is the stride between sources.
-template <typename R>
-__device__ __forceinline__ void source_psd(const Dims& d, const R* w, int wsn, const R* __restrict__ H, int t,
-                                           R (&lam)[kMaxN]) {
-#pragma unroll
-  for (int n = 0; n < kMaxN; ++n) {
-    R acc = 0;
-    if (n < d.N) {
-      const R* hn = H + (size_t)n * d.K * d.T + t;
-      const R* wn = w + (size_t)n * wsn;
-      for (int k = 0; k < d.K; ++k) acc += wn[k] * hn[(size_t)k * d.T];
-    }
-    lam[n] = acc;
-  }
-}
-
-// y_m = max(sum_n lambda_n g[n][m], eps) with gf = g[f][0][0].
-template <typename R>
-__device__ __forceinline__ R model_var(const Dims& d, const R (&lam)[kMaxN], const R* gf, int m) {
-  R acc = 0;
-#pragma unroll
-  for (int n = 0; n < kMaxN; ++n)
-    if (n < d.N) acc += lam[n] * gf[n * d.M + m];
-  return rmax(acc, (R)d.eps);
-}
-
-__host__ __device__ __forceinline__ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------------------------------
 // Weighted covariances, eq. (14): per tile (f, slice) the packed sums
@@ -148,54 +68,6 @@ __global__ __launch_bounds__(kBlock) void k_gram(Dims d, const cx<R>* __restrict
       acc += w * v;
     }
     out[idx] = acc;
-  }
-}
-
-// ---------------------------------------------------------------------------------------
-// In-LDS Gaussian elimination with partial pivoting of the n x ncols row-major
-// matrix A (leading dimension ld), all threads cooperating.  Thread 0 searches the
-// pivot and swaps rows; the others update the trailing rows.  Returns, in thread 0,
-// sum_p ln|A_pp| of the eliminated matrix and whether a zero pivot appeared.
-__device__ void eliminate(cd* A, int ld, int n, int ncols, double* s_logabs, int* s_sing) {
-  const int tid = threadIdx.x, bd = blockDim.x;
-  if (tid == 0) {
-    *s_logabs = 0.0;
-    *s_sing = 0;
-  }
-  for (int p = 0; p < n; ++p) {
-    if (tid == 0) {
-      int piv = p;
-      double best = cabs2(A[p * ld + p]);
-      for (int r = p + 1; r < n; ++r) {
-        const double v = cabs2(A[r * ld + p]);
-        if (v > best) {
-          best = v;
-          piv = r;
-        }
-      }
-      if (piv != p)
-        for (int c = p; c < ncols; ++c) {
-          const cd tmp = A[p * ld + c];
-          A[p * ld + c] = A[piv * ld + c];
-          A[piv * ld + c] = tmp;
-        }
-      if (best == 0.0)
-        *s_sing = 1;
-      else
-        *s_logabs += 0.5 * log(best);
-    }
-    __syncthreads();
-    const cd pv = A[p * ld + p];
-    if (cabs2(pv) != 0.0) {
-      const cd inv = cinv(pv);
-      const int w = ncols - p - 1;
-      for (int i = tid; i < (n - p - 1) * w; i += bd) {
-        const int r = p + 1 + i / w, c = p + 1 + i % w;
-        const cd fac = cmul(A[r * ld + p], inv);
-        A[r * ld + c] = csub(A[r * ld + c], cmul(fac, A[p * ld + c]));
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -779,31 +651,50 @@ static hipError_t sep_impl(const Dims& d, const Buffers& b, void* S, hipStream_t
 
 template <typename R>
 static hipError_t cov_impl(const Dims& d, const Buffers& b, void* V, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram<R>, dim3(d.F, d.S), dim3(kBlock), smem_gram<R>(d), s, d,
-                     static_cast<const cx<R>*>(b.X), static_cast<const R*>(b.W), static_cast<const R*>(b.H),
-                     static_cast<const R*>(b.g), static_cast<R*>(b.Vpart));
+  // The plan's own covariance kernel (both write the same packed slice-sum layout).
+  if (d.fast >= 0) {
+    const hipError_t e = fast_launch(d, b, sizeof(R) == 4 ? DFM_C64 : DFM_C128, kFGram, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_gram<R>, dim3(d.F, d.S), dim3(kBlock), smem_gram<R>(d), s, d,
+                       static_cast<const cx<R>*>(b.X), static_cast<const R*>(b.W), static_cast<const R*>(b.H),
+                       static_cast<const R*>(b.g), static_cast<R*>(b.Vpart));
+  }
   hipLaunchKernelGGL(k_expand<R>, dim3(cdiv((size_t)d.F * d.VF, kBlock)), dim3(kBlock), 0, s, d,
                      static_cast<const R*>(b.Vpart), static_cast<cx<R>*>(V));
   return hipGetLastError();
 }
 
 hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s) {
-  (void)d;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.status, 16);
+  const int nc = 3 * d.F + d.TBN;
+  hipLaunchKernelGGL(k_zero_int, dim3(cdiv(nc, kBlock)), dim3(kBlock), 0, s, reinterpret_cast<int*>(b.counters), nc);
   return hipGetLastError();
 }
 
 hipError_t launch_kernel(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s) {
+  if (kid >= kFGram) return fast_launch(d, b, dtype, kid, s);
   return dtype == DFM_C64 ? kernel_impl<float>(d, b, kid, s) : kernel_impl<double>(d, b, kid, s);
 }
 
 const char* kernel_name(int kid) {
-  static const char* names[kNumKernels] = {"k_gram", "k_ip", "k_pw", "k_wapply", "k_h", "k_happly", "k_g", "k_gapply"};
+  static const char* names[kNumKernels] = {"k_gram", "k_ip",   "k_pw",   "k_wapply", "k_h", "k_happly",
+                                           "k_g",    "k_gapply", "k_gram_f", "k_ip_f", "k_pw_f", "k_h_f",
+                                           "k_g_f"};
   return kid >= 0 && kid < kNumKernels ? names[kid] : nullptr;
 }
 
 // Kernels of each sub-step, in launch order.
-int stage_kernels(int stage, int* kids) {
+int stage_kernels(const Dims& d, int stage, int* kids) {
+  if (d.fast >= 0) {
+    switch (stage) {
+      case DFM_STAGE_IP: kids[0] = kFGram; kids[1] = kFIp; return 2;
+      case DFM_STAGE_W: kids[0] = kFPw; return 1;
+      case DFM_STAGE_H: kids[0] = kFH; return 1;
+      case DFM_STAGE_G: kids[0] = kFG; return 1;
+    }
+    return 0;
+  }
   switch (stage) {
     case DFM_STAGE_IP: kids[0] = kKGram; kids[1] = kKIp; return 2;
     case DFM_STAGE_W: kids[0] = kKPw; kids[1] = kKWApply; return 2;
@@ -811,6 +702,12 @@ int stage_kernels(int stage, int* kids) {
     case DFM_STAGE_G: kids[0] = kKG; kids[1] = kKGApply; return 2;
   }
   return 0;
+}
+
+int iteration_kernels(const Dims& d, int* kids) {
+  int n = 0;
+  for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G; ++stage) n += stage_kernels(d, stage, kids + n);
+  return n;
 }
 
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s) {
