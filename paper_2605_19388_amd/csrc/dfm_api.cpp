@@ -33,7 +33,7 @@ static bool choose_fast(Dims& d, int dtype) {
   int ml = d.mics[0];
   for (int l = 1; l < d.L; ++l)
     if (d.mics[l] != ml) return false;
-  const int set = fast_set_index(d.N, d.K, ml);
+  const int set = fast_set_index(d.N, d.K, ml, d.L);
   if (set < 0) return false;
   d.fast = set;
   d.ML = ml;
@@ -45,6 +45,7 @@ static bool choose_fast(Dims& d, int dtype) {
     d.TBN = (d.T + 15) / 16;
     const int hw = fast_h_waves(dtype);
     d.FG = ((d.F + 15) / 16 + hw - 1) / hw;
+    d.FS = d.FG;  // the activation apply kernel sums FS frequency-group partials
     if (fast_max_smem(d, dtype) <= 64 * 1024) return true;
   }
   d.fast = -1;

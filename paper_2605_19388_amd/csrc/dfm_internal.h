@@ -62,7 +62,8 @@ struct Buffers {
 size_t workspace_bytes(const Dims& d, int dtype);
 void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 
-// Kernels.  Generic path: eight per iteration; specialised path: five (kF*).
+// Kernels.  Generic path: eight per iteration; specialised path: five kF* plus the
+// three apply kernels of the generic path.
 enum KernelId {
   kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply,
   kFGram, kFIp, kFPw, kFH, kFG, kNumKernels
@@ -76,7 +77,7 @@ int stage_kernels(const Dims& d, int stage, int* kids);  // fills kids, returns 
 int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns count
 
 // Shape-specialised kernel sets (dfm_fast.hip).
-int fast_set_index(int N, int K, int ML);
+int fast_set_index(int N, int K, int ML, int L);
 size_t fast_max_smem(const Dims& d, int dtype);
 int fast_h_waves(int dtype);
 hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);

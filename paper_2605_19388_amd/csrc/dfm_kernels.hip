@@ -689,9 +689,9 @@ int stage_kernels(const Dims& d, int stage, int* kids) {
   if (d.fast >= 0) {
     switch (stage) {
       case DFM_STAGE_IP: kids[0] = kFGram; kids[1] = kFIp; return 2;
-      case DFM_STAGE_W: kids[0] = kFPw; return 1;
-      case DFM_STAGE_H: kids[0] = kFH; return 1;
-      case DFM_STAGE_G: kids[0] = kFG; return 1;
+      case DFM_STAGE_W: kids[0] = kFPw; kids[1] = kKWApply; return 2;
+      case DFM_STAGE_H: kids[0] = kFH; kids[1] = kKHApply; return 2;
+      case DFM_STAGE_G: kids[0] = kFG; kids[1] = kKGApply; return 2;
     }
     return 0;
   }
