@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--cpu-sample-iters", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -122,6 +124,14 @@ def main():
         return nll
 
     log(f"[bench] workload {w['name']} F={F} T={T} mics={mics} N={N} K={K} iters/step={iters}")
+    if args.copy_mb:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] calibration copy of {args.copy_mb} MiB done")
     # Per-kernel durations (outside the timed region) to find the dominant kernel.
     reset()
     p.step(2)
@@ -154,8 +164,9 @@ def main():
     log(f"[bench] {args.steps} steps in {elapsed:.4f} s (events {gpu_ms:.2f} ms); nll={nll:.6e}; "
         f"{dominant}: {dom_ms * 1e3:.1f} us avg over {dom_n} launches")
 
-    if dominant in BYTES_PER_BIN:
-        traffic_alg = BYTES_PER_BIN[dominant] * bins
+    base = dominant[:-2] if dominant.endswith("_f") else dominant   # shape-specialised variants
+    if base in BYTES_PER_BIN:
+        traffic_alg = BYTES_PER_BIN[base] * bins
         achieved = traffic_alg / (dom_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,

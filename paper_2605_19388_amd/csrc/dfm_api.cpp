@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -27,8 +28,15 @@ namespace dfm {
 static size_t real_size(int dtype) { return dtype == DFM_C64 ? 4 : 8; }
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
+// Largest frames per slice to try (tile-size tuning): DFM_SLICE in the environment, else 128.
+static int max_slice() {
+  const char* e = std::getenv("DFM_SLICE");
+  const int v = e ? std::atoi(e) : 128;
+  return v == 16 || v == 32 || v == 64 ? v : 128;
+}
+
 // Specialised path: uniform partition with a compiled (N, K, M_l) set.  Frames per slice:
-// the largest of 128, 64, 32, 16 whose LDS needs fit 64 KB in every kernel.
+// the largest of max_slice(), ..., 16 whose LDS needs fit 64 KB in every kernel.
 static bool choose_fast(Dims& d, int dtype) {
   int ml = d.mics[0];
   for (int l = 1; l < d.L; ++l)
@@ -37,15 +45,14 @@ static bool choose_fast(Dims& d, int dtype) {
   if (set < 0) return false;
   d.fast = set;
   d.ML = ml;
-  for (int sl = 128; sl >= 16; sl /= 2) {
+  for (int sl = max_slice(); sl >= 16; sl /= 2) {
     d.S = (d.T + sl - 1) / sl;
     d.SL = (d.T + d.S - 1) / d.S;
     d.SLP = ((d.SL + 3) & ~3) + 4;
     d.TB = 16;
     d.TBN = (d.T + 15) / 16;
-    const int hw = fast_h_waves(dtype);
-    d.FG = ((d.F + 15) / 16 + hw - 1) / hw;
-    d.FS = d.FG;  // the activation apply kernel sums FS frequency-group partials
+    d.FG = ((d.F + 15) / 16 + fast_h_chunks() - 1) / fast_h_chunks();
+    d.FS = d.FG;
     if (fast_max_smem(d, dtype) <= 64 * 1024) return true;
   }
   d.fast = -1;
@@ -124,6 +131,8 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   n += al(16 * d.F * d.QF);                            // Qinv
   n += al(64);                                         // status
   n += al(4 * (3 * (size_t)d.F + d.TBN));              // counters
+  n += al(d.fast >= 0 ? r * d.F * d.T * d.N : 0);      // lambda
+  n += al(d.fast >= 0 ? r * d.T * d.N * d.K : 0);      // frame-major H
   return n;
 }
 
@@ -145,6 +154,8 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   b.Qinv = take(16 * d.F * d.QF);
   b.status = reinterpret_cast<int*>(take(64));
   b.counters = reinterpret_cast<unsigned*>(take(4 * (3 * (size_t)d.F + d.TBN)));
+  b.lam = d.fast >= 0 ? take(r * d.F * d.T * d.N) : nullptr;
+  b.Ht = d.fast >= 0 ? take(r * d.T * d.N * d.K) : nullptr;
 }
 
 static hipError_t run_kernel(dfm_plan* plan, int kid, hipStream_t s) {
@@ -231,6 +242,11 @@ dfm_status dfm_init(dfm_plan** out, const dfm_problem* p, const void* X, void* Q
 dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream) {
   if (!plan || n_iter < 0) return DFM_E_ARG;
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  // The specialised kernels read a frame-major copy of H and lambda = W H, which the H
+  // update and the eq. (10) kernel then keep current; seed both from the caller's state.
+  if (n_iter > 0 && plan->d.fast >= 0 &&
+      (dfm::run_kernel(plan, dfm::kFHt, s) != hipSuccess || dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess))
+    return DFM_E_HIP;
   for (int it = 0; it < n_iter; ++it)
     for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G; ++stage)
       if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
@@ -239,7 +255,14 @@ dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream) {
 
 dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream) {
   if (!plan || stage < DFM_STAGE_IP || stage > DFM_STAGE_G) return DFM_E_ARG;
-  if (dfm::run_stage(plan, stage, static_cast<hipStream_t>(stream)) != hipSuccess) return DFM_E_HIP;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // A sub-step may follow a change of the state by the caller: refresh the frame-major H
+  // (and lambda before the covariances) that the specialised kernels read.
+  if (plan->d.fast >= 0 && stage != DFM_STAGE_H && dfm::run_kernel(plan, dfm::kFHt, s) != hipSuccess)
+    return DFM_E_HIP;
+  if (stage == DFM_STAGE_IP && plan->d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess)
+    return DFM_E_HIP;
+  if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
   return DFM_OK;
 }
 

@@ -7,13 +7,15 @@
 // are issued as one batch behind a scheduling barrier (left alone, the scheduler trades
 // them for occupancy and waits on each load in turn).
 //
-// One iteration is these five kernels plus the three small apply kernels of the generic
-// path, which sum the per-tile partials in a fixed order (so every result is
-// deterministic run to run) and update W, H and g.  Finishing the reductions inside the
+// One iteration is eight kernels: the five below, k_happly_f, and the generic W and g
+// apply kernels, which sum the per-tile partials in a fixed order (so every result is
+// deterministic run to run) and update W and g.  Finishing the reductions inside the
 // streaming kernels with a last-arriving workgroup was measured slower on gfx950: the
 // device-scope release/acquire it needs writes back and invalidates L2 in every
 // workgroup.
 //
+//   k_ht_f    frame-major copy of H (once per call; afterwards the H update keeps it).
+//   k_lam_f   lambda = W H at every frame (once per call; afterwards k_g_f refreshes it).
 //   k_gram_f  tile (f, time slice), 128 threads.  1/y per frame on the vector units,
 //             then the weighted covariances of eq. (14) as a real contraction over
 //             frames on the matrix cores (v_mfma 16x16x4: rows = mu, columns = packed
@@ -22,8 +24,9 @@
 //             larger blocks use the cooperative generic kernel).
 //   k_pw_f    tile (f, time slice), 128 threads.  P = |Q x|^2 and the per-frame sums of
 //             eq. (8); the contraction with H over frames reads H staged in LDS.
-//   k_h_f     16 bins per wave x 16 frames.  lambda = W H and the sum over frequencies
-//             of eq. (9) are both 16x16x4 matrix-core contractions.
+//   k_h_f     2 x 16 bins x 16 frames per 4-wave workgroup.  lambda = W H and the sum
+//             over frequencies of eq. (9) are both 16x16x4 matrix-core contractions.
+//   k_happly_f  H update of eq. (9) from the frequency-group partials (H and its copy).
 //   k_g_f     tile (f, time slice), 128 threads.  Sums of eq. (10).
 #include <hip/hip_runtime.h>
 
@@ -74,29 +77,63 @@ __device__ __forceinline__ void store16_nt(R* dst, const R (&src)[C]) {
   }
 }
 
-// H[n][k][t] for every (n, k) at one frame, as one batch of loads.
-template <typename R, int NK>
-__device__ __forceinline__ void load_h_column(R (&hv)[NK], const R* __restrict__ H, int T, int t) {
+// num = sum_t c[t] a[t], den = sum_t c[t] b[t] over ntp (a multiple of 4) frames of three
+// LDS rows, read four frames per access (rows are 4-element aligned).
+template <typename R>
+__device__ __forceinline__ void dot2_frames(const R* c, const R* a, const R* b, int ntp, R& num, R& den) {
+  typedef R v4r __attribute__((ext_vector_type(4)));
+  R n0 = 0, n1 = 0, d0 = 0, d1 = 0;
+  const int nb = ntp >> 2;
+  for (int q0 = 0; q0 < nb; q0 += 4) {
+    v4r cv[4], av[4], bv[4];
 #pragma unroll
-  for (int i = 0; i < NK; ++i) hv[i] = H[(size_t)i * T + t];
+    for (int u = 0; u < 4; ++u) {
+      const int q = min(q0 + u, nb - 1) * 4;  // clamped in bounds; extra blocks are zeroed below
+      cv[u] = *reinterpret_cast<const v4r*>(c + q);
+      av[u] = *reinterpret_cast<const v4r*>(a + q);
+      bv[u] = *reinterpret_cast<const v4r*>(b + q);
+      if (q0 + u >= nb) cv[u] = v4r{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      n0 += cv[u].x * av[u].x + cv[u].z * av[u].z;
+      n1 += cv[u].y * av[u].y + cv[u].w * av[u].w;
+      d0 += cv[u].x * bv[u].x + cv[u].z * bv[u].z;
+      d1 += cv[u].y * bv[u].y + cv[u].w * bv[u].w;
+    }
+  }
+  num = n0 + n1;
+  den = d0 + d1;
+}
+
+// H[n][k][t] for every (n, k) at one frame, from the frame-major copy Ht[t][n*K + k]
+// (one batch of 16-byte loads).
+template <typename R, int NK>
+__device__ __forceinline__ void load_h_column(R (&hv)[NK], const R* __restrict__ Ht, int t) {
+  load16<R, NK>(hv, Ht + (size_t)t * NK);
 }
 
 // ------------------------------------------------------------------------------------
-// FP64 IP sweep of one subarray block (M_l <= 4), eqs. (15)-(16).  Q in registers; the
-// covariance of the current row in the lane's private LDS slot sV (M_l x M_l complex).
+// FP64 IP sweep of one subarray block (M_l <= 4), eqs. (15)-(16), by one lane.  The lane's
+// Q_fl and the covariance of the current row live in LDS slots laid out element-major,
+// lane-minor (element e of lane i at e * 64 + i, so a wave's accesses are conflict-free);
+// the system A = Q V_mu is eliminated in registers.
 // vp: packed slice sums of the block, [slice (stride vstride)][mu][M_l^2]; V = sum / T.
 template <typename R, int ML>
-__device__ void ip_sweep_lane(const R* vp, size_t vstride, int S, double invT, cd (&Qm)[ML][ML], cd* sV,
-                              double eps, int* status) {
+__device__ void ip_sweep_lane(const R* vp, size_t vstride, int S, double invT, cd* q, cd* v, double eps,
+                              int* status) {
   constexpr int ML2 = ML * ML;
+#define QS(r, c) q[((r) * ML + (c)) * 64]
+#define VS(r, c) v[((r) * ML + (c)) * 64]
+#pragma unroll
   for (int mu = 0; mu < ML; ++mu) {
     double vs[ML2];
 #pragma unroll
     for (int j = 0; j < ML2; ++j) vs[j] = 0.0;
-    for (int q = 0; q < S; ++q) {
+    for (int s = 0; s < S; ++s) {
       R part[ML2];
 #pragma unroll
-      for (int j = 0; j < ML2; ++j) part[j] = vp[q * vstride + mu * ML2 + j];
+      for (int j = 0; j < ML2; ++j) part[j] = vp[s * vstride + mu * ML2 + j];
 #pragma unroll
       for (int j = 0; j < ML2; ++j) vs[j] += (double)part[j];
     }
@@ -104,15 +141,15 @@ __device__ void ip_sweep_lane(const R* vp, size_t vstride, int S, double invT, c
     for (int j = 0; j < ML2; ++j) {
       int a, b, part;
       packed_pair(ML, j, a, b, part);
-      const double v = vs[j] * invT;
+      const double val = vs[j] * invT;
       if (a == b) {
-        sV[a * ML + a] = {v, 0.0};
+        VS(a, a) = {val, 0.0};
       } else if (part == 0) {
-        sV[a * ML + b].re = v;
-        sV[b * ML + a].re = v;
+        VS(a, b).re = val;
+        VS(b, a).re = val;
       } else {
-        sV[a * ML + b].im = v;
-        sV[b * ML + a].im = -v;
+        VS(a, b).im = val;
+        VS(b, a).im = -val;
       }
     }
     cd A[ML][ML + 1];
@@ -122,7 +159,7 @@ __device__ void ip_sweep_lane(const R* vp, size_t vstride, int S, double invT, c
       for (int c = 0; c < ML; ++c) {
         cd acc = {0.0, 0.0};
 #pragma unroll
-        for (int j = 0; j < ML; ++j) acc = cadd(acc, cmul(Qm[r][j], sV[j * ML + c]));
+        for (int j = 0; j < ML; ++j) acc = cadd(acc, cmul(QS(r, j), VS(j, c)));
         A[r][c] = acc;
       }
       A[r][ML] = {r == mu ? 1.0 : 0.0, 0.0};
@@ -134,9 +171,9 @@ __device__ void ip_sweep_lane(const R* vp, size_t vstride, int S, double invT, c
       double best = cabs2(A[p][p]);
 #pragma unroll
       for (int r = p + 1; r < ML; ++r) {
-        const double v = cabs2(A[r][p]);
-        if (v > best) {
-          best = v;
+        const double val = cabs2(A[r][p]);
+        if (val > best) {
+          best = val;
           piv = r;
         }
       }
@@ -176,13 +213,15 @@ __device__ void ip_sweep_lane(const R* vp, size_t vstride, int S, double invT, c
     for (int a = 0; a < ML; ++a) {
       cd vb = {0.0, 0.0};
 #pragma unroll
-      for (int b = 0; b < ML; ++b) vb = cadd(vb, cmul(sV[a * ML + b], bsol[b]));
+      for (int b = 0; b < ML; ++b) vb = cadd(vb, cmul(VS(a, b), bsol[b]));
       sv += bsol[a].re * vb.re + bsol[a].im * vb.im;
     }
     const double sc = 1.0 / sqrt(sv > eps ? sv : eps);
 #pragma unroll
-    for (int c = 0; c < ML; ++c) Qm[mu][c] = {bsol[c].re * sc, -bsol[c].im * sc};
+    for (int c = 0; c < ML; ++c) QS(mu, c) = {bsol[c].re * sc, -bsol[c].im * sc};
   }
+#undef QS
+#undef VS
 }
 
 // ln|det| of an M_l x M_l complex matrix by elimination with partial pivoting, in registers.
@@ -226,123 +265,288 @@ __device__ double logabsdet_lane(cd (&A)[ML][ML]) {
 
 // ------------------------------------------------------------------------------------
 // Weighted covariances (eq. (14)) on the matrix cores.
+//
+// Per-frame operand rows live in LDS, frame-major, with row strides padded so that the
+// 16-byte row writes of one frame per thread are free of bank conflicts:
+//   sInv[t][m] = 1 / y_ftm, and per subarray either the packed entries of x^(l) x^(l)H
+//   (M_l <= 4, formed once per frame) or the x tile itself (larger blocks, whose
+//   M_l^2 packed reals per frame would not fit).
+// FP32 with M_l <= 4: one v_mfma_f32_4x4x1 (16 independent 4x4 blocks) per frame, block
+// b = (subarray, group of 4 packed entries), rows = mu; the frames of a slice are split
+// over the two waves and their sums combined through LDS.
+// Otherwise: v_mfma 16x16x4 per subarray and 16 packed entries, K = 4 frames.
+
+// Row stride (elements) >= n whose 16-byte row segments start in distinct bank groups.
+template <typename R>
+constexpr int padded(int n) {
+  return sizeof(R) == 4 ? n + ((4 - n % 8) + 8) % 8 : n + ((2 - n % 4) + 4) % 4;
+}
+
 template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__ X, const R* __restrict__ W,
-                                               const R* __restrict__ H, const R* __restrict__ g,
+struct GramShape {
+  static constexpr int M = ML * L, ML2 = ML * ML, OF = L * ML2;
+  static constexpr bool kPre = ML <= 4;
+  static constexpr bool kBlocks = kPre && sizeof(R) == 4;  // 4x4x1 matrix-core path
+  static constexpr int MP = padded<R>(M);
+  static constexpr int OP = kPre ? padded<R>(OF) : padded<R>(2 * M);
+  static constexpr int JG4 = (ML2 + 3) / 4;           // groups of 4 packed entries per subarray
+  static constexpr int NG = (L * JG4 + 15) / 16;      // 4x4x1 ops per frame
+};
+
+template <typename R, int N, int K, int ML, int L>
+__global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__ X,
+                                               const R* __restrict__ lamin, const R* __restrict__ g,
                                                R* __restrict__ Vpart) {
-  constexpr int M = ML * L, NK = N * K, ML2 = ML * ML;
+  typedef GramShape<R, N, K, ML, L> G;
+  constexpr int M = G::M, ML2 = G::ML2, OF = G::OF, MP = G::MP, OP = G::OP;
   constexpr int JT = (ML2 + 15) / 16;
   constexpr int E = V16<R>::E;
-  static_assert((2 * M) % E == 0 && M % E == 0, "rows must fill 16-byte vectors");
+  static_assert((2 * M) % E == 0 && M % E == 0 && OF % E == 0, "rows must fill 16-byte vectors");
+  static_assert(N * M <= kT, "g of one frequency is staged one value per thread");
   typedef typename Mma<R>::v4 v4;
   typedef typename V16<R>::type vt;
-  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int T = d.T;
+  const int f = blockIdx.x / d.S, s = blockIdx.x - f * d.S;
   const int t0 = s * d.SL;
   const int nt = min(d.SL, T - t0);
   const int ntp = (nt + 3) & ~3;
   extern __shared__ __align__(16) unsigned char smem[];
-  R* sW = reinterpret_cast<R*>(smem);
-  R* sg = sW + NK;
-  R* sInv = reinterpret_cast<R*>(smem + align_up(sizeof(R) * (NK + N * M), 16));  // [SLP][M]
-  R* sX = sInv + (size_t)d.SLP * M;                                                // [SLP][2M]
+  R* sg = reinterpret_cast<R*>(smem);
+  R* sInv = reinterpret_cast<R*>(smem + align_up(sizeof(R) * N * M, 16));  // [SLP][MP]
+  R* sOp = sInv + (size_t)d.SLP * MP;                                       // [SLP][OP]
 
-  for (int i = tid; i < NK; i += kT) sW[i] = W[((size_t)(i / K) * d.F + f) * K + i % K];
-  for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
-  {  // X tile -> LDS in 16-byte vectors, one batch of loads per thread
-    constexpr int PER = (128 * 2 * M / E + kT - 1) / kT;  // vectors per thread for a 128-frame slice
-    const vt* src = reinterpret_cast<const vt*>(X + ((size_t)f * T + t0) * M);
-    vt* dst = reinterpret_cast<vt*>(sX);
-    const int nv = nt * 2 * M / E, nvp = ntp * 2 * M / E;
-    for (int base = 0; base < nvp; base += PER * kT) {
-      vt buf[PER];
+  // One batch of loads: x and lambda at this thread's frame, one value of g.
+  R xv[2 * M], lam[N], gv = 0;
+  if (tid < nt) {
+    load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + tid) * M));
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int i = base + tid + u * kT;
-        buf[u] = i < nv ? src[i] : vt{};
-      }
-      sched_fence();
+    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * T + t0 + tid) * N + n];
+  } else {  // padding frames contribute zero products
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int i = base + tid + u * kT;
-        if (i < nvp) dst[i] = buf[u];
-      }
-    }
+    for (int i = 0; i < 2 * M; ++i) xv[i] = 0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[n] = 0;
   }
+  if (tid < N * M) gv = g[(size_t)f * N * M + tid];
+  sched_fence();
+  if (tid < N * M) sg[tid] = gv;
   __syncthreads();
-
-  for (int tl = tid; tl < ntp; tl += kT) {
-    R inv[M];
-    if (tl < nt) {
-      R hv[NK];
-      load_h_column<R, NK>(hv, H, T, t0 + tl);
-      sched_fence();
-      R lam[N];
-#pragma unroll
-      for (int n = 0; n < N; ++n) {
-        R acc = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc += sW[n * K + k] * hv[n * K + k];
-        lam[n] = acc;
-      }
+  {
+    const int tl = tid;  // one frame per thread (slices hold at most kT frames)
+    if (tl < ntp) {
+      R inv[M];
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         R y = 0;
 #pragma unroll
         for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
-        inv[m] = rcp(rmax(y, (R)d.eps));
+        inv[m] = tl < nt ? rcp(rmax(y, (R)d.eps)) : (R)0;
       }
-    } else {
 #pragma unroll
-      for (int m = 0; m < M; ++m) inv[m] = 0;
-    }
+      for (int i = 0; i < M / E; ++i) {
+        vt v;
 #pragma unroll
-    for (int i = 0; i < M / E; ++i) {
-      vt v;
+        for (int e = 0; e < E; ++e) v[e] = inv[i * E + e];
+        reinterpret_cast<vt*>(sInv + (size_t)tl * MP)[i] = v;
+      }
+      if constexpr (G::kPre) {
+        R op[OF];
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = inv[i * E + e];
-      reinterpret_cast<vt*>(sInv + (size_t)tl * M)[i] = v;
+        for (int l = 0; l < L; ++l)
+#pragma unroll
+          for (int j = 0; j < ML2; ++j) {
+            int a, b, part;
+            packed_pair(ML, j, a, b, part);
+            const R ar = xv[2 * (l * ML + a)], ai = xv[2 * (l * ML + a) + 1];
+            const R br = xv[2 * (l * ML + b)], bi = xv[2 * (l * ML + b) + 1];
+            op[l * ML2 + j] = part == 0 ? ar * br + ai * bi : ai * br - ar * bi;
+          }
+#pragma unroll
+        for (int i = 0; i < OF / E; ++i) {
+          vt v;
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e] = op[i * E + e];
+          reinterpret_cast<vt*>(sOp + (size_t)tl * OP)[i] = v;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 2 * M / E; ++i) {
+          vt v;
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e] = xv[i * E + e];
+          reinterpret_cast<vt*>(sOp + (size_t)tl * OP)[i] = v;
+        }
+      }
     }
   }
   __syncthreads();
 
-  // C[mu][j] += sum over 4 frames of (1/y)[frame][mu] * O[frame][j], O = packed x x^H;
-  // two accumulators alternate so consecutive matrix-core ops are independent.
-  const int col = lane & 15, kk = lane >> 4;
-  const cx<R>* sXc = reinterpret_cast<const cx<R>*>(sX);
-  for (int item = wave; item < L * JT; item += kT / 64) {
-    const int l = item / JT, jt = item - l * JT;
-    const int o = l * ML;
-    const int j = jt * 16 + col;
-    const bool jv = j < ML2;
-    int a = 0, b = 0, part = 0;
-    if (jv) packed_pair(ML, j, a, b, part);
-    const bool rv = col < ML;
-    v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    for (int step = 0; step < ntp; step += 8) {
+  if constexpr (G::kBlocks) {
+    // Lane i, op group q: block b = 16 q + i / 4 = (subarray l, entry group jg); A row
+    // (mu) and B column (entry) = i % 4.  Frames of the slice alternate between waves.
+    constexpr int JG4 = G::JG4, NG = G::NG;
+    const int sub = lane & 3;
+    v4 acc[NG];
+    int aoff[NG], boff[NG];
+    bool av_ok[NG], bv_ok[NG];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int tl = step + 4 * h + kk;
-        R av = 0, bv = 0;
-        if (tl < ntp) {
-          av = rv ? sInv[tl * M + o + col] : (R)0;
-          if (jv) {
-            const cx<R> xa = sXc[tl * M + o + a], xb = sXc[tl * M + o + b];
-            bv = part == 0 ? xa.re * xb.re + xa.im * xb.im : xa.im * xb.re - xa.re * xb.im;
-          }
+    for (int q = 0; q < NG; ++q) {
+      acc[q] = v4{0, 0, 0, 0};
+      const int b = 16 * q + (lane >> 2), l = b / JG4, jg = b - l * JG4, j = 4 * jg + sub;
+      av_ok[q] = l < L && sub < ML;
+      bv_ok[q] = l < L && j < ML2;
+      aoff[q] = av_ok[q] ? l * ML + sub : 0;
+      boff[q] = bv_ok[q] ? l * ML2 + j : 0;
+    }
+    const int half = ((ntp >> 1) + 3) & ~3;  // frames of wave 0; wave 1 takes the rest
+    const int fb = wave == 0 ? 0 : half, fe = wave == 0 ? min(half, ntp) : ntp;
+    for (int t4 = fb; t4 < fe; t4 += 4) {
+      R av[4][NG], bv[4][NG];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+          const R a = sInv[(t4 + u) * MP + aoff[q]], b = sOp[(t4 + u) * OP + boff[q]];
+          av[u][q] = av_ok[q] ? a : (R)0;
+          bv[u][q] = bv_ok[q] ? b : (R)0;
         }
-        if (h == 0)
-          acc0 = Mma<R>::run(av, bv, acc0);
-        else
-          acc1 = Mma<R>::run(av, bv, acc1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
+    }
+    // Combine the two waves (LDS area of sInv is free now) and store the slice sums.
+    __syncthreads();
+    R* sRed = sInv;  // [NG][64][4]
+    if (wave == 1)
+#pragma unroll
+      for (int q = 0; q < NG; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sRed[(q * 64 + lane) * 4 + r] = acc[q][r];
+    __syncthreads();
+    if (wave == 0) {
+      R* out = Vpart + ((size_t)f * d.S + s) * d.VF;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const int b = 16 * q + (lane >> 2), l = b / JG4, jg = b - l * JG4, j = 4 * jg + sub;
+        if (l < L && j < ML2)
+#pragma unroll
+          for (int r = 0; r < ML; ++r)
+            out[(size_t)l * ML * ML2 + r * ML2 + j] = acc[q][r] + sRed[(q * 64 + lane) * 4 + r];
       }
     }
-    R* out = Vpart + ((size_t)f * d.S + s) * d.VF + (size_t)l * ML * ML2;
+  } else {
+    // C[mu][j] += sum over 4 frames of (1/y)[frame][mu] * O[frame][j] per (subarray, 16
+    // packed entries); four steps of operand loads ahead of their matrix-core ops.
+    const int col = lane & 15, kk = lane >> 4;
+    for (int item = wave; item < L * JT; item += kT / 64) {
+      const int l = item / JT, jt = item - l * JT;
+      const int o = l * ML;
+      const int j = jt * 16 + col;
+      const bool jv = j < ML2;
+      const bool rv = col < ML;
+      v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+      const int nsteps = ntp >> 2;
+      int a = 0, b = 0, part = 0;
+      if (jv) packed_pair(ML, j, a, b, part);
+      const R* ip = sInv + (size_t)kk * MP + o + (rv ? col : 0);
+      for (int q0 = 0; q0 < nsteps; q0 += 4) {
+        R av[4], bv[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int mu = Mma<R>::row(lane, r);
-      if (mu < ML && jv) out[mu * ML2 + j] = acc0[r] + acc1[r];
+        for (int u = 0; u < 4; ++u) {
+          const int q = min(q0 + u, nsteps - 1);
+          const int tq = 4 * q + kk;
+          const R ai = ip[(size_t)q * 4 * MP];
+          R bo;
+          if constexpr (G::kPre) {
+            bo = sOp[(size_t)tq * OP + l * ML2 + (jv ? j : 0)];
+          } else {
+            const R* xr = sOp + (size_t)tq * OP;
+            const R xar = xr[2 * (o + a)], xai = xr[2 * (o + a) + 1];
+            const R xbr = xr[2 * (o + b)], xbi = xr[2 * (o + b) + 1];
+            bo = part == 0 ? xar * xbr + xai * xbi : xai * xbr - xar * xbi;
+          }
+          const bool ok = q0 + u < nsteps;
+          av[u] = (ok && rv) ? ai : (R)0;
+          bv[u] = (ok && jv) ? bo : (R)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u += 2) {
+          acc0 = Mma<R>::run(av[u], bv[u], acc0);
+          acc1 = Mma<R>::run(av[u + 1], bv[u + 1], acc1);
+        }
+      }
+      R* out = Vpart + ((size_t)f * d.S + s) * d.VF + (size_t)l * ML * ML2;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mu = Mma<R>::row(lane, r);
+        if (mu < ML && jv) out[mu * ML2 + j] = acc0[r] + acc1[r];
+      }
     }
+  }
+}
+
+// Frame-major copy of the activations: Ht[t][n*K + k] = H[n][k][t].
+template <typename R, int NK>
+__global__ __launch_bounds__(kT) void k_ht_f(Dims d, const R* __restrict__ H, R* __restrict__ Ht) {
+  const int t = blockIdx.x * kT + threadIdx.x;
+  if (t >= d.T) return;
+  R hv[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) hv[i] = H[(size_t)i * d.T + t];
+  sched_fence();
+  constexpr int E = V16<R>::E;
+#pragma unroll
+  for (int i = 0; i < NK / E; ++i) {
+    typename V16<R>::type v;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = hv[i * E + e];
+    reinterpret_cast<typename V16<R>::type*>(Ht + (size_t)t * NK)[i] = v;
+  }
+}
+
+// Activation update, eq. (9): H <- H sqrt(num / max(den, eps)) with num, den summed over
+// the frequency-group partials in order; writes H and its frame-major copy.
+template <typename R, int NK>
+__global__ __launch_bounds__(256) void k_happly_f(Dims d, R* __restrict__ H, R* __restrict__ Ht,
+                                                  const R* __restrict__ Hpart, int* __restrict__ status) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= NK * d.T) return;
+  const int nk = idx / d.T, t = idx - nk * d.T;
+  R num = 0, den = 0;
+  for (int q = 0; q < d.FG; ++q) {
+    const R* pp = Hpart + (((size_t)q * NK + nk) * d.T + t) * 2;
+    num += pp[0];
+    den += pp[1];
+  }
+  const R v = H[idx] * sqrt(num / rmax(den, (R)d.eps));
+  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  H[idx] = v;
+  Ht[(size_t)t * NK + nk] = v;
+}
+
+// lambda[f][t][n] = sum_k W[n][f][k] H[n][k][t] (eq. (2)) for every frame of a tile.
+template <typename R, int N, int K>
+__global__ __launch_bounds__(kT) void k_lam_f(Dims d, const R* __restrict__ W, const R* __restrict__ Ht,
+                                              R* __restrict__ lamout) {
+  constexpr int NK = N * K;
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int t0 = s * d.SL;
+  const int nt = min(d.SL, d.T - t0);
+  __shared__ R sW[NK];
+  for (int i = tid; i < NK; i += kT) sW[i] = W[((size_t)(i / K) * d.F + f) * K + i % K];
+  __syncthreads();
+  if (tid >= nt) return;
+  R hv[NK];
+  load_h_column<R, NK>(hv, Ht, t0 + tid);
+  sched_fence();
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    R acc = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc += sW[n * K + k] * hv[n * K + k];
+    lamout[((size_t)f * d.T + t0 + tid) * N + n] = acc;
   }
 }
 
@@ -352,34 +556,40 @@ template <typename R, int ML>
 __global__ __launch_bounds__(64) void k_ip_f(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict__ Q,
                                              double* __restrict__ logdet, int* __restrict__ status) {
   constexpr int ML2 = ML * ML;
-  __shared__ cd sV[64 * ML2];
+  __shared__ cd sQ[ML2 * 64];
+  __shared__ cd sV[ML2 * 64];
   const int idx = blockIdx.x * 64 + threadIdx.x;
   if (idx >= d.F * d.L) return;
   const int f = idx / d.L, l = idx - f * d.L;
+  cd* q = sQ + threadIdx.x;
   cx<R>* qb = Q + (size_t)f * d.QF + l * ML2;
-  cd Qm[ML][ML];
+  {
+    cx<R> qv[ML2];
 #pragma unroll
-  for (int r = 0; r < ML; ++r)
+    for (int e = 0; e < ML2; ++e) qv[e] = qb[e];
 #pragma unroll
-    for (int c = 0; c < ML; ++c) Qm[r][c] = {(double)qb[r * ML + c].re, (double)qb[r * ML + c].im};
-  ip_sweep_lane<R, ML>(Vpart + (size_t)f * d.S * d.VF + (size_t)l * ML * ML2, d.VF, d.S, 1.0 / d.T, Qm,
-                       sV + threadIdx.x * ML2, d.eps, status);
+    for (int e = 0; e < ML2; ++e) q[e * 64] = {(double)qv[e].re, (double)qv[e].im};
+  }
+  ip_sweep_lane<R, ML>(Vpart + (size_t)f * d.S * d.VF + (size_t)l * ML * ML2, d.VF, d.S, 1.0 / d.T, q,
+                       sV + threadIdx.x, d.eps, status);
+  cd A[ML][ML];
 #pragma unroll
   for (int r = 0; r < ML; ++r)
 #pragma unroll
     for (int c = 0; c < ML; ++c) {
-      const cx<R> q = {(R)Qm[r][c].re, (R)Qm[r][c].im};
-      qb[r * ML + c] = q;
-      Qm[r][c] = {(double)q.re, (double)q.im};
+      const cd qq = q[(r * ML + c) * 64];
+      const cx<R> o = {(R)qq.re, (R)qq.im};
+      qb[r * ML + c] = o;
+      A[r][c] = {(double)o.re, (double)o.im};
     }
-  logdet[idx] = logabsdet_lane<ML>(Qm);
+  logdet[idx] = logabsdet_lane<ML>(A);
 }
 
 // ------------------------------------------------------------------------------------
 // P = |Q x|^2 and the eq. (8) sums per (f, slice).
 template <typename R, int N, int K, int ML, int L>
 __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
-                                             const R* __restrict__ W, const R* __restrict__ H, const R* __restrict__ g,
+                                             const R* __restrict__ W, const R* __restrict__ Ht, const R* __restrict__ g,
                                              R* __restrict__ P, R* __restrict__ Wpart) {
   constexpr int M = ML * L, NK = N * K, ML2 = ML * ML, QF = L * ML2;
   const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
@@ -389,9 +599,9 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
   const int ntp = (nt + 3) & ~3;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<R>* sQ = reinterpret_cast<cx<R>*>(smem);
-  R* sW = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 16));
+  R* sW = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 32));
   R* sg = sW + NK;
-  R* sH = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 16) + align_up(sizeof(R) * (NK + N * M), 16));
+  R* sH = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 32) + align_up(sizeof(R) * (NK + N * M), 32));
   R* sab = sH + (size_t)NK * SLP;  // [2N][SLP]
 
   for (int i = tid; i < QF; i += kT) sQ[i] = Q[(size_t)f * QF + i];
@@ -403,7 +613,7 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
     if (tl < nt) {
       const int t = t0 + tl;
       R hv[NK], xv[2 * M];
-      load_h_column<R, NK>(hv, H, T, t);
+      load_h_column<R, NK>(hv, Ht, t);
       load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t) * M));
       sched_fence();
       R lam[N];
@@ -471,182 +681,178 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
     const R* hr = sH + o * SLP;
     const R* ar = sab + n * SLP;
     const R* br = sab + (N + n) * SLP;
-    R num0 = 0, den0 = 0, num1 = 0, den1 = 0;
-    for (int tl = 0; tl < ntp; tl += 4) {
-      num0 += hr[tl] * ar[tl] + hr[tl + 2] * ar[tl + 2];
-      den0 += hr[tl] * br[tl] + hr[tl + 2] * br[tl + 2];
-      num1 += hr[tl + 1] * ar[tl + 1] + hr[tl + 3] * ar[tl + 3];
-      den1 += hr[tl + 1] * br[tl + 1] + hr[tl + 3] * br[tl + 3];
-    }
-    out[o * 2 + 0] = num0 + num1;
-    out[o * 2 + 1] = den0 + den1;
+    R num, den;
+    dot2_frames<R>(hr, ar, br, ntp, num, den);
+    out[o * 2 + 0] = num;
+    out[o * 2 + 1] = den;
   }
 
 }
 
 // ------------------------------------------------------------------------------------
-// Activation update, eq. (9).  Workgroup = HW waves; wave w owns 16 bins, all waves share
-// one block of 16 frames.
-template <typename R>
-constexpr int h_waves() { return sizeof(R) == 4 ? 4 : 2; }
+// Activation update sums, eq. (9).  A workgroup of 4 waves covers kHCPW chunks of 16 bins
+// for one block of 16 frames.  Per chunk: lambda = W H by the matrix cores (each wave
+// holds the 16 x 16 tile in the accumulator layout); wave w then computes a' and b' of
+// eq. (9) for the (f, t) pair in accumulator row w of every lane (one pair per lane);
+// finally the sums over the chunk's bins, num/den[n][k][t] = sum_f W[n][f][k] (a', b'),
+// run on the matrix cores with the sources split across the waves.
+constexpr int kHCPW = 2;  // 16-bin chunks per activation workgroup
 
 template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(64 * h_waves<R>()) void k_h_f(Dims d, const R* __restrict__ W, const R* __restrict__ H,
-                                                           const R* __restrict__ g, const R* __restrict__ P,
-                                                           R* __restrict__ Hpart) {
-  constexpr int HW = h_waves<R>();
-  constexpr int NT = 64 * HW;
+__global__ __launch_bounds__(256) void k_h_f(Dims d, const R* __restrict__ W, const R* __restrict__ H,
+                                             const R* __restrict__ g, const R* __restrict__ P,
+                                             R* __restrict__ Hpart) {
   constexpr int M = ML * L, NK = N * K;
   constexpr int KS = (K + 3) / 4;    // 4-deep steps over bases for lambda = W H
-  constexpr int KT = (K + 15) / 16;  // 16-row tiles of bases for the sum over frequencies
+  constexpr int KT = (K + 15) / 16;  // 16-row tiles of bases for the sum over bins
+  constexpr int NW = (N + 3) / 4;    // sources per wave in the sum over bins
   typedef typename Mma<R>::v4 v4;
   const int fg = blockIdx.x, tb = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int T = d.T, F = d.F;
   const int t0 = tb * kHTB;
   const int ntb = min(kHTB, T - t0);
-  const int f0 = (fg * HW + wave) * 16;
-  const int nf = max(0, min(16, F - f0));
-  extern __shared__ __align__(16) unsigned char smem[];
-  R* sHt = reinterpret_cast<R*>(smem);                            // [NK][16]
-  R* sgc = sHt + NK * kHTB + wave * (16 * N * M);                // per wave [16 f][N*M]
-  R* sAB = sHt + NK * kHTB + HW * 16 * N * M + wave * (2 * 256); // per wave [2][16 f][16 t]
-
   const int cl = lane & 15, ck = lane >> 4;
-  // Matrix-core A operands (W) of both contractions, as one batch of loads.
-  R wl[N][KS], wh[N][KT][4];
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-#pragma unroll
-    for (int st = 0; st < KS; ++st) {
-      const int k = 4 * st + ck;
-      wl[n][st] = (k < K && cl < nf) ? W[((size_t)n * F + f0 + cl) * K + k] : (R)0;
-    }
-#pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int fl = 4 * st + ck, k = kt * 16 + cl;
-        wh[n][kt][st] = (k < K && fl < nf) ? W[((size_t)n * F + f0 + fl) * K + k] : (R)0;
-      }
-  }
-  for (int i = tid; i < NK * kHTB; i += NT) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* sHt = reinterpret_cast<R*>(smem);  // [NK][16]
+  R* sgc = sHt + NK * kHTB;             // [16 f][N*M]
+  R* sAB = sgc + 16 * N * M;            // [N][2][16 f][16 t]
+
+  for (int i = tid; i < NK * kHTB; i += 256) {
     const int nk = i / kHTB, tl = i % kHTB;
     sHt[i] = tl < ntb ? H[(size_t)nk * T + t0 + tl] : (R)0;
   }
-  for (int i = lane; i < 16 * N * M; i += 64) {
-    const int fl = i / (N * M);
-    sgc[i] = fl < nf ? g[(size_t)(f0 + fl) * N * M + i % (N * M)] : (R)0;
-  }
-  __syncthreads();
-
-  // lambda_n[f][t] = sum_k W[n][f][k] H[n][k][t]: A = W (rows f), B = H (columns t).
-  R lam[N][4];
+  v4 accN[NW][KT], accD[NW][KT];
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
-    v4 acc = {0, 0, 0, 0};
-#pragma unroll
-    for (int st = 0; st < KS; ++st) {
-      const int k = 4 * st + ck;
-      const R bv = k < K ? sHt[(n * K + k) * kHTB + cl] : (R)0;
-      acc = Mma<R>::run(wl[n][st], bv, acc);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) lam[n][r] = acc[r];
-  }
-  // a' and b' of eq. (9) for the four (f, t) pairs this lane holds (column t = cl).
-  R pv[4][M];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int fl = Mma<R>::row(lane, r);
-    if (fl < nf && cl < ntb) {
-      load16<R, M>(pv[r], P + ((size_t)(f0 + fl) * T + t0 + cl) * M);
-    } else {
-#pragma unroll
-      for (int m = 0; m < M; ++m) pv[r][m] = 0;
-    }
-  }
-  sched_fence();
-  R a[N][4], b[N][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int fl = Mma<R>::row(lane, r);
-    const R* gf = sgc + fl * N * M;
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-      a[n][r] = 0;
-      b[n][r] = 0;
-    }
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      R y = 0;
-#pragma unroll
-      for (int n = 0; n < N; ++n) y += lam[n][r] * gf[n * M + m];
-      const R iy = rcp(rmax(y, (R)d.eps));
-      const R piy2 = pv[r][m] * iy * iy;
-#pragma unroll
-      for (int n = 0; n < N; ++n) {
-        a[n][r] += gf[n * M + m] * piy2;
-        b[n][r] += gf[n * M + m] * iy;
-      }
-    }
-  }
-  // num/den[n][k][t] = sum_f W[n][f][k] (a', b')[n][f][t]: A = W^T (rows k), B = a'/b' (columns t).
-  v4 accN[N][KT], accD[N][KT];
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int fl = Mma<R>::row(lane, r);
-      sAB[fl * 16 + cl] = a[n][r];
-      sAB[256 + fl * 16 + cl] = b[n][r];
-    }
-    __syncthreads();
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
-      accN[n][kt] = v4{0, 0, 0, 0};
-      accD[n][kt] = v4{0, 0, 0, 0};
+      accN[i][kt] = v4{0, 0, 0, 0};
+      accD[i][kt] = v4{0, 0, 0, 0};
+    }
+
+  for (int c = 0; c < kHCPW; ++c) {
+    const int f0 = (fg * kHCPW + c) * 16;
+    const int nf = min(16, F - f0);
+    if (nf <= 0) break;  // uniform over the workgroup
+    // One batch: W operands of both contractions, g of the chunk, P of this lane's pair.
+    R wl[N][KS], wh[NW][KT][4], pv[M];
 #pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int fl = 4 * st + ck;
-        accN[n][kt] = Mma<R>::run(wh[n][kt][st], sAB[fl * 16 + cl], accN[n][kt]);
-        accD[n][kt] = Mma<R>::run(wh[n][kt][st], sAB[256 + fl * 16 + cl], accD[n][kt]);
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+      for (int st = 0; st < KS; ++st) {
+        const int k = 4 * st + ck;
+        wl[n][st] = (k < K && cl < nf) ? W[((size_t)n * F + f0 + cl) * K + k] : (R)0;
+      }
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int n = wave + 4 * i, fl = 4 * st + ck, k = kt * 16 + cl;
+          wh[i][kt][st] = (n < N && k < K && fl < nf) ? W[((size_t)n * F + f0 + fl) * K + k] : (R)0;
+        }
+    const int fl = Mma<R>::row(lane, wave);
+    const bool pair_ok = fl < nf && cl < ntb;
+    if (pair_ok) {
+      load16<R, M>(pv, P + ((size_t)(f0 + fl) * T + t0 + cl) * M);
+    } else {
+#pragma unroll
+      for (int m = 0; m < M; ++m) pv[m] = 0;
+    }
+    for (int i = tid; i < 16 * N * M; i += 256) {
+      const int fi = i / (N * M);
+      sgc[i] = fi < nf ? g[(size_t)(f0 + fi) * N * M + i % (N * M)] : (R)0;
+    }
+    sched_fence();
+    __syncthreads();  // sHt (first chunk), sgc
+    // lambda for the lane's pair (accumulator row `wave`).
+    R lam[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      v4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int st = 0; st < KS; ++st) {
+        const int k = 4 * st + ck;
+        const R bv = k < K ? sHt[(n * K + k) * kHTB + cl] : (R)0;
+        acc = Mma<R>::run(wl[n][st], bv, acc);
+      }
+      lam[n] = acc[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r)
+        if (wave == r) lam[n] = acc[r];
+    }
+    R a[N], b[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      a[n] = 0;
+      b[n] = 0;
+    }
+    if (pair_ok) {
+      const R* gf = sgc + fl * N * M;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        R y = 0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) y += lam[n] * gf[n * M + m];
+        const R iy = rcp(rmax(y, (R)d.eps));
+        const R piy2 = pv[m] * iy * iy;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+          a[n] += gf[n * M + m] * piy2;
+          b[n] += gf[n * M + m] * iy;
+        }
       }
     }
-    __syncthreads();
-  }
-  // Sum the waves in order through LDS, then write this frequency group's partial.
-  R* sRed = reinterpret_cast<R*>(smem);  // [N][KT*16][16][2]
-  for (int w = 0; w < HW; ++w) {
-    if (wave == w) {
 #pragma unroll
-      for (int n = 0; n < N; ++n)
+    for (int n = 0; n < N; ++n) {
+      sAB[((n * 2 + 0) * 16 + fl) * 16 + cl] = a[n];
+      sAB[((n * 2 + 1) * 16 + fl) * 16 + cl] = b[n];
+    }
+    __syncthreads();
+    // num/den for this wave's sources: A = W^T (rows k), B = a'/b' (columns t).
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const int n = wave + 4 * i;
+      if (n < N) {
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int k = kt * 16 + Mma<R>::row(lane, r);
-            R* dst = sRed + ((n * KT * 16 + k) * 16 + cl) * 2;
-            dst[0] = (w == 0 ? (R)0 : dst[0]) + accN[n][kt][r];
-            dst[1] = (w == 0 ? (R)0 : dst[1]) + accD[n][kt][r];
+          for (int st = 0; st < 4; ++st) {
+            const int fb = 4 * st + ck;
+            accN[i][kt] = Mma<R>::run(wh[i][kt][st], sAB[((n * 2 + 0) * 16 + fb) * 16 + cl], accN[i][kt]);
+            accD[i][kt] = Mma<R>::run(wh[i][kt][st], sAB[((n * 2 + 1) * 16 + fb) * 16 + cl], accD[i][kt]);
           }
+      }
     }
-    __syncthreads();
+    __syncthreads();  // before the next chunk overwrites sgc / sAB
   }
-  for (int i = tid; i < NK * ntb * 2; i += NT) {
-    const int w = i & 1, rest = i >> 1;
-    const int tl = rest % ntb, nk = rest / ntb;
-    const int n = nk / K, k = nk % K;
-    Hpart[(((size_t)fg * NK + nk) * T + t0 + tl) * 2 + w] = sRed[((n * KT * 16 + k) * 16 + tl) * 2 + w];
+  // This workgroup's partial for its frequency group: lane holds rows k = row(lane, r).
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int n = wave + 4 * i;
+    if (n >= N || cl >= ntb) continue;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = kt * 16 + Mma<R>::row(lane, r);
+        if (k < K) {
+          R* dst = Hpart + (((size_t)fg * NK + n * K + k) * T + t0 + cl) * 2;
+          dst[0] = accN[i][kt][r];
+          dst[1] = accD[i][kt][r];
+        }
+      }
   }
-
 }
 
 // ------------------------------------------------------------------------------------
-// Eq. (10) sums per (f, slice).
+// Eq. (10) sums per (f, slice).  lambda = W H at every frame is also stored: W and H
+// do not change again in this iteration, so the next covariance kernel reads it.
 template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ W, const R* __restrict__ H,
+__global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ W, const R* __restrict__ Ht,
                                             const R* __restrict__ g, const R* __restrict__ P,
-                                            R* __restrict__ gpart) {
+                                            R* __restrict__ gpart, R* __restrict__ lamout) {
   constexpr int M = ML * L, NK = N * K;
   const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
   const int T = d.T, SLP = d.SLP;
@@ -656,8 +862,8 @@ __global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ W, con
   extern __shared__ __align__(16) unsigned char smem[];
   R* sW = reinterpret_cast<R*>(smem);
   R* sg = sW + NK;
-  R* sLam = sg + N * M;    // [N][SLP]
-  R* sR = sLam + N * SLP;  // [2M][SLP]
+  R* sLam = reinterpret_cast<R*>(smem + align_up(sizeof(R) * (NK + N * M), 32));  // [N][SLP]
+  R* sR = sLam + N * SLP;                                                         // [2M][SLP]
 
   for (int i = tid; i < NK; i += kT) sW[i] = W[((size_t)(i / K) * d.F + f) * K + i % K];
   for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
@@ -667,7 +873,7 @@ __global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ W, con
     if (tl < nt) {
       const int t = t0 + tl;
       R hv[NK], pv[M];
-      load_h_column<R, NK>(hv, H, T, t);
+      load_h_column<R, NK>(hv, Ht, t);
       load16<R, M>(pv, P + ((size_t)f * T + t) * M);
       sched_fence();
       R lam[N];
@@ -678,6 +884,7 @@ __global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ W, con
         for (int k = 0; k < K; ++k) acc += sW[n * K + k] * hv[n * K + k];
         lam[n] = acc;
         sLam[n * SLP + tl] = acc;
+        lamout[((size_t)f * T + t) * N + n] = acc;
       }
 #pragma unroll
       for (int m = 0; m < M; ++m) {
@@ -703,15 +910,10 @@ __global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ W, con
     const R* lr = sLam + n * SLP;
     const R* r1 = sR + m * SLP;
     const R* r2 = sR + (M + m) * SLP;
-    R num0 = 0, den0 = 0, num1 = 0, den1 = 0;
-    for (int tl = 0; tl < ntp; tl += 4) {
-      num0 += lr[tl] * r1[tl] + lr[tl + 2] * r1[tl + 2];
-      den0 += lr[tl] * r2[tl] + lr[tl + 2] * r2[tl + 2];
-      num1 += lr[tl + 1] * r1[tl + 1] + lr[tl + 3] * r1[tl + 3];
-      den1 += lr[tl + 1] * r2[tl + 1] + lr[tl + 3] * r2[tl + 3];
-    }
-    out[o * 2 + 0] = num0 + num1;
-    out[o * 2 + 1] = den0 + den1;
+    R num, den;
+    dot2_frames<R>(lr, r1, r2, ntp, num, den);
+    out[o * 2 + 0] = num;
+    out[o * 2 + 1] = den;
   }
 
 }
@@ -722,20 +924,19 @@ template <typename R, int N, int K, int ML, int L>
 struct Set {
   static constexpr int M = ML * L;
   static size_t smem_gram(const Dims& d) {
-    return align_up(sizeof(R) * (N * K + N * M), 16) + sizeof(R) * d.SLP * 3 * M;
+    typedef GramShape<R, N, K, ML, L> G;
+    const size_t rows = (size_t)d.SLP * (G::MP + G::OP);
+    const size_t red = G::kBlocks ? (size_t)G::NG * 64 * 4 : 0;  // cross-wave sums reuse the rows
+    return align_up(sizeof(R) * N * M, 16) + sizeof(R) * (rows > red ? rows : red);
   }
   static size_t smem_pw(const Dims& d) {
-    return align_up(sizeof(cx<R>) * L * ML * ML, 16) + align_up(sizeof(R) * (N * K + N * M), 16) +
+    return align_up(sizeof(cx<R>) * L * ML * ML, 32) + align_up(sizeof(R) * (N * K + N * M), 32) +
            sizeof(R) * (N * K + 2 * N) * d.SLP;
   }
-  static size_t smem_h(const Dims&) {
-    constexpr int KT = (K + 15) / 16;
-    constexpr int HW = h_waves<R>();
-    const size_t stage = sizeof(R) * (N * K * kHTB + HW * 16 * N * M + HW * 2 * 256);
-    const size_t red = sizeof(R) * N * KT * 16 * 16 * 2;
-    return stage > red ? stage : red;
+  static size_t smem_h(const Dims&) { return sizeof(R) * (N * K * kHTB + 16 * N * M + N * 2 * 256); }
+  static size_t smem_g(const Dims& d) {
+    return align_up(sizeof(R) * (N * K + N * M), 32) + sizeof(R) * (N + 2 * M) * d.SLP;
   }
-  static size_t smem_g(const Dims& d) { return sizeof(R) * (N * K + N * M + (N + 2 * M) * d.SLP); }
   static size_t max_smem(const Dims& d) {
     size_t m = smem_gram(d);
     m = smem_pw(d) > m ? smem_pw(d) : m;
@@ -751,9 +952,21 @@ struct Set {
     R* H = static_cast<R*>(b.H);
     R* P = static_cast<R*>(b.P);
     switch (kid) {
+      case kFHt:
+        hipLaunchKernelGGL((k_ht_f<R, N * K>), dim3((d.T + kT - 1) / kT), dim3(kT), 0, s, d, H,
+                           static_cast<R*>(b.Ht));
+        break;
+      case kFHApply:
+        hipLaunchKernelGGL((k_happly_f<R, N * K>), dim3((N * K * d.T + 255) / 256), dim3(256), 0, s, d, H,
+                           static_cast<R*>(b.Ht), static_cast<const R*>(b.Hpart), b.status);
+        break;
+      case kFLam:
+        hipLaunchKernelGGL((k_lam_f<R, N, K>), dim3(d.F, d.S), dim3(kT), 0, s, d, W,
+                           static_cast<const R*>(b.Ht), static_cast<R*>(b.lam));
+        break;
       case kFGram:
-        hipLaunchKernelGGL((k_gram_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_gram(d), s, d, X, W, H, g,
-                           static_cast<R*>(b.Vpart));
+        hipLaunchKernelGGL((k_gram_f<R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d, X,
+                           static_cast<const R*>(b.lam), g, static_cast<R*>(b.Vpart));
         break;
       case kFIp:
         if constexpr (ML <= 4) {
@@ -764,16 +977,16 @@ struct Set {
         }
         break;
       case kFPw:
-        hipLaunchKernelGGL((k_pw_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_pw(d), s, d, X, Q, W, H, g,
-                           P, static_cast<R*>(b.Wpart));
+        hipLaunchKernelGGL((k_pw_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_pw(d), s, d, X, Q, W,
+                           static_cast<const R*>(b.Ht), g, P, static_cast<R*>(b.Wpart));
         break;
       case kFH:
-        hipLaunchKernelGGL((k_h_f<R, N, K, ML, L>), dim3(d.FG, d.TBN), dim3(64 * h_waves<R>()), smem_h(d), s, d,
-                           W, H, g, P, static_cast<R*>(b.Hpart));
+        hipLaunchKernelGGL((k_h_f<R, N, K, ML, L>), dim3(d.FG, d.TBN), dim3(256), smem_h(d), s, d, W, H, g, P,
+                           static_cast<R*>(b.Hpart));
         break;
       case kFG:
-        hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_g(d), s, d, W, H, g, P,
-                           static_cast<R*>(b.gpart));
+        hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_g(d), s, d, W,
+                           static_cast<const R*>(b.Ht), g, P, static_cast<R*>(b.gpart), static_cast<R*>(b.lam));
         break;
       default:
         return hipErrorInvalidValue;
@@ -796,7 +1009,7 @@ int fast_set_index(int N, int K, int ML, int L) {
   return -1;
 }
 
-int fast_h_waves(int dtype) { return dtype == DFM_C64 ? fast::h_waves<float>() : fast::h_waves<double>(); }
+int fast_h_chunks() { return fast::kHCPW; }
 
 size_t fast_max_smem(const Dims& d, int dtype) {
   switch (d.fast) {

@@ -56,7 +56,9 @@ struct Buffers {
   double* nllpart;  // [F][S]
   void* Qinv;       // [F][QF] complex double
   int* status;      // sticky status word
-  unsigned* counters;  // last-arrival counters of the specialised kernels: [F] [F] [TBN] [F]
+  unsigned* counters;  // last-arrival counters (unused by the current kernel sets)
+  void* lam;           // [F][T][N] real: lambda = W H of the specialised kernels
+  void* Ht;            // [T][N*K] real: frame-major copy of H of the specialised kernels
 };
 
 size_t workspace_bytes(const Dims& d, int dtype);
@@ -66,7 +68,7 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 // three apply kernels of the generic path.
 enum KernelId {
   kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply,
-  kFGram, kFIp, kFPw, kFH, kFG, kNumKernels
+  kFGram, kFIp, kFPw, kFH, kFG, kFLam, kFHt, kFHApply, kNumKernels
 };
 
 // Launchers (return hipSuccess or the first launch error).
@@ -79,7 +81,7 @@ int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns 
 // Shape-specialised kernel sets (dfm_fast.hip).
 int fast_set_index(int N, int K, int ML, int L);
 size_t fast_max_smem(const Dims& d, int dtype);
-int fast_h_waves(int dtype);
+int fast_h_chunks();
 hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s);
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);

@@ -653,7 +653,10 @@ template <typename R>
 static hipError_t cov_impl(const Dims& d, const Buffers& b, void* V, hipStream_t s) {
   // The plan's own covariance kernel (both write the same packed slice-sum layout).
   if (d.fast >= 0) {
-    const hipError_t e = fast_launch(d, b, sizeof(R) == 4 ? DFM_C64 : DFM_C128, kFGram, s);
+    const int dt = sizeof(R) == 4 ? DFM_C64 : DFM_C128;
+    hipError_t e = fast_launch(d, b, dt, kFHt, s);
+    if (e == hipSuccess) e = fast_launch(d, b, dt, kFLam, s);
+    if (e == hipSuccess) e = fast_launch(d, b, dt, kFGram, s);
     if (e != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(k_gram<R>, dim3(d.F, d.S), dim3(kBlock), smem_gram<R>(d), s, d,
@@ -680,7 +683,7 @@ hipError_t launch_kernel(const Dims& d, const Buffers& b, int dtype, int kid, hi
 const char* kernel_name(int kid) {
   static const char* names[kNumKernels] = {"k_gram", "k_ip",   "k_pw",   "k_wapply", "k_h", "k_happly",
                                            "k_g",    "k_gapply", "k_gram_f", "k_ip_f", "k_pw_f", "k_h_f",
-                                           "k_g_f"};
+                                           "k_g_f",  "k_lam_f",  "k_ht_f",   "k_happly_f"};
   return kid >= 0 && kid < kNumKernels ? names[kid] : nullptr;
 }
 
@@ -690,7 +693,7 @@ int stage_kernels(const Dims& d, int stage, int* kids) {
     switch (stage) {
       case DFM_STAGE_IP: kids[0] = kFGram; kids[1] = kFIp; return 2;
       case DFM_STAGE_W: kids[0] = kFPw; kids[1] = kKWApply; return 2;
-      case DFM_STAGE_H: kids[0] = kFH; kids[1] = kKHApply; return 2;
+      case DFM_STAGE_H: kids[0] = kFH; kids[1] = kFHApply; return 2;
       case DFM_STAGE_G: kids[0] = kFG; kids[1] = kKGApply; return 2;
     }
     return 0;
