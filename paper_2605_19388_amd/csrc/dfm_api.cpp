@@ -257,10 +257,9 @@ dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream) {
   if (!plan || stage < DFM_STAGE_IP || stage > DFM_STAGE_G) return DFM_E_ARG;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   // A sub-step may follow a change of the state by the caller: refresh the frame-major H
-  // (and lambda before the covariances) that the specialised kernels read.
-  if (plan->d.fast >= 0 && stage != DFM_STAGE_H && dfm::run_kernel(plan, dfm::kFHt, s) != hipSuccess)
-    return DFM_E_HIP;
-  if (stage == DFM_STAGE_IP && plan->d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess)
+  // and lambda = W H that the specialised kernels read (the H sub-step forms its own).
+  if (plan->d.fast >= 0 && stage != DFM_STAGE_H &&
+      (dfm::run_kernel(plan, dfm::kFHt, s) != hipSuccess || dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess))
     return DFM_E_HIP;
   if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
   return DFM_OK;

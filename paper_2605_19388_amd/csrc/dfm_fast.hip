@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__
   if (tid < nt) {
     load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + tid) * M));
 #pragma unroll
-    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * T + t0 + tid) * N + n];
+    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
   } else {  // padding frames contribute zero products
 #pragma unroll
     for (int i = 0; i < 2 * M; ++i) xv[i] = 0;
@@ -506,48 +506,86 @@ __global__ __launch_bounds__(kT) void k_ht_f(Dims d, const R* __restrict__ H, R*
   }
 }
 
-// Activation update, eq. (9): H <- H sqrt(num / max(den, eps)) with num, den summed over
-// the frequency-group partials in order; writes H and its frame-major copy.
-template <typename R, int NK>
-__global__ __launch_bounds__(256) void k_happly_f(Dims d, R* __restrict__ H, R* __restrict__ Ht,
-                                                  const R* __restrict__ Hpart, int* __restrict__ status) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= NK * d.T) return;
-  const int nk = idx / d.T, t = idx - nk * d.T;
-  R num = 0, den = 0;
-  for (int q = 0; q < d.FG; ++q) {
-    const R* pp = Hpart + (((size_t)q * NK + nk) * d.T + t) * 2;
-    num += pp[0];
-    den += pp[1];
+// lambda[f][n][t] = sum_k W[n][f][k] H[n][k][t] (eq. (2)) on the matrix cores: one 16 x 16
+// tile (rows f, columns t) per wave, contraction over the bases four at a time.
+// Hn: the activations of source n for the tile's 16 frames, [4 * ceil(K/4)][16] in LDS,
+// zero beyond K and T.
+template <typename R, int N, int K>
+__device__ __forceinline__ void lambda_tile(const Dims& d, const R* __restrict__ W, const R* Hn, int n, int f0,
+                                            int t0, int lane, R* __restrict__ lam) {
+  constexpr int KS = (K + 3) / 4;
+  typedef typename Mma<R>::v4 v4;
+  const int i = lane & 15, kk = lane >> 4;
+  const int fr = f0 + i;
+  R av[KS], bv[KS];
+#pragma unroll
+  for (int st = 0; st < KS; ++st) {
+    const int k = 4 * st + kk;
+    av[st] = (fr < d.F && k < K) ? W[((size_t)n * d.F + fr) * K + k] : (R)0;
+    bv[st] = Hn[(4 * st + kk) * 16 + i];
   }
-  const R v = H[idx] * sqrt(num / rmax(den, (R)d.eps));
-  if (!isfinite(v)) atomicOr(status, kStNonFinite);
-  H[idx] = v;
-  Ht[(size_t)t * NK + nk] = v;
+  v4 acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int st = 0; st < KS; ++st) acc = Mma<R>::run(av[st], bv[st], acc);
+  const int t = t0 + i;
+  if (t < d.T)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int f = f0 + Mma<R>::row(lane, r);
+      if (f < d.F) lam[((size_t)f * N + n) * d.T + t] = acc[r];
+    }
 }
 
-// lambda[f][t][n] = sum_k W[n][f][k] H[n][k][t] (eq. (2)) for every frame of a tile.
+constexpr int kLamWaves = 8;  // waves of the activation-apply workgroup
+
+// Activation update, eq. (9): H <- H sqrt(num / max(den, eps)) with num, den summed over
+// the frequency-group partials in order; writes H and its frame-major copy.  W is final
+// for the iteration at this point, so lambda = W H (eq. (2)) for the new H is formed here
+// too (it serves the eq. (10) sums and the next iteration's covariances and powers).
+// Workgroup: one source n, 16 frames.
 template <typename R, int N, int K>
-__global__ __launch_bounds__(kT) void k_lam_f(Dims d, const R* __restrict__ W, const R* __restrict__ Ht,
-                                              R* __restrict__ lamout) {
-  constexpr int NK = N * K;
-  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
-  const int t0 = s * d.SL;
-  const int nt = min(d.SL, d.T - t0);
-  __shared__ R sW[NK];
-  for (int i = tid; i < NK; i += kT) sW[i] = W[((size_t)(i / K) * d.F + f) * K + i % K];
-  __syncthreads();
-  if (tid >= nt) return;
-  R hv[NK];
-  load_h_column<R, NK>(hv, Ht, t0 + tid);
-  sched_fence();
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-    R acc = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc += sW[n * K + k] * hv[n * K + k];
-    lamout[((size_t)f * d.T + t0 + tid) * N + n] = acc;
+__global__ __launch_bounds__(64 * kLamWaves) void k_happly_f(Dims d, const R* __restrict__ W, R* __restrict__ H,
+                                                             R* __restrict__ Ht, const R* __restrict__ Hpart,
+                                                             R* __restrict__ lam, int* __restrict__ status) {
+  constexpr int NK = N * K, KS = (K + 3) / 4;
+  __shared__ R sHn[4 * KS * 16];
+  const int n = blockIdx.x, t0 = blockIdx.y * 16, tid = threadIdx.x;
+  const int tl = tid & 15, t = t0 + tl;
+  for (int k = tid >> 4; k < 4 * KS; k += 4 * kLamWaves) {
+    R v = 0;
+    if (k < K && t < d.T) {
+      const size_t idx = ((size_t)n * K + k) * d.T + t;
+      R num = 0, den = 0;
+      for (int q = 0; q < d.FG; ++q) {
+        const R* pp = Hpart + (((size_t)q * NK + n * K + k) * d.T + t) * 2;
+        num += pp[0];
+        den += pp[1];
+      }
+      v = H[idx] * sqrt(num / rmax(den, (R)d.eps));
+      if (!isfinite(v)) atomicOr(status, kStNonFinite);
+      H[idx] = v;
+      Ht[(size_t)t * NK + n * K + k] = v;
+    }
+    sHn[k * 16 + tl] = v;
   }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int f0 = wave * 16; f0 < d.F; f0 += 16 * kLamWaves) lambda_tile<R, N, K>(d, W, sHn, n, f0, t0, lane, lam);
+}
+
+// lambda for the caller's W and H (before the first iteration); grid (N, tiles of 16 frames).
+template <typename R, int N, int K>
+__global__ __launch_bounds__(64 * kLamWaves) void k_lam_f(Dims d, const R* __restrict__ W, const R* __restrict__ H,
+                                                          R* __restrict__ lam) {
+  constexpr int KS = (K + 3) / 4;
+  __shared__ R sHn[4 * KS * 16];
+  const int n = blockIdx.x, t0 = blockIdx.y * 16, tid = threadIdx.x;
+  const int tl = tid & 15, t = t0 + tl;
+  for (int k = tid >> 4; k < 4 * KS; k += 4 * kLamWaves)
+    sHn[k * 16 + tl] = (k < K && t < d.T) ? H[((size_t)n * K + k) * d.T + t] : (R)0;
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int f0 = wave * 16; f0 < d.F; f0 += 16 * kLamWaves) lambda_tile<R, N, K>(d, W, sHn, n, f0, t0, lane, lam);
 }
 
 // IP sweep, eqs. (15)-(16), one lane per (f, subarray) block of size M_l <= 4, in FP64;
@@ -586,107 +624,174 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const R* __restrict__ Vpart
 }
 
 // ------------------------------------------------------------------------------------
-// P = |Q x|^2 and the eq. (8) sums per (f, slice).
+// P = |Q x|^2 and the eq. (8) sums per (f, slice).  Per frame: the powers, 1/y, and
+// a_n = sum_m g_nm P_m / y_m^2, b_n = sum_m g_nm / y_m, stored frame-major in LDS.  Then
+// num/den[n][k] = sum_t H[n][k][t] (a_n, b_n)[t]: in FP32 on the 4x4x1 matrix-core blocks
+// (block = (n, group of 4 bases), rows = bases, columns = (a_n, b_n, -, -)), one op per
+// frame and 16 blocks, with H read from its frame-major copy; frames alternate between
+// the two waves.
+template <typename R, int N, int K, int ML, int L>
+struct PwShape {
+  static constexpr int M = ML * L, NK = N * K, ML2 = ML * ML, QF = L * ML2;
+  static constexpr int NP = (N + 3) & ~3;
+  static constexpr int CP = padded<R>(2 * NP);  // LDS row: a_0 .. a_{NP-1}, b_0 .. b_{NP-1}
+  static constexpr int KG = K / 4;
+  static constexpr int NI = (N * KG + 15) / 16;  // 4x4x1 ops per frame
+};
+
 template <typename R, int N, int K, int ML, int L>
 __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
-                                             const R* __restrict__ W, const R* __restrict__ Ht, const R* __restrict__ g,
-                                             R* __restrict__ P, R* __restrict__ Wpart) {
-  constexpr int M = ML * L, NK = N * K, ML2 = ML * ML, QF = L * ML2;
-  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
-  const int T = d.T, SLP = d.SLP;
+                                             const R* __restrict__ lamin, const R* __restrict__ Ht,
+                                             const R* __restrict__ g, R* __restrict__ P, R* __restrict__ Wpart) {
+  typedef PwShape<R, N, K, ML, L> S_;
+  constexpr int M = S_::M, NK = S_::NK, ML2 = S_::ML2, QF = S_::QF, NP = S_::NP, CP = S_::CP;
+  constexpr int E = V16<R>::E;
+  static_assert(K % 4 == 0 && (2 * M) % E == 0 && M % E == 0 && (2 * NP) % E == 0, "shape");
+  typedef typename V16<R>::type vt;
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int T = d.T;
   const int t0 = s * d.SL;
   const int nt = min(d.SL, T - t0);
   const int ntp = (nt + 3) & ~3;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<R>* sQ = reinterpret_cast<cx<R>*>(smem);
-  R* sW = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 32));
-  R* sg = sW + NK;
-  R* sH = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 32) + align_up(sizeof(R) * (NK + N * M), 32));
-  R* sab = sH + (size_t)NK * SLP;  // [2N][SLP]
+  R* sg = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 16));
+  R* sC = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 16) + align_up(sizeof(R) * N * M, 16));
+  R* sRed = sC + (size_t)d.SLP * CP;  // FP32: [NI][64][4]
 
+  // One batch of loads: x and lambda at this thread's frame.
+  R xv[2 * M], lam[N];
+  if (tid < nt) {
+    load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + tid) * M));
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2 * M; ++i) xv[i] = 0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[n] = 0;
+  }
   for (int i = tid; i < QF; i += kT) sQ[i] = Q[(size_t)f * QF + i];
-  for (int i = tid; i < NK; i += kT) sW[i] = W[((size_t)(i / K) * d.F + f) * K + i % K];
   for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
+  sched_fence();
   __syncthreads();
 
-  for (int tl = tid; tl < ntp; tl += kT) {
-    if (tl < nt) {
-      const int t = t0 + tl;
-      R hv[NK], xv[2 * M];
-      load_h_column<R, NK>(hv, Ht, t);
-      load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t) * M));
-      sched_fence();
-      R lam[N];
+  if (tid < ntp) {
+    R a[NP], b[NP], pv[M];
 #pragma unroll
-      for (int n = 0; n < N; ++n) {
-        R acc = 0;
+    for (int n = 0; n < NP; ++n) {
+      a[n] = 0;
+      b[n] = 0;
+    }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          sH[(n * K + k) * SLP + tl] = hv[n * K + k];
-          acc += sW[n * K + k] * hv[n * K + k];
+    for (int l = 0; l < L; ++l) {
+#pragma unroll
+      for (int mu = 0; mu < ML; ++mu) {
+        R zr = 0, zi = 0;
+#pragma unroll
+        for (int c = 0; c < ML; ++c) {
+          const cx<R> q = sQ[l * ML2 + mu * ML + c];
+          const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
+          zr += q.re * xr - q.im * xi;
+          zi += q.re * xi + q.im * xr;
         }
-        lam[n] = acc;
-      }
-      R a[N], b[N], pv[M];
+        const int m = l * ML + mu;
+        const R p = zr * zr + zi * zi;
+        pv[m] = p;
+        R y = 0;
 #pragma unroll
-      for (int n = 0; n < N; ++n) {
-        a[n] = 0;
-        b[n] = 0;
-      }
+        for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
+        const R iy = tid < nt ? rcp(rmax(y, (R)d.eps)) : (R)0;
+        const R piy2 = p * iy * iy;
 #pragma unroll
-      for (int l = 0; l < L; ++l) {
-#pragma unroll
-        for (int mu = 0; mu < ML; ++mu) {
-          R zr = 0, zi = 0;
-#pragma unroll
-          for (int c = 0; c < ML; ++c) {
-            const cx<R> q = sQ[l * ML2 + mu * ML + c];
-            const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
-            zr += q.re * xr - q.im * xi;
-            zi += q.re * xi + q.im * xr;
-          }
-          const int m = l * ML + mu;
-          const R p = zr * zr + zi * zi;
-          pv[m] = p;
-          R y = 0;
-#pragma unroll
-          for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
-          const R iy = rcp(rmax(y, (R)d.eps));
-          const R piy2 = p * iy * iy;
-#pragma unroll
-          for (int n = 0; n < N; ++n) {
-            a[n] += sg[n * M + m] * piy2;
-            b[n] += sg[n * M + m] * iy;
-          }
+        for (int n = 0; n < N; ++n) {
+          a[n] += sg[n * M + m] * piy2;
+          b[n] += sg[n * M + m] * iy;
         }
       }
-      store16_nt<R, M>(P + ((size_t)f * T + t) * M, pv);
+    }
+    if (tid < nt) store16_nt<R, M>(P + ((size_t)f * T + t0 + tid) * M, pv);
 #pragma unroll
-      for (int n = 0; n < N; ++n) {
-        sab[n * SLP + tl] = a[n];
-        sab[(N + n) * SLP + tl] = b[n];
+    for (int i = 0; i < NP / E; ++i) {
+      vt va, vb;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        va[e] = a[i * E + e];
+        vb[e] = b[i * E + e];
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < NK; ++i) sH[i * SLP + tl] = 0;
-#pragma unroll
-      for (int i = 0; i < 2 * N; ++i) sab[i * SLP + tl] = 0;
+      reinterpret_cast<vt*>(sC + (size_t)tid * CP)[i] = va;
+      reinterpret_cast<vt*>(sC + (size_t)tid * CP + NP)[i] = vb;
     }
   }
   __syncthreads();
 
   R* out = Wpart + ((size_t)f * d.S + s) * NK * 2;
-  for (int o = tid; o < NK; o += kT) {
-    const int n = o / K;
-    const R* hr = sH + o * SLP;
-    const R* ar = sab + n * SLP;
-    const R* br = sab + (N + n) * SLP;
-    R num, den;
-    dot2_frames<R>(hr, ar, br, ntp, num, den);
-    out[o * 2 + 0] = num;
-    out[o * 2 + 1] = den;
+  if constexpr (sizeof(R) == 4) {
+    constexpr int NI = S_::NI, KG = S_::KG;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const int sub = lane & 3;
+    v4f acc[NI];
+    int hcol[NI], coff[NI];
+    bool aok[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      acc[q] = v4f{0, 0, 0, 0};
+      const int blk = 16 * q + (lane >> 2), n = blk / KG;
+      aok[q] = blk < N * KG;
+      hcol[q] = aok[q] ? 64 * q + lane : 0;  // = n * K + 4 * (blk % KG) + sub
+      coff[q] = (aok[q] && sub < 2) ? sub * NP + n : -1;
+    }
+    const int half = ((ntp >> 1) + 3) & ~3;
+    const int fb = wave == 0 ? 0 : half, fe = wave == 0 ? min(half, ntp) : ntp;
+    const R* hbase = Ht + (size_t)t0 * NK;
+    for (int t4 = fb; t4 < fe; t4 += 4) {
+      R av[4][NI], bv[4][NI];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int tt = min(t4 + u, nt - 1);  // padding frames: any in-bounds row (their b is zero)
+#pragma unroll
+        for (int q = 0; q < NI; ++q) av[u][q] = hbase[(size_t)tt * NK + hcol[q]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+          const R c = sC[(size_t)(t4 + u) * CP + (coff[q] < 0 ? 0 : coff[q])];
+          bv[u][q] = coff[q] < 0 ? (R)0 : c;
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NI; ++q) acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
+    }
+    if (wave == 1)
+#pragma unroll
+      for (int q = 0; q < NI; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sRed[(q * 64 + lane) * 4 + r] = acc[q][r];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        if (coff[q] < 0) continue;
+        const int blk = 16 * q + (lane >> 2), n = blk / KG, kg = blk - n * KG;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[(n * K + 4 * kg + r) * 2 + sub] = acc[q][r] + sRed[(q * 64 + lane) * 4 + r];
+      }
+  } else {
+    for (int o = tid; o < NK; o += kT) {
+      const int n = o / K;
+      R num = 0, den = 0;
+      for (int tt = 0; tt < nt; ++tt) {
+        const R h = Ht[(size_t)(t0 + tt) * NK + o];
+        num += h * sC[(size_t)tt * CP + n];
+        den += h * sC[(size_t)tt * CP + NP + n];
+      }
+      out[o * 2 + 0] = num;
+      out[o * 2 + 1] = den;
+    }
   }
-
 }
 
 // ------------------------------------------------------------------------------------
@@ -847,75 +952,149 @@ __global__ __launch_bounds__(256) void k_h_f(Dims d, const R* __restrict__ W, co
 }
 
 // ------------------------------------------------------------------------------------
-// Eq. (10) sums per (f, slice).  lambda = W H at every frame is also stored: W and H
-// do not change again in this iteration, so the next covariance kernel reads it.
+// Eq. (10) sums per (f, slice).  Per frame: 1/y and P/y^2 from lambda (read), stored
+// frame-major in LDS with lambda.  Then num/den[n][m] = sum_t lambda_n (P_m/y_m^2, 1/y_m):
+// in FP32 on the 4x4x1 matrix-core blocks (block = (group of 4 sources, group of 4 mics,
+// numerator or denominator)), one op per frame and 16 blocks; frames alternate between
+// the two waves.
 template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ W, const R* __restrict__ Ht,
-                                            const R* __restrict__ g, const R* __restrict__ P,
-                                            R* __restrict__ gpart, R* __restrict__ lamout) {
-  constexpr int M = ML * L, NK = N * K;
-  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
-  const int T = d.T, SLP = d.SLP;
+struct GShape {
+  static constexpr int M = ML * L;
+  static constexpr int NP = (N + 3) & ~3;
+  static constexpr int AP = padded<R>(NP);     // LDS row of lambda
+  static constexpr int BP = padded<R>(2 * M);  // LDS row of P/y^2 then 1/y
+  static constexpr int NGR = NP / 4, MG = M / 4;
+  static constexpr int NI = (2 * NGR * MG + 15) / 16;
+};
+
+template <typename R, int N, int K, int ML, int L>
+__global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ lamin, const R* __restrict__ g,
+                                            const R* __restrict__ P, R* __restrict__ gpart) {
+  typedef GShape<R, N, K, ML, L> G;
+  constexpr int M = G::M, NP = G::NP, AP = G::AP, BP = G::BP;
+  constexpr int E = V16<R>::E;
+  static_assert(M % 4 == 0 && M % E == 0 && NP % E == 0 && N * M <= kT, "shape");
+  typedef typename V16<R>::type vt;
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int T = d.T;
   const int t0 = s * d.SL;
   const int nt = min(d.SL, T - t0);
   const int ntp = (nt + 3) & ~3;
   extern __shared__ __align__(16) unsigned char smem[];
-  R* sW = reinterpret_cast<R*>(smem);
-  R* sg = sW + NK;
-  R* sLam = reinterpret_cast<R*>(smem + align_up(sizeof(R) * (NK + N * M), 32));  // [N][SLP]
-  R* sR = sLam + N * SLP;                                                         // [2M][SLP]
+  R* sg = reinterpret_cast<R*>(smem);
+  R* sA = reinterpret_cast<R*>(smem + align_up(sizeof(R) * N * M, 16));  // [SLP][AP]
+  R* sB = sA + (size_t)d.SLP * AP;                                         // [SLP][BP]
+  R* sRed = sB + (size_t)d.SLP * BP;                                       // FP32: [NI][64][4]
 
-  for (int i = tid; i < NK; i += kT) sW[i] = W[((size_t)(i / K) * d.F + f) * K + i % K];
-  for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
+  R pv[M], lam[NP], gv = 0;
+#pragma unroll
+  for (int n = N; n < NP; ++n) lam[n] = 0;
+  if (tid < nt) {
+    load16<R, M>(pv, P + ((size_t)f * T + t0 + tid) * M);
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
+  } else {
+#pragma unroll
+    for (int m = 0; m < M; ++m) pv[m] = 0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[n] = 0;
+  }
+  if (tid < N * M) gv = g[(size_t)f * N * M + tid];
+  sched_fence();
+  if (tid < N * M) sg[tid] = gv;
   __syncthreads();
-
-  for (int tl = tid; tl < ntp; tl += kT) {
-    if (tl < nt) {
-      const int t = t0 + tl;
-      R hv[NK], pv[M];
-      load_h_column<R, NK>(hv, Ht, t);
-      load16<R, M>(pv, P + ((size_t)f * T + t) * M);
-      sched_fence();
-      R lam[N];
+  if (tid < ntp) {
+    R u[2 * M];
 #pragma unroll
-      for (int n = 0; n < N; ++n) {
-        R acc = 0;
+    for (int m = 0; m < M; ++m) {
+      R y = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc += sW[n * K + k] * hv[n * K + k];
-        lam[n] = acc;
-        sLam[n * SLP + tl] = acc;
-        lamout[((size_t)f * T + t) * N + n] = acc;
-      }
+      for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
+      const R iy = tid < nt ? rcp(rmax(y, (R)d.eps)) : (R)0;
+      u[m] = pv[m] * iy * iy;
+      u[M + m] = iy;
+    }
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        R y = 0;
+    for (int i = 0; i < NP / E; ++i) {
+      vt v;
 #pragma unroll
-        for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
-        const R iy = rcp(rmax(y, (R)d.eps));
-        sR[m * SLP + tl] = pv[m] * iy * iy;
-        sR[(M + m) * SLP + tl] = iy;
-      }
-    } else {
+      for (int e = 0; e < E; ++e) v[e] = lam[i * E + e];
+      reinterpret_cast<vt*>(sA + (size_t)tid * AP)[i] = v;
+    }
 #pragma unroll
-      for (int n = 0; n < N; ++n) sLam[n * SLP + tl] = 0;
+    for (int i = 0; i < 2 * M / E; ++i) {
+      vt v;
 #pragma unroll
-      for (int m = 0; m < 2 * M; ++m) sR[m * SLP + tl] = 0;
+      for (int e = 0; e < E; ++e) v[e] = u[i * E + e];
+      reinterpret_cast<vt*>(sB + (size_t)tid * BP)[i] = v;
     }
   }
   __syncthreads();
 
   R* out = gpart + ((size_t)f * d.S + s) * N * M * 2;
-  for (int o = tid; o < N * M; o += kT) {
-    const int n = o / M, m = o % M;
-    const R* lr = sLam + n * SLP;
-    const R* r1 = sR + m * SLP;
-    const R* r2 = sR + (M + m) * SLP;
-    R num, den;
-    dot2_frames<R>(lr, r1, r2, ntp, num, den);
-    out[o * 2 + 0] = num;
-    out[o * 2 + 1] = den;
+  if constexpr (sizeof(R) == 4) {
+    constexpr int NI = G::NI, NGR = G::NGR, MG = G::MG;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const int sub = lane & 3;
+    v4f acc[NI];
+    int aoff[NI], boff[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      acc[q] = v4f{0, 0, 0, 0};
+      const int blk = 16 * q + (lane >> 2);
+      const bool ok = blk < 2 * NGR * MG;
+      const int ng = blk % NGR, rest = blk / NGR, mg = rest % MG, uz = rest / MG;
+      aoff[q] = ok ? 4 * ng + sub : 0;
+      boff[q] = ok ? uz * M + 4 * mg + sub : 0;
+    }
+    const int half = ((ntp >> 1) + 3) & ~3;
+    const int fb = wave == 0 ? 0 : half, fe = wave == 0 ? min(half, ntp) : ntp;
+    for (int t4 = fb; t4 < fe; t4 += 4) {
+      R av[4][NI], bv[4][NI];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+          av[u][q] = sA[(size_t)(t4 + u) * AP + aoff[q]];
+          bv[u][q] = sB[(size_t)(t4 + u) * BP + boff[q]];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NI; ++q) acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
+    }
+    if (wave == 1)
+#pragma unroll
+      for (int q = 0; q < NI; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sRed[(q * 64 + lane) * 4 + r] = acc[q][r];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        const int blk = 16 * q + (lane >> 2);
+        if (blk >= 2 * NGR * MG) continue;
+        const int ng = blk % NGR, rest = blk / NGR, mg = rest % MG, uz = rest / MG;
+        const int m = 4 * mg + sub;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = 4 * ng + r;
+          if (n < N) out[(n * M + m) * 2 + uz] = acc[q][r] + sRed[(q * 64 + lane) * 4 + r];
+        }
+      }
+  } else {
+    for (int o = tid; o < N * M; o += kT) {
+      const int n = o / M, m = o - n * M;
+      R num = 0, den = 0;
+      for (int tt = 0; tt < ntp; ++tt) {
+        const R lv = sA[(size_t)tt * AP + n];
+        num += lv * sB[(size_t)tt * BP + m];
+        den += lv * sB[(size_t)tt * BP + M + m];
+      }
+      out[o * 2 + 0] = num;
+      out[o * 2 + 1] = den;
+    }
   }
-
 }
 
 // ------------------------------------------------------------------------------------
@@ -930,12 +1109,14 @@ struct Set {
     return align_up(sizeof(R) * N * M, 16) + sizeof(R) * (rows > red ? rows : red);
   }
   static size_t smem_pw(const Dims& d) {
-    return align_up(sizeof(cx<R>) * L * ML * ML, 32) + align_up(sizeof(R) * (N * K + N * M), 32) +
-           sizeof(R) * (N * K + 2 * N) * d.SLP;
+    typedef PwShape<R, N, K, ML, L> S_;
+    return align_up(sizeof(cx<R>) * S_::QF, 16) + align_up(sizeof(R) * N * M, 16) +
+           sizeof(R) * ((size_t)d.SLP * S_::CP + S_::NI * 256);
   }
   static size_t smem_h(const Dims&) { return sizeof(R) * (N * K * kHTB + 16 * N * M + N * 2 * 256); }
   static size_t smem_g(const Dims& d) {
-    return align_up(sizeof(R) * (N * K + N * M), 32) + sizeof(R) * (N + 2 * M) * d.SLP;
+    typedef GShape<R, N, K, ML, L> G;
+    return align_up(sizeof(R) * N * M, 16) + sizeof(R) * ((size_t)d.SLP * (G::AP + G::BP) + G::NI * 256);
   }
   static size_t max_smem(const Dims& d) {
     size_t m = smem_gram(d);
@@ -957,12 +1138,13 @@ struct Set {
                            static_cast<R*>(b.Ht));
         break;
       case kFHApply:
-        hipLaunchKernelGGL((k_happly_f<R, N * K>), dim3((N * K * d.T + 255) / 256), dim3(256), 0, s, d, H,
-                           static_cast<R*>(b.Ht), static_cast<const R*>(b.Hpart), b.status);
+        hipLaunchKernelGGL((k_happly_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kLamWaves), 0, s, d, W, H,
+                           static_cast<R*>(b.Ht), static_cast<const R*>(b.Hpart), static_cast<R*>(b.lam),
+                           b.status);
         break;
       case kFLam:
-        hipLaunchKernelGGL((k_lam_f<R, N, K>), dim3(d.F, d.S), dim3(kT), 0, s, d, W,
-                           static_cast<const R*>(b.Ht), static_cast<R*>(b.lam));
+        hipLaunchKernelGGL((k_lam_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kLamWaves), 0, s, d, W, H,
+                           static_cast<R*>(b.lam));
         break;
       case kFGram:
         hipLaunchKernelGGL((k_gram_f<R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d, X,
@@ -977,16 +1159,17 @@ struct Set {
         }
         break;
       case kFPw:
-        hipLaunchKernelGGL((k_pw_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_pw(d), s, d, X, Q, W,
-                           static_cast<const R*>(b.Ht), g, P, static_cast<R*>(b.Wpart));
+        hipLaunchKernelGGL((k_pw_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_pw(d), s, d, X, Q,
+                           static_cast<const R*>(b.lam), static_cast<const R*>(b.Ht), g, P,
+                           static_cast<R*>(b.Wpart));
         break;
       case kFH:
         hipLaunchKernelGGL((k_h_f<R, N, K, ML, L>), dim3(d.FG, d.TBN), dim3(256), smem_h(d), s, d, W, H, g, P,
                            static_cast<R*>(b.Hpart));
         break;
       case kFG:
-        hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_g(d), s, d, W,
-                           static_cast<const R*>(b.Ht), g, P, static_cast<R*>(b.gpart), static_cast<R*>(b.lam));
+        hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_g(d), s, d,
+                           static_cast<const R*>(b.lam), g, P, static_cast<R*>(b.gpart));
         break;
       default:
         return hipErrorInvalidValue;

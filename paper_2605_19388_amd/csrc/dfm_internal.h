@@ -57,7 +57,7 @@ struct Buffers {
   void* Qinv;       // [F][QF] complex double
   int* status;      // sticky status word
   unsigned* counters;  // last-arrival counters (unused by the current kernel sets)
-  void* lam;           // [F][T][N] real: lambda = W H of the specialised kernels
+  void* lam;           // [F][N][T] real: lambda = W H of the specialised kernels
   void* Ht;            // [T][N*K] real: frame-major copy of H of the specialised kernels
 };
 
