@@ -51,8 +51,7 @@ static bool choose_fast(Dims& d, int dtype) {
     d.SLP = ((d.SL + 3) & ~3) + 4;
     d.TB = 16;
     d.TBN = (d.T + 15) / 16;
-    d.FG = ((d.F + 15) / 16 + fast_h_chunks() - 1) / fast_h_chunks();
-    d.FS = d.FG;
+    d.TP = (d.T + 15) & ~15;
     if (fast_max_smem(d, dtype) <= 64 * 1024) return true;
   }
   d.fast = -1;
@@ -123,16 +122,17 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   size_t n = 0;
   n += al(r * d.F * d.T * d.M);                        // P
   n += al(r * d.F * d.S * d.VF);                       // Vpart
-  n += al(r * d.F * d.S * d.N * d.K * 2);              // Wpart
-  n += al(r * (size_t)(d.fast >= 0 ? d.FG : d.FS) * d.N * d.K * d.T * 2);  // Hpart
+  const bool fast = d.fast >= 0;
+  n += al(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);    // Wpart
+  n += al(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);  // Hpart
   n += al(r * d.F * d.S * d.N * d.M * 2);              // gpart
   n += al(8 * d.F * d.L);                              // logdet
   n += al(8 * d.F * d.S);                              // nllpart
   n += al(16 * d.F * d.QF);                            // Qinv
   n += al(64);                                         // status
-  n += al(4 * (3 * (size_t)d.F + d.TBN));              // counters
-  n += al(d.fast >= 0 ? r * d.F * d.T * d.N : 0);      // lambda
-  n += al(d.fast >= 0 ? r * d.T * d.N * d.K : 0);      // frame-major H
+  n += al(fast ? r * d.F * d.T * d.N : 0);             // lambda
+  n += al(fast ? r * d.T * d.N * d.K : 0);             // frame-major H
+  n += al(fast ? r * 2 * d.N * (size_t)d.F * d.TP : 0);  // coefficient planes
   return n;
 }
 
@@ -146,16 +146,17 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   };
   b.P = take(r * d.F * d.T * d.M);
   b.Vpart = take(r * d.F * d.S * d.VF);
-  b.Wpart = take(r * d.F * d.S * d.N * d.K * 2);
-  b.Hpart = take(r * (size_t)(d.fast >= 0 ? d.FG : d.FS) * d.N * d.K * d.T * 2);
+  const bool fast = d.fast >= 0;
+  b.Wpart = take(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);
+  b.Hpart = take(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);
   b.gpart = take(r * d.F * d.S * d.N * d.M * 2);
   b.logdet = reinterpret_cast<double*>(take(8 * d.F * d.L));
   b.nllpart = reinterpret_cast<double*>(take(8 * d.F * d.S));
   b.Qinv = take(16 * d.F * d.QF);
   b.status = reinterpret_cast<int*>(take(64));
-  b.counters = reinterpret_cast<unsigned*>(take(4 * (3 * (size_t)d.F + d.TBN)));
-  b.lam = d.fast >= 0 ? take(r * d.F * d.T * d.N) : nullptr;
-  b.Ht = d.fast >= 0 ? take(r * d.T * d.N * d.K) : nullptr;
+  b.lam = fast ? take(r * d.F * d.T * d.N) : nullptr;
+  b.Ht = fast ? take(r * d.T * d.N * d.K) : nullptr;
+  b.AB = fast ? take(r * 2 * d.N * (size_t)d.F * d.TP) : nullptr;
 }
 
 static hipError_t run_kernel(dfm_plan* plan, int kid, hipStream_t s) {
@@ -257,8 +258,8 @@ dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream) {
   if (!plan || stage < DFM_STAGE_IP || stage > DFM_STAGE_G) return DFM_E_ARG;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   // A sub-step may follow a change of the state by the caller: refresh the frame-major H
-  // and lambda = W H that the specialised kernels read (the H sub-step forms its own).
-  if (plan->d.fast >= 0 && stage != DFM_STAGE_H &&
+  // and lambda = W H that the specialised kernels read.
+  if (plan->d.fast >= 0 &&
       (dfm::run_kernel(plan, dfm::kFHt, s) != hipSuccess || dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess))
     return DFM_E_HIP;
   if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;

@@ -161,17 +161,4 @@ struct Mma<double> {
   static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-// Last-arrival test for a per-item counter shared by `expected` workgroups: every
-// workgroup publishes its partial results (release), the last one to arrive sees all of
-// them (acquire) and returns true; it must reset the counter when done.
-__device__ __forceinline__ bool last_arrival(unsigned* counter, unsigned expected, int* s_flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) *s_flag = atomicAdd(counter, 1u) == expected - 1u;
-  __syncthreads();
-  const bool last = *s_flag != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 }  // namespace dfm

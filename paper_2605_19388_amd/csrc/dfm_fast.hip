@@ -64,8 +64,9 @@ __device__ __forceinline__ void load16(R (&dst)[C], const R* src) {
   }
 }
 
+// Plain 16-byte stores (not non-temporal: a wave's partial-line stores must merge in L2).
 template <typename R, int C>
-__device__ __forceinline__ void store16_nt(R* dst, const R (&src)[C]) {
+__device__ __forceinline__ void store16(R* dst, const R (&src)[C]) {
   constexpr int E = V16<R>::E;
   static_assert(C % E == 0, "length must fill 16-byte vectors");
 #pragma unroll
@@ -73,44 +74,8 @@ __device__ __forceinline__ void store16_nt(R* dst, const R (&src)[C]) {
     typename V16<R>::type v;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = src[i * E + e];
-    __builtin_nontemporal_store(v, reinterpret_cast<typename V16<R>::type*>(dst) + i);
+    reinterpret_cast<typename V16<R>::type*>(dst)[i] = v;
   }
-}
-
-// num = sum_t c[t] a[t], den = sum_t c[t] b[t] over ntp (a multiple of 4) frames of three
-// LDS rows, read four frames per access (rows are 4-element aligned).
-template <typename R>
-__device__ __forceinline__ void dot2_frames(const R* c, const R* a, const R* b, int ntp, R& num, R& den) {
-  typedef R v4r __attribute__((ext_vector_type(4)));
-  R n0 = 0, n1 = 0, d0 = 0, d1 = 0;
-  const int nb = ntp >> 2;
-  for (int q0 = 0; q0 < nb; q0 += 4) {
-    v4r cv[4], av[4], bv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = min(q0 + u, nb - 1) * 4;  // clamped in bounds; extra blocks are zeroed below
-      cv[u] = *reinterpret_cast<const v4r*>(c + q);
-      av[u] = *reinterpret_cast<const v4r*>(a + q);
-      bv[u] = *reinterpret_cast<const v4r*>(b + q);
-      if (q0 + u >= nb) cv[u] = v4r{0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      n0 += cv[u].x * av[u].x + cv[u].z * av[u].z;
-      n1 += cv[u].y * av[u].y + cv[u].w * av[u].w;
-      d0 += cv[u].x * bv[u].x + cv[u].z * bv[u].z;
-      d1 += cv[u].y * bv[u].y + cv[u].w * bv[u].w;
-    }
-  }
-  num = n0 + n1;
-  den = d0 + d1;
-}
-
-// H[n][k][t] for every (n, k) at one frame, from the frame-major copy Ht[t][n*K + k]
-// (one batch of 16-byte loads).
-template <typename R, int NK>
-__device__ __forceinline__ void load_h_column(R (&hv)[NK], const R* __restrict__ Ht, int t) {
-  load16<R, NK>(hv, Ht + (size_t)t * NK);
 }
 
 // ------------------------------------------------------------------------------------
@@ -267,13 +232,14 @@ __device__ double logabsdet_lane(cd (&A)[ML][ML]) {
 // Weighted covariances (eq. (14)) on the matrix cores.
 //
 // Per-frame operand rows live in LDS, frame-major, with row strides padded so that the
-// 16-byte row writes of one frame per thread are free of bank conflicts:
-//   sInv[t][m] = 1 / y_ftm, and per subarray either the packed entries of x^(l) x^(l)H
-//   (M_l <= 4, formed once per frame) or the x tile itself (larger blocks, whose
-//   M_l^2 packed reals per frame would not fit).
+// 16-byte row writes of one frame per thread are free of bank conflicts: sInv[t][m] =
+// 1 / y_ftm, and either the x tile (x_ft itself) or, for FP64 with M_l <= 4, the packed
+// entries of every x^(l) x^(l)H formed once per frame.
 // FP32 with M_l <= 4: one v_mfma_f32_4x4x1 (16 independent 4x4 blocks) per frame, block
-// b = (subarray, group of 4 packed entries), rows = mu; the frames of a slice are split
-// over the two waves and their sums combined through LDS.
+// b = (subarray, group of 4 packed entries), rows = mu, each lane forming its packed entry
+// from two staged x values; the frames of a slice are split over the two waves and their
+// sums combined through LDS.  Staging x (2 M reals per frame) instead of the products
+// (L M_l^2) keeps the LDS per workgroup small enough for five workgroups per CU.
 // Otherwise: v_mfma 16x16x4 per subarray and 16 packed entries, K = 4 frames.
 
 // Row stride (elements) >= n whose 16-byte row segments start in distinct bank groups.
@@ -285,8 +251,8 @@ constexpr int padded(int n) {
 template <typename R, int N, int K, int ML, int L>
 struct GramShape {
   static constexpr int M = ML * L, ML2 = ML * ML, OF = L * ML2;
-  static constexpr bool kPre = ML <= 4;
-  static constexpr bool kBlocks = kPre && sizeof(R) == 4;  // 4x4x1 matrix-core path
+  static constexpr bool kBlocks = ML <= 4 && sizeof(R) == 4;  // 4x4x1 matrix-core path (x rows)
+  static constexpr bool kPre = ML <= 4 && !kBlocks;           // packed products staged per frame
   static constexpr int MP = padded<R>(M);
   static constexpr int OP = kPre ? padded<R>(OF) : padded<R>(2 * M);
   static constexpr int JG4 = (ML2 + 3) / 4;           // groups of 4 packed entries per subarray
@@ -387,9 +353,11 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__
     // (mu) and B column (entry) = i % 4.  Frames of the slice alternate between waves.
     constexpr int JG4 = G::JG4, NG = G::NG;
     const int sub = lane & 3;
+    // The lane's packed entry j of subarray l is Re or Im of x_a conj(x_b): B = u x_b.re + v x_b.im
+    // with (u, v) = (x_a.re, x_a.im) for the real part and (x_a.im, -x_a.re) for the imaginary.
     v4 acc[NG];
-    int aoff[NG], boff[NG];
-    bool av_ok[NG], bv_ok[NG];
+    int aoff[NG], xa[NG], xb[NG];
+    bool av_ok[NG], bv_ok[NG], im[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
       acc[q] = v4{0, 0, 0, 0};
@@ -397,19 +365,28 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__
       av_ok[q] = l < L && sub < ML;
       bv_ok[q] = l < L && j < ML2;
       aoff[q] = av_ok[q] ? l * ML + sub : 0;
-      boff[q] = bv_ok[q] ? l * ML2 + j : 0;
+      int pa = 0, pb = 0, part = 0;
+      if (bv_ok[q]) packed_pair(ML, j, pa, pb, part);
+      xa[q] = bv_ok[q] ? 2 * (l * ML + pa) : 0;
+      xb[q] = bv_ok[q] ? 2 * (l * ML + pb) : 0;
+      im[q] = part != 0;
     }
     const int half = ((ntp >> 1) + 3) & ~3;  // frames of wave 0; wave 1 takes the rest
     const int fb = wave == 0 ? 0 : half, fe = wave == 0 ? min(half, ntp) : ntp;
+    typedef R v2r __attribute__((ext_vector_type(2)));
     for (int t4 = fb; t4 < fe; t4 += 4) {
       R av[4][NG], bv[4][NG];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int q = 0; q < NG; ++q) {
-          const R a = sInv[(t4 + u) * MP + aoff[q]], b = sOp[(t4 + u) * OP + boff[q]];
+          const R* xr = sOp + (t4 + u) * OP;
+          const R a = sInv[(t4 + u) * MP + aoff[q]];
+          const v2r pa = *reinterpret_cast<const v2r*>(xr + xa[q]);
+          const v2r pb = *reinterpret_cast<const v2r*>(xr + xb[q]);
+          const R cu = im[q] ? pa.y : pa.x, cv = im[q] ? -pa.x : pa.y;
           av[u][q] = av_ok[q] ? a : (R)0;
-          bv[u][q] = bv_ok[q] ? b : (R)0;
+          bv[u][q] = bv_ok[q] ? cu * pb.x + cv * pb.y : (R)0;
         }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -538,41 +515,6 @@ __device__ __forceinline__ void lambda_tile(const Dims& d, const R* __restrict__
 
 constexpr int kLamWaves = 8;  // waves of the activation-apply workgroup
 
-// Activation update, eq. (9): H <- H sqrt(num / max(den, eps)) with num, den summed over
-// the frequency-group partials in order; writes H and its frame-major copy.  W is final
-// for the iteration at this point, so lambda = W H (eq. (2)) for the new H is formed here
-// too (it serves the eq. (10) sums and the next iteration's covariances and powers).
-// Workgroup: one source n, 16 frames.
-template <typename R, int N, int K>
-__global__ __launch_bounds__(64 * kLamWaves) void k_happly_f(Dims d, const R* __restrict__ W, R* __restrict__ H,
-                                                             R* __restrict__ Ht, const R* __restrict__ Hpart,
-                                                             R* __restrict__ lam, int* __restrict__ status) {
-  constexpr int NK = N * K, KS = (K + 3) / 4;
-  __shared__ R sHn[4 * KS * 16];
-  const int n = blockIdx.x, t0 = blockIdx.y * 16, tid = threadIdx.x;
-  const int tl = tid & 15, t = t0 + tl;
-  for (int k = tid >> 4; k < 4 * KS; k += 4 * kLamWaves) {
-    R v = 0;
-    if (k < K && t < d.T) {
-      const size_t idx = ((size_t)n * K + k) * d.T + t;
-      R num = 0, den = 0;
-      for (int q = 0; q < d.FG; ++q) {
-        const R* pp = Hpart + (((size_t)q * NK + n * K + k) * d.T + t) * 2;
-        num += pp[0];
-        den += pp[1];
-      }
-      v = H[idx] * sqrt(num / rmax(den, (R)d.eps));
-      if (!isfinite(v)) atomicOr(status, kStNonFinite);
-      H[idx] = v;
-      Ht[(size_t)t * NK + n * K + k] = v;
-    }
-    sHn[k * 16 + tl] = v;
-  }
-  __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6;
-  for (int f0 = wave * 16; f0 < d.F; f0 += 16 * kLamWaves) lambda_tile<R, N, K>(d, W, sHn, n, f0, t0, lane, lam);
-}
-
 // lambda for the caller's W and H (before the first iteration); grid (N, tiles of 16 frames).
 template <typename R, int N, int K>
 __global__ __launch_bounds__(64 * kLamWaves) void k_lam_f(Dims d, const R* __restrict__ W, const R* __restrict__ H,
@@ -624,330 +566,411 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const R* __restrict__ Vpart
 }
 
 // ------------------------------------------------------------------------------------
-// P = |Q x|^2 and the eq. (8) sums per (f, slice).  Per frame: the powers, 1/y, and
-// a_n = sum_m g_nm P_m / y_m^2, b_n = sum_m g_nm / y_m, stored frame-major in LDS.  Then
-// num/den[n][k] = sum_t H[n][k][t] (a_n, b_n)[t]: in FP32 on the 4x4x1 matrix-core blocks
-// (block = (n, group of 4 bases), rows = bases, columns = (a_n, b_n, -, -)), one op per
-// frame and 16 blocks, with H read from its frame-major copy; frames alternate between
-// the two waves.
-template <typename R, int N, int K, int ML, int L>
-struct PwShape {
-  static constexpr int M = ML * L, NK = N * K, ML2 = ML * ML, QF = L * ML2;
-  static constexpr int NP = (N + 3) & ~3;
-  static constexpr int CP = padded<R>(2 * NP);  // LDS row: a_0 .. a_{NP-1}, b_0 .. b_{NP-1}
-  static constexpr int KG = K / 4;
-  static constexpr int NI = (N * KG + 15) / 16;  // 4x4x1 ops per frame
-};
-
+// P = |Q x|^2 and the per-bin coefficients of eq. (8) for every (f, t) of a slice:
+// a_n = sum_m g_nm P_m / y_m^2 and b_n = sum_m g_nm / y_m, written as planes
+// AB[n][f][t] and AB[N + n][f][t] for the sums over frames in k_wgemm_f.
 template <typename R, int N, int K, int ML, int L>
 __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
-                                             const R* __restrict__ lamin, const R* __restrict__ Ht,
-                                             const R* __restrict__ g, R* __restrict__ P, R* __restrict__ Wpart) {
-  typedef PwShape<R, N, K, ML, L> S_;
-  constexpr int M = S_::M, NK = S_::NK, ML2 = S_::ML2, QF = S_::QF, NP = S_::NP, CP = S_::CP;
-  constexpr int E = V16<R>::E;
-  static_assert(K % 4 == 0 && (2 * M) % E == 0 && M % E == 0 && (2 * NP) % E == 0, "shape");
-  typedef typename V16<R>::type vt;
-  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+                                             const R* __restrict__ lamin, const R* __restrict__ g,
+                                             R* __restrict__ P, R* __restrict__ AB) {
+  constexpr int M = ML * L, ML2 = ML * ML, QF = L * ML2;
+  static_assert((2 * M) % V16<R>::E == 0 && M % V16<R>::E == 0, "rows must fill 16-byte vectors");
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
   const int T = d.T;
   const int t0 = s * d.SL;
   const int nt = min(d.SL, T - t0);
-  const int ntp = (nt + 3) & ~3;
-  extern __shared__ __align__(16) unsigned char smem[];
-  cx<R>* sQ = reinterpret_cast<cx<R>*>(smem);
-  R* sg = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 16));
-  R* sC = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * QF, 16) + align_up(sizeof(R) * N * M, 16));
-  R* sRed = sC + (size_t)d.SLP * CP;  // FP32: [NI][64][4]
+  __shared__ cx<R> sQ[QF];
+  __shared__ R sg[N * M];
 
   // One batch of loads: x and lambda at this thread's frame.
   R xv[2 * M], lam[N];
-  if (tid < nt) {
+  const bool live = tid < nt;
+  if (live) {
     load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + tid) * M));
 #pragma unroll
     for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
-  } else {
-#pragma unroll
-    for (int i = 0; i < 2 * M; ++i) xv[i] = 0;
-#pragma unroll
-    for (int n = 0; n < N; ++n) lam[n] = 0;
   }
   for (int i = tid; i < QF; i += kT) sQ[i] = Q[(size_t)f * QF + i];
   for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
   sched_fence();
   __syncthreads();
+  if (!live) return;
 
-  if (tid < ntp) {
-    R a[NP], b[NP], pv[M];
+  R a[N], b[N], pv[M];
 #pragma unroll
-    for (int n = 0; n < NP; ++n) {
-      a[n] = 0;
-      b[n] = 0;
-    }
+  for (int n = 0; n < N; ++n) {
+    a[n] = 0;
+    b[n] = 0;
+  }
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < L; ++l) {
 #pragma unroll
-      for (int mu = 0; mu < ML; ++mu) {
-        R zr = 0, zi = 0;
+    for (int mu = 0; mu < ML; ++mu) {
+      R zr = 0, zi = 0;
 #pragma unroll
-        for (int c = 0; c < ML; ++c) {
-          const cx<R> q = sQ[l * ML2 + mu * ML + c];
-          const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
-          zr += q.re * xr - q.im * xi;
-          zi += q.re * xi + q.im * xr;
-        }
-        const int m = l * ML + mu;
-        const R p = zr * zr + zi * zi;
-        pv[m] = p;
-        R y = 0;
-#pragma unroll
-        for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
-        const R iy = tid < nt ? rcp(rmax(y, (R)d.eps)) : (R)0;
-        const R piy2 = p * iy * iy;
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-          a[n] += sg[n * M + m] * piy2;
-          b[n] += sg[n * M + m] * iy;
-        }
+      for (int c = 0; c < ML; ++c) {
+        const cx<R> q = sQ[l * ML2 + mu * ML + c];
+        const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
+        zr += q.re * xr - q.im * xi;
+        zi += q.re * xi + q.im * xr;
       }
-    }
-    if (tid < nt) store16_nt<R, M>(P + ((size_t)f * T + t0 + tid) * M, pv);
+      const int m = l * ML + mu;
+      const R p = zr * zr + zi * zi;
+      pv[m] = p;
+      R y = 0;
 #pragma unroll
-    for (int i = 0; i < NP / E; ++i) {
-      vt va, vb;
+      for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
+      const R iy = rcp(rmax(y, (R)d.eps));
+      const R piy2 = p * iy * iy;
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        va[e] = a[i * E + e];
-        vb[e] = b[i * E + e];
+      for (int n = 0; n < N; ++n) {
+        a[n] += sg[n * M + m] * piy2;
+        b[n] += sg[n * M + m] * iy;
       }
-      reinterpret_cast<vt*>(sC + (size_t)tid * CP)[i] = va;
-      reinterpret_cast<vt*>(sC + (size_t)tid * CP + NP)[i] = vb;
     }
   }
-  __syncthreads();
-
-  R* out = Wpart + ((size_t)f * d.S + s) * NK * 2;
-  if constexpr (sizeof(R) == 4) {
-    constexpr int NI = S_::NI, KG = S_::KG;
-    typedef float v4f __attribute__((ext_vector_type(4)));
-    const int sub = lane & 3;
-    v4f acc[NI];
-    int hcol[NI], coff[NI];
-    bool aok[NI];
+  const int t = t0 + tid;
+  store16<R, M>(P + ((size_t)f * T + t) * M, pv);
 #pragma unroll
-    for (int q = 0; q < NI; ++q) {
-      acc[q] = v4f{0, 0, 0, 0};
-      const int blk = 16 * q + (lane >> 2), n = blk / KG;
-      aok[q] = blk < N * KG;
-      hcol[q] = aok[q] ? 64 * q + lane : 0;  // = n * K + 4 * (blk % KG) + sub
-      coff[q] = (aok[q] && sub < 2) ? sub * NP + n : -1;
-    }
-    const int half = ((ntp >> 1) + 3) & ~3;
-    const int fb = wave == 0 ? 0 : half, fe = wave == 0 ? min(half, ntp) : ntp;
-    const R* hbase = Ht + (size_t)t0 * NK;
-    for (int t4 = fb; t4 < fe; t4 += 4) {
-      R av[4][NI], bv[4][NI];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int tt = min(t4 + u, nt - 1);  // padding frames: any in-bounds row (their b is zero)
-#pragma unroll
-        for (int q = 0; q < NI; ++q) av[u][q] = hbase[(size_t)tt * NK + hcol[q]];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < NI; ++q) {
-          const R c = sC[(size_t)(t4 + u) * CP + (coff[q] < 0 ? 0 : coff[q])];
-          bv[u][q] = coff[q] < 0 ? (R)0 : c;
-        }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < NI; ++q) acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
-    }
-    if (wave == 1)
-#pragma unroll
-      for (int q = 0; q < NI; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sRed[(q * 64 + lane) * 4 + r] = acc[q][r];
-    __syncthreads();
-    if (wave == 0)
-#pragma unroll
-      for (int q = 0; q < NI; ++q) {
-        if (coff[q] < 0) continue;
-        const int blk = 16 * q + (lane >> 2), n = blk / KG, kg = blk - n * KG;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          out[(n * K + 4 * kg + r) * 2 + sub] = acc[q][r] + sRed[(q * 64 + lane) * 4 + r];
-      }
-  } else {
-    for (int o = tid; o < NK; o += kT) {
-      const int n = o / K;
-      R num = 0, den = 0;
-      for (int tt = 0; tt < nt; ++tt) {
-        const R h = Ht[(size_t)(t0 + tt) * NK + o];
-        num += h * sC[(size_t)tt * CP + n];
-        den += h * sC[(size_t)tt * CP + NP + n];
-      }
-      out[o * 2 + 0] = num;
-      out[o * 2 + 1] = den;
-    }
+  for (int n = 0; n < N; ++n) {
+    AB[((size_t)n * d.F + f) * d.TP + t] = a[n];
+    AB[((size_t)(N + n) * d.F + f) * d.TP + t] = b[n];
   }
 }
 
 // ------------------------------------------------------------------------------------
-// Activation update sums, eq. (9).  A workgroup of 4 waves covers kHCPW chunks of 16 bins
-// for one block of 16 frames.  Per chunk: lambda = W H by the matrix cores (each wave
-// holds the 16 x 16 tile in the accumulator layout); wave w then computes a' and b' of
-// eq. (9) for the (f, t) pair in accumulator row w of every lane (one pair per lane);
-// finally the sums over the chunk's bins, num/den[n][k][t] = sum_f W[n][f][k] (a', b'),
-// run on the matrix cores with the sources split across the waves.
-constexpr int kHCPW = 2;  // 16-bin chunks per activation workgroup
+// Sums over frames or frequencies of the coefficient planes on the 16x16x4 matrix cores,
+// with the multiplicative update applied in the same kernel.  A workgroup has kGW waves;
+// the contraction range is dealt out to the waves in chunks of 16 (four 4-deep steps).
+// Every operand a wave needs, for the sums and for the lambda tiles that follow the
+// update, is loaded in one batch of up to kGB chunks and kGB tiles; the waves'
+// accumulators are then summed in LDS in wave order.
+constexpr int kGW = 8;  // waves per workgroup
+constexpr int kGB = 6;  // chunks (and lambda tiles) per wave and load batch
 
-template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(256) void k_h_f(Dims d, const R* __restrict__ W, const R* __restrict__ H,
-                                             const R* __restrict__ g, const R* __restrict__ P,
-                                             R* __restrict__ Hpart) {
-  constexpr int M = ML * L, NK = N * K;
-  constexpr int KS = (K + 3) / 4;    // 4-deep steps over bases for lambda = W H
-  constexpr int KT = (K + 15) / 16;  // 16-row tiles of bases for the sum over bins
-  constexpr int NW = (N + 3) / 4;    // sources per wave in the sum over bins
-  typedef typename Mma<R>::v4 v4;
-  const int fg = blockIdx.x, tb = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int T = d.T, F = d.F;
-  const int t0 = tb * kHTB;
-  const int ntb = min(kHTB, T - t0);
-  const int cl = lane & 15, ck = lane >> 4;
-  extern __shared__ __align__(16) unsigned char smem[];
-  R* sHt = reinterpret_cast<R*>(smem);  // [NK][16]
-  R* sgc = sHt + NK * kHTB;             // [16 f][N*M]
-  R* sAB = sgc + 16 * N * M;            // [N][2][16 f][16 t]
-
-  for (int i = tid; i < NK * kHTB; i += 256) {
-    const int nk = i / kHTB, tl = i % kHTB;
-    sHt[i] = tl < ntb ? H[(size_t)nk * T + t0 + tl] : (R)0;
-  }
-  v4 accN[NW][KT], accD[NW][KT];
+// Wave sums -> LDS as red[wave][which][tile][row][col], rows/cols of the 16 x 16 tiles.
+template <typename R, int NT>
+__device__ __forceinline__ void spill_tiles(R* red, int wave, int lane, const typename Mma<R>::v4 (&accN)[NT],
+                                            const typename Mma<R>::v4 (&accD)[NT]) {
 #pragma unroll
-  for (int i = 0; i < NW; ++i)
+  for (int kt = 0; kt < NT; ++kt)
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) {
-      accN[i][kt] = v4{0, 0, 0, 0};
-      accD[i][kt] = v4{0, 0, 0, 0};
+    for (int r = 0; r < 4; ++r) {
+      const int row = Mma<R>::row(lane, r), col = lane & 15;
+      red[(((wave * 2 + 0) * NT + kt) * 16 + row) * 16 + col] = accN[kt][r];
+      red[(((wave * 2 + 1) * NT + kt) * 16 + row) * 16 + col] = accD[kt][r];
     }
+}
 
-  for (int c = 0; c < kHCPW; ++c) {
-    const int f0 = (fg * kHCPW + c) * 16;
-    const int nf = min(16, F - f0);
-    if (nf <= 0) break;  // uniform over the workgroup
-    // One batch: W operands of both contractions, g of the chunk, P of this lane's pair.
-    R wl[N][KS], wh[NW][KT][4], pv[M];
+template <typename R, int NT>
+__device__ __forceinline__ void sum_tiles(const R* red, int kt, int row, int col, R& num, R& den) {
+  num = 0;
+  den = 0;
 #pragma unroll
-    for (int n = 0; n < N; ++n)
+  for (int w = 0; w < kGW; ++w) {
+    num += red[(((w * 2 + 0) * NT + kt) * 16 + row) * 16 + col];
+    den += red[(((w * 2 + 1) * NT + kt) * 16 + row) * 16 + col];
+  }
+}
+
+// Bases update, eq. (8), for one source n and 16 bins: num/den[f][k] = sum_t (a, b)[f][t] H[k][t]
+// (rows f, columns k, contraction over frames), W <- W sqrt(num / max(den, eps)); then
+// lambda = W H for the new W at these bins and every frame (the H sums read it).
+template <typename R, int N, int K>
+__global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restrict__ AB, const R* __restrict__ Ht,
+                                                      R* __restrict__ W, R* __restrict__ lam,
+                                                      int* __restrict__ status) {
+  constexpr int NK = N * K, KT = (K + 15) / 16, KS = (K + 3) / 4;
+  static_assert(KT <= 2, "bases per source");
+  typedef typename Mma<R>::v4 v4;
+  typedef R v4r __attribute__((ext_vector_type(4)));
+  __shared__ R red[kGW * 2 * KT * 256];
+  __shared__ R sWn[16 * 4 * KS];  // new W of the 16 bins, [f][k], zero beyond K and F
+  const int n = blockIdx.x, f0 = blockIdx.y * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int T = d.T, F = d.F;
+  const int fr = min(f0 + i, F - 1);  // rows beyond F are computed on a valid row and dropped
+  const R* arow = AB + ((size_t)n * F + fr) * d.TP;
+  const R* brow = AB + ((size_t)(N + n) * F + fr) * d.TP;
+  const R* hcol = Ht + n * K;
+  const int nch = (T + 15) / 16;  // chunks of 16 frames = lambda tiles of 16 frames
+
+  v4 accN[KT], accD[KT];
 #pragma unroll
-      for (int st = 0; st < KS; ++st) {
-        const int k = 4 * st + ck;
-        wl[n][st] = (k < K && cl < nf) ? W[((size_t)n * F + f0 + cl) * K + k] : (R)0;
-      }
+  for (int kt = 0; kt < KT; ++kt) {
+    accN[kt] = v4{0, 0, 0, 0};
+    accD[kt] = v4{0, 0, 0, 0};
+  }
+  R hb[kGB][KS];  // B operands of this wave's lambda tiles (first batch)
+  for (int c0 = wave; c0 < nch; c0 += kGW * kGB) {
+    v4r av[kGB], bv[kGB];
+    R hv[kGB][KT][4];
 #pragma unroll
-    for (int i = 0; i < NW; ++i)
+    for (int u = 0; u < kGB; ++u) {
+      const int cc = min(c0 + u * kGW, nch - 1);
+      const int tq = cc * 16 + 4 * kk;  // step s covers frame tq + s
+      av[u] = *reinterpret_cast<const v4r*>(arow + tq);
+      bv[u] = *reinterpret_cast<const v4r*>(brow + tq);
 #pragma unroll
       for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
-          const int n = wave + 4 * i, fl = 4 * st + ck, k = kt * 16 + cl;
-          wh[i][kt][st] = (n < N && k < K && fl < nf) ? W[((size_t)n * F + f0 + fl) * K + k] : (R)0;
+          const int k = kt * 16 + i, t = min(tq + st, T - 1);
+          hv[u][kt][st] = hcol[(size_t)t * NK + (k < K ? k : 0)];
         }
-    const int fl = Mma<R>::row(lane, wave);
-    const bool pair_ok = fl < nf && cl < ntb;
-    if (pair_ok) {
-      load16<R, M>(pv, P + ((size_t)(f0 + fl) * T + t0 + cl) * M);
-    } else {
+      if (c0 == wave) {
+        const int t = min(cc * 16 + i, T - 1);
 #pragma unroll
-      for (int m = 0; m < M; ++m) pv[m] = 0;
-    }
-    for (int i = tid; i < 16 * N * M; i += 256) {
-      const int fi = i / (N * M);
-      sgc[i] = fi < nf ? g[(size_t)(f0 + fi) * N * M + i % (N * M)] : (R)0;
+        for (int st = 0; st < KS; ++st) {
+          const int k = 4 * st + kk;
+          hb[u][st] = hcol[(size_t)t * NK + (k < K ? k : 0)];
+        }
+      }
     }
     sched_fence();
-    __syncthreads();  // sHt (first chunk), sgc
-    // lambda for the lane's pair (accumulator row `wave`).
-    R lam[N];
 #pragma unroll
-    for (int n = 0; n < N; ++n) {
+    for (int u = 0; u < kGB; ++u) {
+      const int c = c0 + u * kGW;
+      const int tq = c * 16 + 4 * kk;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const bool ok = c < nch && tq + st < T;
+        const R a = ok ? av[u][st] : (R)0, b = ok ? bv[u][st] : (R)0;
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const R h = kt * 16 + i < K ? hv[u][kt][st] : (R)0;
+          accN[kt] = Mma<R>::run(a, h, accN[kt]);
+          accD[kt] = Mma<R>::run(b, h, accD[kt]);
+        }
+      }
+    }
+  }
+  spill_tiles<R, KT>(red, wave, lane, accN, accD);
+  __syncthreads();
+  for (int e = tid; e < 16 * 4 * KS; e += 64 * kGW) {
+    const int fi = e / (4 * KS), k = e - fi * (4 * KS), f = f0 + fi;
+    R w = 0;
+    if (k < K && f < F) {
+      R num, den;
+      sum_tiles<R, KT>(red, k >> 4, fi, k & 15, num, den);
+      const size_t idx = ((size_t)n * F + f) * K + k;
+      w = W[idx] * sqrt(num / rmax(den, (R)d.eps));
+      if (!isfinite(w)) atomicOr(status, kStNonFinite);
+      W[idx] = w;
+    }
+    sWn[e] = w;
+  }
+  __syncthreads();
+
+  // lambda[f][n][t] for the 16 bins: rows f (A = new W from LDS), columns t (B = H), over k.
+  R wa[KS];
+#pragma unroll
+  for (int st = 0; st < KS; ++st) wa[st] = sWn[i * 4 * KS + 4 * st + kk];
+  for (int c0 = wave; c0 < nch; c0 += kGW * kGB) {
+    if (c0 != wave) {  // batches after the first (more than kGW * kGB tiles)
+#pragma unroll
+      for (int u = 0; u < kGB; ++u) {
+        const int t = min(min(c0 + u * kGW, nch - 1) * 16 + i, T - 1);
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+          const int k = 4 * st + kk;
+          hb[u][st] = hcol[(size_t)t * NK + (k < K ? k : 0)];
+        }
+      }
+      sched_fence();
+    }
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int c = c0 + u * kGW;
+      if (c >= nch) break;
       v4 acc = {0, 0, 0, 0};
 #pragma unroll
-      for (int st = 0; st < KS; ++st) {
-        const int k = 4 * st + ck;
-        const R bv = k < K ? sHt[(n * K + k) * kHTB + cl] : (R)0;
-        acc = Mma<R>::run(wl[n][st], bv, acc);
-      }
-      lam[n] = acc[0];
+      for (int st = 0; st < KS; ++st) acc = Mma<R>::run(wa[st], 4 * st + kk < K ? hb[u][st] : (R)0, acc);
+      const int t = c * 16 + i;
+      if (t < T)
 #pragma unroll
-      for (int r = 1; r < 4; ++r)
-        if (wave == r) lam[n] = acc[r];
-    }
-    R a[N], b[N];
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-      a[n] = 0;
-      b[n] = 0;
-    }
-    if (pair_ok) {
-      const R* gf = sgc + fl * N * M;
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        R y = 0;
-#pragma unroll
-        for (int n = 0; n < N; ++n) y += lam[n] * gf[n * M + m];
-        const R iy = rcp(rmax(y, (R)d.eps));
-        const R piy2 = pv[m] * iy * iy;
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-          a[n] += gf[n * M + m] * piy2;
-          b[n] += gf[n * M + m] * iy;
+        for (int r = 0; r < 4; ++r) {
+          const int f = f0 + Mma<R>::row(lane, r);
+          if (f < F) lam[((size_t)f * N + n) * T + t] = acc[r];
         }
-      }
     }
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-      sAB[((n * 2 + 0) * 16 + fl) * 16 + cl] = a[n];
-      sAB[((n * 2 + 1) * 16 + fl) * 16 + cl] = b[n];
-    }
-    __syncthreads();
-    // num/den for this wave's sources: A = W^T (rows k), B = a'/b' (columns t).
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      const int n = wave + 4 * i;
-      if (n < N) {
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-          for (int st = 0; st < 4; ++st) {
-            const int fb = 4 * st + ck;
-            accN[i][kt] = Mma<R>::run(wh[i][kt][st], sAB[((n * 2 + 0) * 16 + fb) * 16 + cl], accN[i][kt]);
-            accD[i][kt] = Mma<R>::run(wh[i][kt][st], sAB[((n * 2 + 1) * 16 + fb) * 16 + cl], accD[i][kt]);
-          }
-      }
-    }
-    __syncthreads();  // before the next chunk overwrites sgc / sAB
   }
-  // This workgroup's partial for its frequency group: lane holds rows k = row(lane, r).
+}
+
+// Per-bin coefficients of eq. (9) with lambda for the new W: a'_n = sum_m g_nm P_m / y_m^2,
+// b'_n = sum_m g_nm / y_m, written as planes for the sums over frequencies in k_hgemm_f.
+template <typename R, int N, int K, int ML, int L>
+__global__ __launch_bounds__(kT) void k_h_f(Dims d, const R* __restrict__ lamin, const R* __restrict__ g,
+                                            const R* __restrict__ P, R* __restrict__ AB) {
+  constexpr int M = ML * L;
+  static_assert(M % V16<R>::E == 0, "rows must fill 16-byte vectors");
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int T = d.T;
+  const int t0 = s * d.SL;
+  const int nt = min(d.SL, T - t0);
+  __shared__ R sg[N * M];
+  R pv[M], lam[N];
+  const bool live = tid < nt;
+  if (live) {
+    load16<R, M>(pv, P + ((size_t)f * T + t0 + tid) * M);
 #pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    const int n = wave + 4 * i;
-    if (n >= N || cl >= ntb) continue;
+    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
+  }
+  for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
+  sched_fence();
+  __syncthreads();
+  if (!live) return;
+  R a[N], b[N];
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
+  for (int n = 0; n < N; ++n) {
+    a[n] = 0;
+    b[n] = 0;
+  }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = kt * 16 + Mma<R>::row(lane, r);
-        if (k < K) {
-          R* dst = Hpart + (((size_t)fg * NK + n * K + k) * T + t0 + cl) * 2;
-          dst[0] = accN[i][kt][r];
-          dst[1] = accD[i][kt][r];
+  for (int m = 0; m < M; ++m) {
+    R y = 0;
+#pragma unroll
+    for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
+    const R iy = rcp(rmax(y, (R)d.eps));
+    const R piy2 = pv[m] * iy * iy;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      a[n] += sg[n * M + m] * piy2;
+      b[n] += sg[n * M + m] * iy;
+    }
+  }
+  const int t = t0 + tid;
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    AB[((size_t)n * d.F + f) * d.TP + t] = a[n];
+    AB[((size_t)(N + n) * d.F + f) * d.TP + t] = b[n];
+  }
+}
+
+// Activation update, eq. (9), for one source n and 16 frames: num/den[k][t] = sum_f W[f][k]
+// (a', b')[f][t] (rows k, columns t, contraction over bins), H <- H sqrt(num / max(den, eps))
+// (H and its frame-major copy); then lambda = W H for the new H at these frames and every
+// bin (the g sums and the next iteration read it).
+template <typename R, int N, int K>
+__global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restrict__ W, const R* __restrict__ AB,
+                                                      R* __restrict__ H, R* __restrict__ Ht, R* __restrict__ lam,
+                                                      int* __restrict__ status) {
+  constexpr int NK = N * K, KT = (K + 15) / 16, KS = (K + 3) / 4;
+  static_assert(KT <= 2, "bases per source");
+  typedef typename Mma<R>::v4 v4;
+  __shared__ R red[kGW * 2 * KT * 256];
+  __shared__ R sHn[4 * KS * 16];  // new H of the 16 frames, [k][t], zero beyond K and T
+  const int n = blockIdx.x, t0 = blockIdx.y * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int T = d.T, F = d.F;
+  const R* ap = AB + (size_t)n * F * d.TP + t0 + i;
+  const R* bp = AB + (size_t)(N + n) * F * d.TP + t0 + i;
+  const R* wp = W + (size_t)n * F * K;
+  const int nch = (F + 15) / 16;  // chunks of 16 bins = lambda tiles of 16 bins
+
+  v4 accN[KT], accD[KT];
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt) {
+    accN[kt] = v4{0, 0, 0, 0};
+    accD[kt] = v4{0, 0, 0, 0};
+  }
+  R wl[kGB][KS];  // A operands of this wave's lambda tiles (first batch)
+  for (int c0 = wave; c0 < nch; c0 += kGW * kGB) {
+    R wa[kGB][KT][4], av[kGB][4], bv[kGB][4];
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int cc = min(c0 + u * kGW, nch - 1);
+      const int fq = cc * 16 + 4 * kk;  // step s covers bin fq + s
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int f = min(fq + st, F - 1);
+        av[u][st] = ap[(size_t)f * d.TP];
+        bv[u][st] = bp[(size_t)f * d.TP];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const int k = kt * 16 + i;
+          wa[u][kt][st] = wp[(size_t)f * K + (k < K ? k : 0)];
         }
       }
+      if (c0 == wave) {
+        const int f = min(cc * 16 + i, F - 1);
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+          const int k = 4 * st + kk;
+          wl[u][st] = wp[(size_t)f * K + (k < K ? k : 0)];
+        }
+      }
+    }
+    sched_fence();
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int c = c0 + u * kGW;
+      const int fq = c * 16 + 4 * kk;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const bool ok = c < nch && fq + st < F;
+        const R a = ok ? av[u][st] : (R)0, b = ok ? bv[u][st] : (R)0;
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const R w = kt * 16 + i < K ? wa[u][kt][st] : (R)0;
+          accN[kt] = Mma<R>::run(w, a, accN[kt]);
+          accD[kt] = Mma<R>::run(w, b, accD[kt]);
+        }
+      }
+    }
+  }
+  spill_tiles<R, KT>(red, wave, lane, accN, accD);
+  __syncthreads();
+  for (int e = tid; e < 4 * KS * 16; e += 64 * kGW) {
+    const int k = e >> 4, tl = e & 15, t = t0 + tl;
+    R h = 0;
+    if (k < K && t < T) {
+      R num, den;
+      sum_tiles<R, KT>(red, k >> 4, k & 15, tl, num, den);
+      const size_t idx = ((size_t)n * K + k) * T + t;
+      h = H[idx] * sqrt(num / rmax(den, (R)d.eps));
+      if (!isfinite(h)) atomicOr(status, kStNonFinite);
+      H[idx] = h;
+      Ht[(size_t)t * NK + n * K + k] = h;
+    }
+    sHn[e] = h;
+  }
+  __syncthreads();
+
+  // lambda[f][n][t] for the 16 frames: rows f (A = W), columns t (B = new H from LDS), over k.
+  R hb[KS];
+#pragma unroll
+  for (int st = 0; st < KS; ++st) hb[st] = sHn[(4 * st + kk) * 16 + i];
+  for (int c0 = wave; c0 < nch; c0 += kGW * kGB) {
+    if (c0 != wave) {  // batches after the first (more than kGW * kGB tiles)
+#pragma unroll
+      for (int u = 0; u < kGB; ++u) {
+        const int f = min(min(c0 + u * kGW, nch - 1) * 16 + i, F - 1);
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+          const int k = 4 * st + kk;
+          wl[u][st] = wp[(size_t)f * K + (k < K ? k : 0)];
+        }
+      }
+      sched_fence();
+    }
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int c = c0 + u * kGW;
+      if (c >= nch) break;
+      v4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int st = 0; st < KS; ++st) acc = Mma<R>::run(4 * st + kk < K ? wl[u][st] : (R)0, hb[st], acc);
+      const int t = t0 + i;
+      if (t < T)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int f = c * 16 + Mma<R>::row(lane, r);
+          if (f < F) lam[((size_t)f * N + n) * T + t] = acc[r];
+        }
+    }
   }
 }
 
@@ -1108,22 +1131,11 @@ struct Set {
     const size_t red = G::kBlocks ? (size_t)G::NG * 64 * 4 : 0;  // cross-wave sums reuse the rows
     return align_up(sizeof(R) * N * M, 16) + sizeof(R) * (rows > red ? rows : red);
   }
-  static size_t smem_pw(const Dims& d) {
-    typedef PwShape<R, N, K, ML, L> S_;
-    return align_up(sizeof(cx<R>) * S_::QF, 16) + align_up(sizeof(R) * N * M, 16) +
-           sizeof(R) * ((size_t)d.SLP * S_::CP + S_::NI * 256);
-  }
-  static size_t smem_h(const Dims&) { return sizeof(R) * (N * K * kHTB + 16 * N * M + N * 2 * 256); }
   static size_t smem_g(const Dims& d) {
     typedef GShape<R, N, K, ML, L> G;
     return align_up(sizeof(R) * N * M, 16) + sizeof(R) * ((size_t)d.SLP * (G::AP + G::BP) + G::NI * 256);
   }
-  static size_t max_smem(const Dims& d) {
-    size_t m = smem_gram(d);
-    m = smem_pw(d) > m ? smem_pw(d) : m;
-    m = smem_h(d) > m ? smem_h(d) : m;
-    return smem_g(d) > m ? smem_g(d) : m;
-  }
+  static size_t max_smem(const Dims& d) { return smem_gram(d) > smem_g(d) ? smem_gram(d) : smem_g(d); }
 
   static hipError_t launch(const Dims& d, const Buffers& b, int kid, hipStream_t s) {
     const cx<R>* X = static_cast<const cx<R>*>(b.X);
@@ -1136,11 +1148,6 @@ struct Set {
       case kFHt:
         hipLaunchKernelGGL((k_ht_f<R, N * K>), dim3((d.T + kT - 1) / kT), dim3(kT), 0, s, d, H,
                            static_cast<R*>(b.Ht));
-        break;
-      case kFHApply:
-        hipLaunchKernelGGL((k_happly_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kLamWaves), 0, s, d, W, H,
-                           static_cast<R*>(b.Ht), static_cast<const R*>(b.Hpart), static_cast<R*>(b.lam),
-                           b.status);
         break;
       case kFLam:
         hipLaunchKernelGGL((k_lam_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kLamWaves), 0, s, d, W, H,
@@ -1159,13 +1166,21 @@ struct Set {
         }
         break;
       case kFPw:
-        hipLaunchKernelGGL((k_pw_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_pw(d), s, d, X, Q,
-                           static_cast<const R*>(b.lam), static_cast<const R*>(b.Ht), g, P,
-                           static_cast<R*>(b.Wpart));
+        hipLaunchKernelGGL((k_pw_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), 0, s, d, X, Q,
+                           static_cast<const R*>(b.lam), g, P, static_cast<R*>(b.AB));
+        break;
+      case kFWGemm:
+        hipLaunchKernelGGL((k_wgemm_f<R, N, K>), dim3(N, (d.F + 15) / 16), dim3(64 * kGW), 0, s, d,
+                           static_cast<const R*>(b.AB), static_cast<const R*>(b.Ht), W, static_cast<R*>(b.lam),
+                           b.status);
         break;
       case kFH:
-        hipLaunchKernelGGL((k_h_f<R, N, K, ML, L>), dim3(d.FG, d.TBN), dim3(256), smem_h(d), s, d, W, H, g, P,
-                           static_cast<R*>(b.Hpart));
+        hipLaunchKernelGGL((k_h_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), 0, s, d,
+                           static_cast<const R*>(b.lam), g, P, static_cast<R*>(b.AB));
+        break;
+      case kFHGemm:
+        hipLaunchKernelGGL((k_hgemm_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kGW), 0, s, d, W,
+                           static_cast<const R*>(b.AB), H, static_cast<R*>(b.Ht), static_cast<R*>(b.lam), b.status);
         break;
       case kFG:
         hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_g(d), s, d,
@@ -1191,8 +1206,6 @@ int fast_set_index(int N, int K, int ML, int L) {
 #undef DFM_MATCH
   return -1;
 }
-
-int fast_h_chunks() { return fast::kHCPW; }
 
 size_t fast_max_smem(const Dims& d, int dtype) {
   switch (d.fast) {

@@ -32,7 +32,7 @@ struct Dims {
   int fast;  // index of the shape-specialised kernel set, or -1 for the generic kernels
   int ML;    // common subarray size when the partition is uniform, else 0
   int SLP;   // LDS row stride (elements) of per-frame arrays in the specialised kernels
-  int FG;    // frequency groups of the specialised activation kernel
+  int TP;    // frames rounded up to 16: row length of the coefficient planes (specialised kernels)
   int mics[kMaxL];  // M_l
   int moff[kMaxL];  // first mic of subarray l
   int qoff[kMaxL];  // offset of block l in a frequency's packed Q (complex units)
@@ -49,26 +49,26 @@ struct Buffers {
   void* H;
   void* P;       // [F][T][M] real: |Q x|^2 of the latest W sub-step
   void* Vpart;   // [F][S][VF] real: per-slice packed covariance sums
-  void* Wpart;   // [F][S][N][K][2] real
-  void* Hpart;   // [FS][N][K][T][2] real
+  void* Wpart;   // [F][S][N][K][2] real (generic kernels)
+  void* Hpart;   // [FS][N][K][T][2] real (generic kernels)
   void* gpart;   // [F][S][N][M][2] real
   double* logdet;   // [F][L]
   double* nllpart;  // [F][S]
   void* Qinv;       // [F][QF] complex double
   int* status;      // sticky status word
-  unsigned* counters;  // last-arrival counters (unused by the current kernel sets)
   void* lam;           // [F][N][T] real: lambda = W H of the specialised kernels
   void* Ht;            // [T][N*K] real: frame-major copy of H of the specialised kernels
+  void* AB;            // [2N][F][TP] real: per-bin MM coefficients of the specialised kernels
 };
 
 size_t workspace_bytes(const Dims& d, int dtype);
 void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 
-// Kernels.  Generic path: eight per iteration; specialised path: five kF* plus the
-// three apply kernels of the generic path.
+// Kernels.  Generic path: eight per iteration; specialised path: seven kF* plus the g
+// apply kernel of the generic path (kFLam and kFHt seed lambda and the copy of H).
 enum KernelId {
   kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply,
-  kFGram, kFIp, kFPw, kFH, kFG, kFLam, kFHt, kFHApply, kNumKernels
+  kFGram, kFIp, kFPw, kFWGemm, kFH, kFHGemm, kFG, kFLam, kFHt, kNumKernels
 };
 
 // Launchers (return hipSuccess or the first launch error).
@@ -81,7 +81,6 @@ int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns 
 // Shape-specialised kernel sets (dfm_fast.hip).
 int fast_set_index(int N, int K, int ML, int L);
 size_t fast_max_smem(const Dims& d, int dtype);
-int fast_h_chunks();
 hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s);
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);

@@ -670,8 +670,6 @@ static hipError_t cov_impl(const Dims& d, const Buffers& b, void* V, hipStream_t
 
 hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.status, 16);
-  const int nc = 3 * d.F + d.TBN;
-  hipLaunchKernelGGL(k_zero_int, dim3(cdiv(nc, kBlock)), dim3(kBlock), 0, s, reinterpret_cast<int*>(b.counters), nc);
   return hipGetLastError();
 }
 
@@ -681,9 +679,10 @@ hipError_t launch_kernel(const Dims& d, const Buffers& b, int dtype, int kid, hi
 }
 
 const char* kernel_name(int kid) {
-  static const char* names[kNumKernels] = {"k_gram", "k_ip",   "k_pw",   "k_wapply", "k_h", "k_happly",
-                                           "k_g",    "k_gapply", "k_gram_f", "k_ip_f", "k_pw_f", "k_h_f",
-                                           "k_g_f",  "k_lam_f",  "k_ht_f",   "k_happly_f"};
+  static const char* names[kNumKernels] = {"k_gram",   "k_ip",    "k_pw",    "k_wapply",  "k_h",
+                                           "k_happly", "k_g",     "k_gapply", "k_gram_f", "k_ip_f",
+                                           "k_pw_f",   "k_wgemm_f", "k_h_f",  "k_hgemm_f", "k_g_f",
+                                           "k_lam_f",  "k_ht_f"};
   return kid >= 0 && kid < kNumKernels ? names[kid] : nullptr;
 }
 
@@ -692,8 +691,8 @@ int stage_kernels(const Dims& d, int stage, int* kids) {
   if (d.fast >= 0) {
     switch (stage) {
       case DFM_STAGE_IP: kids[0] = kFGram; kids[1] = kFIp; return 2;
-      case DFM_STAGE_W: kids[0] = kFPw; kids[1] = kKWApply; return 2;
-      case DFM_STAGE_H: kids[0] = kFH; kids[1] = kFHApply; return 2;
+      case DFM_STAGE_W: kids[0] = kFPw; kids[1] = kFWGemm; return 2;
+      case DFM_STAGE_H: kids[0] = kFH; kids[1] = kFHGemm; return 2;
       case DFM_STAGE_G: kids[0] = kFG; kids[1] = kKGApply; return 2;
     }
     return 0;
