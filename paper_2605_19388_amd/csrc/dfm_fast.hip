@@ -79,153 +79,208 @@ __device__ __forceinline__ void store16(R* dst, const R (&src)[C]) {
 }
 
 // ------------------------------------------------------------------------------------
-// FP64 IP sweep of one subarray block (M_l <= 4), eqs. (15)-(16), by one lane.  The lane's
-// Q_fl and the covariance of the current row live in LDS slots laid out element-major,
-// lane-minor (element e of lane i at e * 64 + i, so a wave's accesses are conflict-free);
-// the system A = Q V_mu is eliminated in registers.
-// vp: packed slice sums of the block, [slice (stride vstride)][mu][M_l^2]; V = sum / T.
-template <typename R, int ML>
-__device__ void ip_sweep_lane(const R* vp, size_t vstride, int S, double invT, cd* q, cd* v, double eps,
-                              int* status) {
-  constexpr int ML2 = ML * ML;
-#define QS(r, c) q[((r) * ML + (c)) * 64]
-#define VS(r, c) v[((r) * ML + (c)) * 64]
+// FP64 IP sweep (eqs. (15)-(16)) for subarrays of M_l <= 4 mics, M_l lanes per (f, l) block.
+//
+// (Q V_mu) b = e_mu is solved as V_mu b = c with c = Q^{-1} e_mu (the same system, since Q is
+// nonsingular), so the M_l factorisations of V_mu (Hermitian positive definite: no
+// pivoting) do not depend on the sweep and run on the block's lanes side by side; lane r
+// factorises V_r and owns column r of Q^{-1}.  Row mu
+// then takes one solve on lane mu, the normalisation s = b^H V b = d^H c (eq. (16)), and a
+// rank-1 update of Q^{-1} on every lane: with row mu of Q replaced by b^H,
+//   Q^{-1} <- Q^{-1} - c (b^H Q^{-1} - e_mu^T) / (b^H c),
+// where b^H c = det(Q_new) / det(Q_old), so ln|det Q_fl| for the cost (13) is the log of
+// the pivots of Q plus the sum of ln|b^H c| over the rows.  A zero pivot (V_mu or Q
+// singular) keeps the row and sets the sticky singular flag.
+
+// LU factorisation without pivoting of a Hermitian positive (semi)definite n x n matrix in
+// registers (L unit lower, U upper; inverse pivots of U in dinv).  Elimination without
+// row exchanges is stable for such matrices; a zero pivot (a singular covariance, e.g. a
+// silent mic) returns false.
+template <int n>
+__device__ __forceinline__ bool hpd_factor(cd (&A)[n][n], cd (&dinv)[n]) {
+  bool ok = true;
 #pragma unroll
-  for (int mu = 0; mu < ML; ++mu) {
-    double vs[ML2];
+  for (int p = 0; p < n; ++p) {
+    const bool zero = cabs2(A[p][p]) == 0.0;
+    if (zero) ok = false;
+    dinv[p] = zero ? cd{0.0, 0.0} : cinv(A[p][p]);
 #pragma unroll
-    for (int j = 0; j < ML2; ++j) vs[j] = 0.0;
-    for (int s = 0; s < S; ++s) {
-      R part[ML2];
+    for (int r = p + 1; r < n; ++r) {
+      const cd fac = cmul(A[r][p], dinv[p]);
+      A[r][p] = fac;
 #pragma unroll
-      for (int j = 0; j < ML2; ++j) part[j] = vp[s * vstride + mu * ML2 + j];
-#pragma unroll
-      for (int j = 0; j < ML2; ++j) vs[j] += (double)part[j];
+      for (int c = p + 1; c < n; ++c) A[r][c] = csub(A[r][c], cmul(fac, A[p][c]));
     }
-#pragma unroll
-    for (int j = 0; j < ML2; ++j) {
-      int a, b, part;
-      packed_pair(ML, j, a, b, part);
-      const double val = vs[j] * invT;
-      if (a == b) {
-        VS(a, a) = {val, 0.0};
-      } else if (part == 0) {
-        VS(a, b).re = val;
-        VS(b, a).re = val;
-      } else {
-        VS(a, b).im = val;
-        VS(b, a).im = -val;
-      }
-    }
-    cd A[ML][ML + 1];
-#pragma unroll
-    for (int r = 0; r < ML; ++r) {
-#pragma unroll
-      for (int c = 0; c < ML; ++c) {
-        cd acc = {0.0, 0.0};
-#pragma unroll
-        for (int j = 0; j < ML; ++j) acc = cadd(acc, cmul(QS(r, j), VS(j, c)));
-        A[r][c] = acc;
-      }
-      A[r][ML] = {r == mu ? 1.0 : 0.0, 0.0};
-    }
-    bool sing = false;
-#pragma unroll
-    for (int p = 0; p < ML; ++p) {
-      int piv = p;
-      double best = cabs2(A[p][p]);
-#pragma unroll
-      for (int r = p + 1; r < ML; ++r) {
-        const double val = cabs2(A[r][p]);
-        if (val > best) {
-          best = val;
-          piv = r;
-        }
-      }
-#pragma unroll
-      for (int r = p + 1; r < ML; ++r) {
-        const bool sw = piv == r;
-#pragma unroll
-        for (int c = p; c <= ML; ++c) {
-          const cd tp = A[p][c], tr = A[r][c];
-          A[p][c] = sw ? tr : tp;
-          A[r][c] = sw ? tp : tr;
-        }
-      }
-      if (best == 0.0) sing = true;
-      const cd inv = best == 0.0 ? cd{0.0, 0.0} : cinv(A[p][p]);
-#pragma unroll
-      for (int r = p + 1; r < ML; ++r) {
-        const cd fac = cmul(A[r][p], inv);
-#pragma unroll
-        for (int c = p + 1; c <= ML; ++c) A[r][c] = csub(A[r][c], cmul(fac, A[p][c]));
-      }
-    }
-    if (sing) {
-      atomicOr(status, kStSingular);  // row kept; reported as DFM_E_SINGULAR
-      continue;
-    }
-    cd bsol[ML];
-#pragma unroll
-    for (int r = ML - 1; r >= 0; --r) {
-      cd acc = A[r][ML];
-#pragma unroll
-      for (int c = r + 1; c < ML; ++c) acc = csub(acc, cmul(A[r][c], bsol[c]));
-      bsol[r] = cmul(acc, cinv(A[r][r]));
-    }
-    double sv = 0.0;
-#pragma unroll
-    for (int a = 0; a < ML; ++a) {
-      cd vb = {0.0, 0.0};
-#pragma unroll
-      for (int b = 0; b < ML; ++b) vb = cadd(vb, cmul(VS(a, b), bsol[b]));
-      sv += bsol[a].re * vb.re + bsol[a].im * vb.im;
-    }
-    const double sc = 1.0 / sqrt(sv > eps ? sv : eps);
-#pragma unroll
-    for (int c = 0; c < ML; ++c) QS(mu, c) = {bsol[c].re * sc, -bsol[c].im * sc};
   }
-#undef QS
-#undef VS
+  return ok;
 }
 
-// ln|det| of an M_l x M_l complex matrix by elimination with partial pivoting, in registers.
-template <int ML>
-__device__ double logabsdet_lane(cd (&A)[ML][ML]) {
-  double acc = 0.0;
+// x <- A^{-1} x for the factors of hpd_factor.
+template <int n>
+__device__ __forceinline__ void hpd_solve(const cd (&A)[n][n], const cd (&dinv)[n], cd (&x)[n]) {
 #pragma unroll
-  for (int p = 0; p < ML; ++p) {
-    int piv = p;
+  for (int r = 1; r < n; ++r)
+#pragma unroll
+    for (int c = 0; c < r; ++c) x[r] = csub(x[r], cmul(A[r][c], x[c]));
+#pragma unroll
+  for (int r = n - 1; r >= 0; --r) {
+#pragma unroll
+    for (int c = r + 1; c < n; ++c) x[r] = csub(x[r], cmul(A[r][c], x[c]));
+    x[r] = cmul(x[r], dinv[r]);
+  }
+}
+
+// Column `col` of A^{-1} and ln|det A| by elimination of [A | e_col] with partial pivoting
+// (rows exchanged over the active columns only).  Returns false on a zero pivot.
+template <int n>
+__device__ __forceinline__ bool inverse_column(cd (&A)[n][n + 1], int col, cd (&x)[n], double& logabs) {
+  bool ok = true;
+  logabs = 0.0;
+#pragma unroll
+  for (int r = 0; r < n; ++r) A[r][n] = {r == col ? 1.0 : 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < n; ++p) {
+    int pr = p;
     double best = cabs2(A[p][p]);
 #pragma unroll
-    for (int r = p + 1; r < ML; ++r) {
+    for (int r = p + 1; r < n; ++r) {
       const double v = cabs2(A[r][p]);
       if (v > best) {
         best = v;
-        piv = r;
+        pr = r;
       }
     }
 #pragma unroll
-    for (int r = p + 1; r < ML; ++r) {
-      const bool sw = piv == r;
+    for (int r = p + 1; r < n; ++r) {
+      const bool sw = pr == r;
 #pragma unroll
-      for (int c = p; c < ML; ++c) {
+      for (int c = p; c <= n; ++c) {
         const cd tp = A[p][c], tr = A[r][c];
         A[p][c] = sw ? tr : tp;
         A[r][c] = sw ? tp : tr;
       }
     }
-    if (best == 0.0) return -INFINITY;
-    acc += 0.5 * log(best);
-    const cd inv = cinv(A[p][p]);
+    if (best == 0.0) ok = false;
+    logabs += best == 0.0 ? 0.0 : 0.5 * log(best);
+    const cd inv = best == 0.0 ? cd{0.0, 0.0} : cinv(A[p][p]);
 #pragma unroll
-    for (int r = p + 1; r < ML; ++r) {
+    for (int r = p + 1; r < n; ++r) {
       const cd fac = cmul(A[r][p], inv);
 #pragma unroll
-      for (int c = p + 1; c < ML; ++c) A[r][c] = csub(A[r][c], cmul(fac, A[p][c]));
+      for (int c = p + 1; c <= n; ++c) A[r][c] = csub(A[r][c], cmul(fac, A[p][c]));
     }
   }
-  return acc;
+#pragma unroll
+  for (int r = n - 1; r >= 0; --r) {
+    cd acc = A[r][n];
+#pragma unroll
+    for (int c = r + 1; c < n; ++c) acc = csub(acc, cmul(A[r][c], x[c]));
+    x[r] = cabs2(A[r][r]) == 0.0 ? cd{0.0, 0.0} : cmul(acc, cinv(A[r][r]));
+  }
+  return ok;
+}
+
+template <typename R, int ML>
+__global__ __launch_bounds__(64) void k_ip_f(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict__ Q,
+                                             double* __restrict__ logdet, int* __restrict__ status) {
+  constexpr int ML2 = ML * ML, BPW = 64 / ML;  // blocks per wave
+  static_assert(ML >= 1 && ML <= 4 && 64 % ML == 0, "lanes per block");
+  __shared__ cd sB[BPW][ML], sC[BPW][ML], sW[BPW];
+  __shared__ int sOk[BPW];
+  const int lane = threadIdx.x, blk = lane / ML, r = lane - blk * ML;
+  const int idx = blockIdx.x * BPW + blk;
+  const bool live = idx < d.F * d.L;
+  const int f = live ? idx / d.L : 0, l = live ? idx - f * d.L : 0;
+
+  // V_r = (sum over slices) / T, Hermitian from its packed entries.
+  cd V[ML][ML];
+  {
+    double vs[ML2];
+#pragma unroll
+    for (int j = 0; j < ML2; ++j) vs[j] = 0.0;
+    const R* vp = Vpart + (size_t)f * d.S * d.VF + (size_t)l * ML * ML2 + r * ML2;
+    for (int s = 0; s < d.S; ++s) {
+      R part[ML2];
+#pragma unroll
+      for (int j = 0; j < ML2; ++j) part[j] = vp[(size_t)s * d.VF + j];
+#pragma unroll
+      for (int j = 0; j < ML2; ++j) vs[j] += (double)part[j];
+    }
+    // Packed order: the M_l diagonal entries, then (Re, Im) of V[a][b], a < b, row-major.
+    const double invT = 1.0 / d.T;
+#pragma unroll
+    for (int a = 0; a < ML; ++a) {
+      V[a][a] = {vs[a] * invT, 0.0};
+#pragma unroll
+      for (int b = a + 1; b < ML; ++b) {
+        const int j = ML + 2 * (a * ML - a * (a + 1) / 2 + (b - a - 1));
+        V[a][b] = {vs[j] * invT, vs[j + 1] * invT};
+        V[b][a] = {vs[j] * invT, -vs[j + 1] * invT};
+      }
+    }
+  }
+  cd vdinv[ML];
+  const bool vok = hpd_factor<ML>(V, vdinv);
+
+  // Q_fl (every lane of the block), column r of its inverse, ln|det Q_fl|.
+  cx<R>* qb = Q + (size_t)f * d.QF + l * ML2;
+  cd A[ML][ML + 1], row[ML];
+#pragma unroll
+  for (int a = 0; a < ML; ++a)
+#pragma unroll
+    for (int c = 0; c < ML; ++c) {
+      const cx<R> v = qb[a * ML + c];
+      A[a][c] = {(double)v.re, (double)v.im};
+    }
+#pragma unroll
+  for (int c = 0; c < ML; ++c) {
+    const cx<R> v = qb[r * ML + c];  // this lane's row (r is not a compile-time index)
+    row[c] = {(double)v.re, (double)v.im};
+  }
+  cd ci[ML];
+  double ld;
+  const bool qok = inverse_column<ML>(A, r, ci, ld);
+
+#pragma unroll
+  for (int mu = 0; mu < ML; ++mu) {
+    if (r == mu) {
+      const bool ok = vok && qok;
+      cd dv[ML];
+#pragma unroll
+      for (int k = 0; k < ML; ++k) dv[k] = ci[k];
+      hpd_solve<ML>(V, vdinv, dv);
+      cd dc = {0.0, 0.0};  // d^H c = d^H V d
+#pragma unroll
+      for (int k = 0; k < ML; ++k) dc = cadd(dc, cmul(cconj(dv[k]), ci[k]));
+      const double sc = 1.0 / sqrt(dc.re > d.eps ? dc.re : d.eps);
+#pragma unroll
+      for (int k = 0; k < ML; ++k) {
+        const cd b = {dv[k].re * sc, dv[k].im * sc};
+        sB[blk][k] = b;
+        sC[blk][k] = ci[k];
+        if (ok) row[k] = cconj(b);
+      }
+      sW[blk] = {dc.re * sc, dc.im * sc};  // b^H c
+      sOk[blk] = ok;
+      if (live && !ok) atomicOr(status, kStSingular);  // row kept; reported as DFM_E_SINGULAR
+    }
+    __syncthreads();
+    if (sOk[blk]) {
+      cd bq = {r == mu ? -1.0 : 0.0, 0.0};  // b^H Q^{-1}[:, r] - delta_{mu r}
+#pragma unroll
+      for (int k = 0; k < ML; ++k) bq = cadd(bq, cmul(cconj(sB[blk][k]), ci[k]));
+      const cd w = sW[blk];
+      const cd fac = cmul(bq, cinv(w));
+#pragma unroll
+      for (int k = 0; k < ML; ++k) ci[k] = csub(ci[k], cmul(sC[blk][k], fac));
+      ld += 0.5 * log(cabs2(w));
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+#pragma unroll
+  for (int c = 0; c < ML; ++c) qb[r * ML + c] = {(R)row[c].re, (R)row[c].im};
+  if (r == 0) logdet[idx] = qok ? ld : -INFINITY;
 }
 
 // ------------------------------------------------------------------------------------
@@ -530,40 +585,6 @@ __global__ __launch_bounds__(64 * kLamWaves) void k_lam_f(Dims d, const R* __res
   for (int f0 = wave * 16; f0 < d.F; f0 += 16 * kLamWaves) lambda_tile<R, N, K>(d, W, sHn, n, f0, t0, lane, lam);
 }
 
-// IP sweep, eqs. (15)-(16), one lane per (f, subarray) block of size M_l <= 4, in FP64;
-// then ln|det Q_fl| for the cost (13).
-template <typename R, int ML>
-__global__ __launch_bounds__(64) void k_ip_f(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict__ Q,
-                                             double* __restrict__ logdet, int* __restrict__ status) {
-  constexpr int ML2 = ML * ML;
-  __shared__ cd sQ[ML2 * 64];
-  __shared__ cd sV[ML2 * 64];
-  const int idx = blockIdx.x * 64 + threadIdx.x;
-  if (idx >= d.F * d.L) return;
-  const int f = idx / d.L, l = idx - f * d.L;
-  cd* q = sQ + threadIdx.x;
-  cx<R>* qb = Q + (size_t)f * d.QF + l * ML2;
-  {
-    cx<R> qv[ML2];
-#pragma unroll
-    for (int e = 0; e < ML2; ++e) qv[e] = qb[e];
-#pragma unroll
-    for (int e = 0; e < ML2; ++e) q[e * 64] = {(double)qv[e].re, (double)qv[e].im};
-  }
-  ip_sweep_lane<R, ML>(Vpart + (size_t)f * d.S * d.VF + (size_t)l * ML * ML2, d.VF, d.S, 1.0 / d.T, q,
-                       sV + threadIdx.x, d.eps, status);
-  cd A[ML][ML];
-#pragma unroll
-  for (int r = 0; r < ML; ++r)
-#pragma unroll
-    for (int c = 0; c < ML; ++c) {
-      const cd qq = q[(r * ML + c) * 64];
-      const cx<R> o = {(R)qq.re, (R)qq.im};
-      qb[r * ML + c] = o;
-      A[r][c] = {(double)o.re, (double)o.im};
-    }
-  logdet[idx] = logabsdet_lane<ML>(A);
-}
 
 // ------------------------------------------------------------------------------------
 // P = |Q x|^2 and the per-bin coefficients of eq. (8) for every (f, t) of a slice:
@@ -1159,7 +1180,7 @@ struct Set {
         break;
       case kFIp:
         if constexpr (ML <= 4) {
-          hipLaunchKernelGGL((k_ip_f<R, ML>), dim3((d.F * L + 63) / 64), dim3(64), 0, s, d,
+          hipLaunchKernelGGL((k_ip_f<R, ML>), dim3((d.F * L + 64 / ML - 1) / (64 / ML)), dim3(64), 0, s, d,
                              static_cast<const R*>(b.Vpart), Q, b.logdet, b.status);
         } else {
           return launch_kernel(d, b, sizeof(R) == 4 ? DFM_C64 : DFM_C128, kKIp, s);
