@@ -306,12 +306,9 @@ constexpr int padded(int n) {
 template <typename R, int N, int K, int ML, int L>
 struct GramShape {
   static constexpr int M = ML * L, ML2 = ML * ML, OF = L * ML2;
-  static constexpr bool kBlocks = ML <= 4 && sizeof(R) == 4;  // 4x4x1 matrix-core path (x rows)
-  static constexpr bool kPre = ML <= 4 && !kBlocks;           // packed products staged per frame
+  static constexpr bool kPre = ML <= 4;  // packed products staged per frame
   static constexpr int MP = padded<R>(M);
   static constexpr int OP = kPre ? padded<R>(OF) : padded<R>(2 * M);
-  static constexpr int JG4 = (ML2 + 3) / 4;           // groups of 4 packed entries per subarray
-  static constexpr int NG = (L * JG4 + 15) / 16;      // 4x4x1 ops per frame
 };
 
 template <typename R, int N, int K, int ML, int L>
@@ -376,12 +373,16 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__
 #pragma unroll
         for (int l = 0; l < L; ++l)
 #pragma unroll
-          for (int j = 0; j < ML2; ++j) {
-            int a, b, part;
-            packed_pair(ML, j, a, b, part);
+          for (int a = 0; a < ML; ++a) {
             const R ar = xv[2 * (l * ML + a)], ai = xv[2 * (l * ML + a) + 1];
-            const R br = xv[2 * (l * ML + b)], bi = xv[2 * (l * ML + b) + 1];
-            op[l * ML2 + j] = part == 0 ? ar * br + ai * bi : ai * br - ar * bi;
+            op[l * ML2 + a] = ar * ar + ai * ai;
+#pragma unroll
+            for (int b = a + 1; b < ML; ++b) {
+              const int jj = l * ML2 + ML + 2 * (a * ML - a * (a + 1) / 2 + (b - a - 1));
+              const R br = xv[2 * (l * ML + b)], bi = xv[2 * (l * ML + b) + 1];
+              op[jj] = ar * br + ai * bi;
+              op[jj + 1] = ai * br - ar * bi;
+            }
           }
 #pragma unroll
         for (int i = 0; i < OF / E; ++i) {
@@ -403,118 +404,221 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__
   }
   __syncthreads();
 
-  if constexpr (G::kBlocks) {
-    // Lane i, op group q: block b = 16 q + i / 4 = (subarray l, entry group jg); A row
-    // (mu) and B column (entry) = i % 4.  Frames of the slice alternate between waves.
-    constexpr int JG4 = G::JG4, NG = G::NG;
-    const int sub = lane & 3;
-    // The lane's packed entry j of subarray l is Re or Im of x_a conj(x_b): B = u x_b.re + v x_b.im
-    // with (u, v) = (x_a.re, x_a.im) for the real part and (x_a.im, -x_a.re) for the imaginary.
-    v4 acc[NG];
-    int aoff[NG], xa[NG], xb[NG];
-    bool av_ok[NG], bv_ok[NG], im[NG];
+  // C[mu][j] += sum over 4 frames of (1/y)[frame][mu] * O[frame][j] per (subarray, 16
+  // packed entries); four steps of operand loads ahead of their matrix-core ops.
+  const int col = lane & 15, kk = lane >> 4;
+  for (int item = wave; item < L * JT; item += kT / 64) {
+    const int l = item / JT, jt = item - l * JT;
+    const int o = l * ML;
+    const int j = jt * 16 + col;
+    const bool jv = j < ML2;
+    const bool rv = col < ML;
+    v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const int nsteps = ntp >> 2;
+    int a = 0, b = 0, part = 0;
+    if (jv) packed_pair(ML, j, a, b, part);
+    const R* ip = sInv + (size_t)kk * MP + o + (rv ? col : 0);
+    for (int q0 = 0; q0 < nsteps; q0 += 4) {
+      R av[4], bv[4];
 #pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      acc[q] = v4{0, 0, 0, 0};
-      const int b = 16 * q + (lane >> 2), l = b / JG4, jg = b - l * JG4, j = 4 * jg + sub;
-      av_ok[q] = l < L && sub < ML;
-      bv_ok[q] = l < L && j < ML2;
-      aoff[q] = av_ok[q] ? l * ML + sub : 0;
-      int pa = 0, pb = 0, part = 0;
-      if (bv_ok[q]) packed_pair(ML, j, pa, pb, part);
-      xa[q] = bv_ok[q] ? 2 * (l * ML + pa) : 0;
-      xb[q] = bv_ok[q] ? 2 * (l * ML + pb) : 0;
-      im[q] = part != 0;
+      for (int u = 0; u < 4; ++u) {
+        const int q = min(q0 + u, nsteps - 1);
+        const int tq = 4 * q + kk;
+        const R ai = ip[(size_t)q * 4 * MP];
+        R bo;
+        if constexpr (G::kPre) {
+          bo = sOp[(size_t)tq * OP + l * ML2 + (jv ? j : 0)];
+        } else {
+          const R* xr = sOp + (size_t)tq * OP;
+          const R xar = xr[2 * (o + a)], xai = xr[2 * (o + a) + 1];
+          const R xbr = xr[2 * (o + b)], xbi = xr[2 * (o + b) + 1];
+          bo = part == 0 ? xar * xbr + xai * xbi : xai * xbr - xar * xbi;
+        }
+        const bool ok = q0 + u < nsteps;
+        av[u] = (ok && rv) ? ai : (R)0;
+        bv[u] = (ok && jv) ? bo : (R)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u += 2) {
+        acc0 = Mma<R>::run(av[u], bv[u], acc0);
+        acc1 = Mma<R>::run(av[u + 1], bv[u + 1], acc1);
+      }
     }
-    const int half = ((ntp >> 1) + 3) & ~3;  // frames of wave 0; wave 1 takes the rest
-    const int fb = wave == 0 ? 0 : half, fe = wave == 0 ? min(half, ntp) : ntp;
-    typedef R v2r __attribute__((ext_vector_type(2)));
+    R* out = Vpart + ((size_t)f * d.S + s) * d.VF + (size_t)l * ML * ML2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mu = Mma<R>::row(lane, r);
+      if (mu < ML && jv) out[mu * ML2 + j] = acc0[r] + acc1[r];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Weighted covariances (eq. (14)), FP32, subarrays of M_l <= 4 mics.  A 128-frame slice is
+// taken in two passes of 64 frames so that the per-frame LDS rows of one pass (1/y_ftm for
+// every mic, then the L M_l^2 packed entries of x^(l) x^(l)H) stay small enough for about
+// seven workgroups per CU.  In each pass two threads share a frame, each forming 1/y and
+// the packed products for half of the subarrays; then the two waves take 32 frames each
+// on v_mfma_f32_4x4x1 (16 blocks = (subarray, 4 packed entries), rows = mu, one frame per
+// op), reading one 1/y and one product per lane and frame.  The waves' sums are combined
+// in LDS (over the product rows) after both passes.
+template <typename R, int N, int K, int ML, int L>
+struct Gram4Shape {
+  static constexpr int M = ML * L, ML2 = ML * ML, OF = L * ML2;
+  static constexpr int LH = (L + 1) / 2;           // subarrays per thread in the first half
+  static constexpr int MP = padded<R>(M), OP = padded<R>(OF);
+  static constexpr int JG4 = (ML2 + 3) / 4;        // groups of 4 packed entries per subarray
+  static constexpr int NG = (L * JG4 + 15) / 16;   // 4x4x1 ops per frame
+  static constexpr int PF = 64;                    // frames per pass
+};
+
+template <typename R, int N, int K, int ML, int L>
+__global__ __launch_bounds__(kT) void k_gram4_f(Dims d, const cx<R>* __restrict__ X,
+                                                const R* __restrict__ lamin, const R* __restrict__ g,
+                                                R* __restrict__ Vpart) {
+  typedef Gram4Shape<R, N, K, ML, L> G;
+  constexpr int M = G::M, ML2 = G::ML2, MP = G::MP, OP = G::OP, LH = G::LH, PF = G::PF;
+  constexpr int JG4 = G::JG4, NG = G::NG;
+  constexpr int E = V16<R>::E;
+  static_assert(sizeof(R) == 4 && (ML == 2 || ML == 4), "FP32, M_l of 2 or 4");
+  static_assert(N * M <= kT, "g of one frequency is staged one value per thread");
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int T = d.T;
+  const int f = blockIdx.x / d.S, s = blockIdx.x - f * d.S;
+  const int t0 = s * d.SL;
+  const int nt = min(d.SL, T - t0);
+  __shared__ __align__(16) R sg[N * M];
+  __shared__ __align__(16) R sInv[PF * MP];
+  __shared__ __align__(16) R sOp[PF * OP];
+  R* sRed = sOp;  // [NG][64][4] after the last pass
+  static_assert(NG * 256 <= PF * OP, "cross-wave sums fit in the product rows");
+
+  // This thread: frame tid / 2 of each pass, subarrays [l0, l0 + LH) (those < L).
+  const int tf = tid >> 1, h = tid & 1, l0 = h * LH;
+  R xv[2][LH][2 * ML], lam[2][N], gv = 0;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int tl = p * PF + tf;
+    const bool live = tl < nt;
+#pragma unroll
+    for (int ll = 0; ll < LH; ++ll) {
+      const int l = min(l0 + ll, L - 1);
+      const R* src = reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + (live ? tl : 0)) * M + l * ML);
+      R tmp[2 * ML];
+      load16<R, 2 * ML>(tmp, src);
+#pragma unroll
+      for (int i = 0; i < 2 * ML; ++i) xv[p][ll][i] = live ? tmp[i] : (R)0;
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[p][n] = live ? lamin[((size_t)f * N + n) * T + t0 + tl] : (R)0;
+  }
+  if (tid < N * M) gv = g[(size_t)f * N * M + tid];
+  sched_fence();
+  if (tid < N * M) sg[tid] = gv;
+
+  // Lane i, op group q: block b = 16 q + i / 4 = (subarray l, entry group jg); A row (mu) and
+  // B column (entry) = i % 4.
+  const int sub = lane & 3;
+  v4f acc[NG];
+  int aoff[NG], boff[NG];
+  bool aok[NG], bok[NG];  // A: row mu = sub of the block; B: packed entry j
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    acc[q] = v4f{0, 0, 0, 0};
+    const int b = 16 * q + (lane >> 2), l = b / JG4, jg = b - l * JG4, j = 4 * jg + sub;
+    aok[q] = l < L && sub < ML;
+    bok[q] = l < L && j < ML2;
+    aoff[q] = aok[q] ? l * ML + sub : 0;
+    boff[q] = bok[q] ? l * ML2 + j : 0;
+  }
+
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int np = min(max(nt - p * PF, 0), PF);  // frames of this pass
+    __syncthreads();  // sg staged (first pass) / previous pass's rows consumed
+    if (np == 0) break;
+    const bool live = tf < np;
+#pragma unroll
+    for (int ll = 0; ll < LH; ++ll) {
+      const int l = l0 + ll;
+      if (l >= L) break;
+      R inv[ML];
+#pragma unroll
+      for (int mu = 0; mu < ML; ++mu) {
+        R y = 0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) y += lam[p][n] * sg[n * M + l * ML + mu];
+        inv[mu] = live ? rcp(rmax(y, (R)d.eps)) : (R)0;
+      }
+      R op[ML2];
+#pragma unroll
+      for (int a = 0; a < ML; ++a) {
+        const R ar = xv[p][ll][2 * a], ai = xv[p][ll][2 * a + 1];
+        op[a] = ar * ar + ai * ai;
+#pragma unroll
+        for (int b = a + 1; b < ML; ++b) {
+          const int j = ML + 2 * (a * ML - a * (a + 1) / 2 + (b - a - 1));
+          const R br = xv[p][ll][2 * b], bi = xv[p][ll][2 * b + 1];
+          op[j] = ar * br + ai * bi;
+          op[j + 1] = ai * br - ar * bi;
+        }
+      }
+      if (ML % E == 0) {
+#pragma unroll
+        for (int i = 0; i < ML / E; ++i) {
+          v4f v;
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e] = inv[i * E + e];
+          *reinterpret_cast<v4f*>(sInv + tf * MP + l * ML + i * E) = v;
+        }
+      } else {
+#pragma unroll
+        for (int mu = 0; mu < ML; ++mu) sInv[tf * MP + l * ML + mu] = inv[mu];
+      }
+#pragma unroll
+      for (int i = 0; i < ML2 / E; ++i) {
+        v4f v;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = op[i * E + e];
+        *reinterpret_cast<v4f*>(sOp + tf * OP + l * ML2 + i * E) = v;
+      }
+    }
+    __syncthreads();
+    // Frames [32 wave, 32 wave + 32) of the pass, rounded up to 4 (rows past np are zero).
+    const int fb = 32 * wave, fe = min(fb + 32, (np + 3) & ~3);
     for (int t4 = fb; t4 < fe; t4 += 4) {
       R av[4][NG], bv[4][NG];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int q = 0; q < NG; ++q) {
-          const R* xr = sOp + (t4 + u) * OP;
-          const R a = sInv[(t4 + u) * MP + aoff[q]];
-          const v2r pa = *reinterpret_cast<const v2r*>(xr + xa[q]);
-          const v2r pb = *reinterpret_cast<const v2r*>(xr + xb[q]);
-          const R cu = im[q] ? pa.y : pa.x, cv = im[q] ? -pa.x : pa.y;
-          av[u][q] = av_ok[q] ? a : (R)0;
-          bv[u][q] = bv_ok[q] ? cu * pb.x + cv * pb.y : (R)0;
+          const R a = sInv[(t4 + u) * MP + aoff[q]], b = sOp[(t4 + u) * OP + boff[q]];
+          av[u][q] = aok[q] ? a : (R)0;
+          bv[u][q] = bok[q] ? b : (R)0;
         }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
     }
-    // Combine the two waves (LDS area of sInv is free now) and store the slice sums.
-    __syncthreads();
-    R* sRed = sInv;  // [NG][64][4]
-    if (wave == 1)
+  }
+  __syncthreads();  // both waves done with the product rows
+  if (wave == 1)
 #pragma unroll
-      for (int q = 0; q < NG; ++q)
+    for (int q = 0; q < NG; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sRed[(q * 64 + lane) * 4 + r] = acc[q][r];
-    __syncthreads();
-    if (wave == 0) {
-      R* out = Vpart + ((size_t)f * d.S + s) * d.VF;
+      for (int r = 0; r < 4; ++r) sRed[(q * 64 + lane) * 4 + r] = acc[q][r];
+  __syncthreads();
+  if (wave == 0) {
+    R* out = Vpart + ((size_t)f * d.S + s) * d.VF;
 #pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        const int b = 16 * q + (lane >> 2), l = b / JG4, jg = b - l * JG4, j = 4 * jg + sub;
-        if (l < L && j < ML2)
+    for (int q = 0; q < NG; ++q) {
+      const int b = 16 * q + (lane >> 2), l = b / JG4, jg = b - l * JG4, j = 4 * jg + sub;
+      if (l < L && j < ML2)
 #pragma unroll
-          for (int r = 0; r < ML; ++r)
-            out[(size_t)l * ML * ML2 + r * ML2 + j] = acc[q][r] + sRed[(q * 64 + lane) * 4 + r];
-      }
-    }
-  } else {
-    // C[mu][j] += sum over 4 frames of (1/y)[frame][mu] * O[frame][j] per (subarray, 16
-    // packed entries); four steps of operand loads ahead of their matrix-core ops.
-    const int col = lane & 15, kk = lane >> 4;
-    for (int item = wave; item < L * JT; item += kT / 64) {
-      const int l = item / JT, jt = item - l * JT;
-      const int o = l * ML;
-      const int j = jt * 16 + col;
-      const bool jv = j < ML2;
-      const bool rv = col < ML;
-      v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-      const int nsteps = ntp >> 2;
-      int a = 0, b = 0, part = 0;
-      if (jv) packed_pair(ML, j, a, b, part);
-      const R* ip = sInv + (size_t)kk * MP + o + (rv ? col : 0);
-      for (int q0 = 0; q0 < nsteps; q0 += 4) {
-        R av[4], bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int q = min(q0 + u, nsteps - 1);
-          const int tq = 4 * q + kk;
-          const R ai = ip[(size_t)q * 4 * MP];
-          R bo;
-          if constexpr (G::kPre) {
-            bo = sOp[(size_t)tq * OP + l * ML2 + (jv ? j : 0)];
-          } else {
-            const R* xr = sOp + (size_t)tq * OP;
-            const R xar = xr[2 * (o + a)], xai = xr[2 * (o + a) + 1];
-            const R xbr = xr[2 * (o + b)], xbi = xr[2 * (o + b) + 1];
-            bo = part == 0 ? xar * xbr + xai * xbi : xai * xbr - xar * xbi;
-          }
-          const bool ok = q0 + u < nsteps;
-          av[u] = (ok && rv) ? ai : (R)0;
-          bv[u] = (ok && jv) ? bo : (R)0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; u += 2) {
-          acc0 = Mma<R>::run(av[u], bv[u], acc0);
-          acc1 = Mma<R>::run(av[u + 1], bv[u + 1], acc1);
-        }
-      }
-      R* out = Vpart + ((size_t)f * d.S + s) * d.VF + (size_t)l * ML * ML2;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int mu = Mma<R>::row(lane, r);
-        if (mu < ML && jv) out[mu * ML2 + j] = acc0[r] + acc1[r];
-      }
+        for (int r = 0; r < ML; ++r)
+          out[(size_t)l * ML * ML2 + r * ML2 + j] = acc[q][r] + sRed[(q * 64 + lane) * 4 + r];
     }
   }
 }
@@ -1148,9 +1252,7 @@ struct Set {
   static constexpr int M = ML * L;
   static size_t smem_gram(const Dims& d) {
     typedef GramShape<R, N, K, ML, L> G;
-    const size_t rows = (size_t)d.SLP * (G::MP + G::OP);
-    const size_t red = G::kBlocks ? (size_t)G::NG * 64 * 4 : 0;  // cross-wave sums reuse the rows
-    return align_up(sizeof(R) * N * M, 16) + sizeof(R) * (rows > red ? rows : red);
+    return align_up(sizeof(R) * N * M, 16) + sizeof(R) * (size_t)d.SLP * (G::MP + G::OP);
   }
   static size_t smem_g(const Dims& d) {
     typedef GShape<R, N, K, ML, L> G;
@@ -1175,8 +1277,13 @@ struct Set {
                            static_cast<R*>(b.lam));
         break;
       case kFGram:
-        hipLaunchKernelGGL((k_gram_f<R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d, X,
-                           static_cast<const R*>(b.lam), g, static_cast<R*>(b.Vpart));
+        if constexpr (sizeof(R) == 4 && (ML == 2 || ML == 4)) {
+          hipLaunchKernelGGL((k_gram4_f<R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), 0, s, d, X,
+                             static_cast<const R*>(b.lam), g, static_cast<R*>(b.Vpart));
+        } else {
+          hipLaunchKernelGGL((k_gram_f<R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d, X,
+                             static_cast<const R*>(b.lam), g, static_cast<R*>(b.Vpart));
+        }
         break;
       case kFIp:
         if constexpr (ML <= 4) {
