@@ -125,7 +125,7 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   const bool fast = d.fast >= 0;
   n += al(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);    // Wpart
   n += al(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);  // Hpart
-  n += al(r * d.F * d.S * d.N * d.M * 2);              // gpart
+  n += al(fast ? 0 : r * d.F * d.S * d.N * d.M * 2);    // gpart
   n += al(8 * d.F * d.L);                              // logdet
   n += al(8 * d.F * d.S);                              // nllpart
   n += al(16 * d.F * d.QF);                            // Qinv
@@ -149,7 +149,7 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   const bool fast = d.fast >= 0;
   b.Wpart = take(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);
   b.Hpart = take(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);
-  b.gpart = take(r * d.F * d.S * d.N * d.M * 2);
+  b.gpart = take(fast ? 0 : r * d.F * d.S * d.N * d.M * 2);
   b.logdet = reinterpret_cast<double*>(take(8 * d.F * d.L));
   b.nllpart = reinterpret_cast<double*>(take(8 * d.F * d.S));
   b.Qinv = take(16 * d.F * d.QF);

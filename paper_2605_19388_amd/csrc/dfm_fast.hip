@@ -1100,11 +1100,16 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
 }
 
 // ------------------------------------------------------------------------------------
-// Eq. (10) sums per (f, slice).  Per frame: 1/y and P/y^2 from lambda (read), stored
-// frame-major in LDS with lambda.  Then num/den[n][m] = sum_t lambda_n (P_m/y_m^2, 1/y_m):
-// in FP32 on the 4x4x1 matrix-core blocks (block = (group of 4 sources, group of 4 mics,
-// numerator or denominator)), one op per frame and 16 blocks; frames alternate between
-// the two waves.
+// Diagonal SCM update, eq. (10), one workgroup per frequency: num/den[n][m] =
+// sum_t lambda_n (P_m / y_m^2, 1 / y_m) over every frame, then g <- g sqrt(num / max(den, eps)).
+// Frames are taken in passes of GShape::PF, one thread per frame: 1/y and P/y^2 are formed
+// and stored frame-major in LDS with lambda (read), while the next pass's P and lambda are
+// already in flight; the sums over the pass then run, in FP32, on the 4x4x1 matrix-core
+// blocks (block = (4 sources, 4 mics, numerator or denominator), one op per frame, frames
+// dealt to the four waves), in FP64 on the vector units.  The waves' sums are added in
+// wave order in LDS.
+constexpr int kGT = 256;  // threads of the g-update workgroup
+
 template <typename R, int N, int K, int ML, int L>
 struct GShape {
   static constexpr int M = ML * L;
@@ -1113,109 +1118,135 @@ struct GShape {
   static constexpr int BP = padded<R>(2 * M);  // LDS row of P/y^2 then 1/y
   static constexpr int NGR = NP / 4, MG = M / 4;
   static constexpr int NI = (2 * NGR * MG + 15) / 16;
+  static constexpr int PF = sizeof(R) == 4 ? 256 : 128;  // frames per pass
+  static constexpr size_t smem() {
+    return (sizeof(R) * N * M + 15) / 16 * 16 + sizeof(R) * (size_t)PF * (AP + BP) + sizeof(R) * 2 * N * M;
+  }
 };
 
 template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ lamin, const R* __restrict__ g,
-                                            const R* __restrict__ P, R* __restrict__ gpart) {
+__global__ __launch_bounds__(kGT) void k_g_f(Dims d, const R* __restrict__ lamin, R* __restrict__ g,
+                                             const R* __restrict__ P, int* __restrict__ status) {
   typedef GShape<R, N, K, ML, L> G;
-  constexpr int M = G::M, NP = G::NP, AP = G::AP, BP = G::BP;
+  constexpr int M = G::M, NP = G::NP, AP = G::AP, BP = G::BP, PF = G::PF;
   constexpr int E = V16<R>::E;
-  static_assert(M % 4 == 0 && M % E == 0 && NP % E == 0 && N * M <= kT, "shape");
+  static_assert(M % 4 == 0 && M % E == 0 && NP % E == 0 && N * M <= kGT, "shape");
+  static_assert(G::NI * 256 * 4 <= PF * BP, "cross-wave sums fit in the P/y^2 rows");
+  static_assert(G::smem() <= 64 * 1024, "LDS of the g-update workgroup");
   typedef typename V16<R>::type vt;
-  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int T = d.T;
-  const int t0 = s * d.SL;
-  const int nt = min(d.SL, T - t0);
-  const int ntp = (nt + 3) & ~3;
   extern __shared__ __align__(16) unsigned char smem[];
   R* sg = reinterpret_cast<R*>(smem);
-  R* sA = reinterpret_cast<R*>(smem + align_up(sizeof(R) * N * M, 16));  // [SLP][AP]
-  R* sB = sA + (size_t)d.SLP * AP;                                         // [SLP][BP]
-  R* sRed = sB + (size_t)d.SLP * BP;                                       // FP32: [NI][64][4]
+  R* sA = reinterpret_cast<R*>(smem + align_up(sizeof(R) * N * M, 16));  // [PF][AP]
+  R* sB = sA + (size_t)PF * AP;                                            // [PF][BP]
+  R* sND = sB + (size_t)PF * BP;                                           // [N*M][2]
 
-  R pv[M], lam[NP], gv = 0;
+  // Operands of the first pass (this thread's frame), g of the frequency.
+  R pv[M], lam[NP];
+  auto fetch = [&](int t) {
+    const bool live = tid < PF && t < T;
 #pragma unroll
-  for (int n = N; n < NP; ++n) lam[n] = 0;
-  if (tid < nt) {
-    load16<R, M>(pv, P + ((size_t)f * T + t0 + tid) * M);
+    for (int n = 0; n < NP; ++n) lam[n] = (live && n < N) ? lamin[((size_t)f * N + n) * T + t] : (R)0;
+    if (live) {
+      load16<R, M>(pv, P + ((size_t)f * T + t) * M);
+    } else {
 #pragma unroll
-    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
-  } else {
-#pragma unroll
-    for (int m = 0; m < M; ++m) pv[m] = 0;
-#pragma unroll
-    for (int n = 0; n < N; ++n) lam[n] = 0;
-  }
+      for (int m = 0; m < M; ++m) pv[m] = 0;
+    }
+  };
+  fetch(tid);
+  R gv = 0;
   if (tid < N * M) gv = g[(size_t)f * N * M + tid];
   sched_fence();
   if (tid < N * M) sg[tid] = gv;
-  __syncthreads();
-  if (tid < ntp) {
-    R u[2 * M];
+
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  constexpr int NI = G::NI, NGR = G::NGR, MG = G::MG;
+  const int sub = lane & 3;
+  v4f acc[NI];
+  int aoff[NI], boff[NI];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      R y = 0;
+  for (int q = 0; q < NI; ++q) {
+    acc[q] = v4f{0, 0, 0, 0};
+    const int blk = 16 * q + (lane >> 2);
+    const bool ok = blk < 2 * NGR * MG;
+    const int ng = blk % NGR, rest = blk / NGR, mg = rest % MG, uz = rest / MG;
+    aoff[q] = ok ? 4 * ng + sub : 0;
+    boff[q] = ok ? uz * M + 4 * mg + sub : 0;
+  }
+  R num = 0, den = 0;  // FP64 path: thread o = n * M + m
+
+  for (int t0 = 0; t0 < T; t0 += PF) {
+    const int np = min(PF, T - t0);
+    __syncthreads();  // sg staged / previous pass's rows consumed
+    if (tid < PF) {
+      const bool live = tid < np;
+      R u[2 * M];
 #pragma unroll
-      for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
-      const R iy = tid < nt ? rcp(rmax(y, (R)d.eps)) : (R)0;
-      u[m] = pv[m] * iy * iy;
-      u[M + m] = iy;
+      for (int m = 0; m < M; ++m) {
+        R y = 0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
+        const R iy = live ? rcp(rmax(y, (R)d.eps)) : (R)0;
+        u[m] = pv[m] * iy * iy;
+        u[M + m] = iy;
+      }
+#pragma unroll
+      for (int i = 0; i < NP / E; ++i) {
+        vt v;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = lam[i * E + e];
+        reinterpret_cast<vt*>(sA + (size_t)tid * AP)[i] = v;
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * M / E; ++i) {
+        vt v;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = u[i * E + e];
+        reinterpret_cast<vt*>(sB + (size_t)tid * BP)[i] = v;
+      }
     }
+    if (t0 + PF < T) fetch(t0 + PF + tid);  // next pass, in flight during the sums
+    __syncthreads();
+    const int ntp = (np + 3) & ~3;  // rows past np hold zeros
+    if constexpr (sizeof(R) == 4) {
+      constexpr int FW = PF / 4;  // frames per wave
+      const int fb = wave * FW, fe = min(fb + FW, ntp);
+      for (int t4 = fb; t4 < fe; t4 += 4) {
+        R av[4][NI], bv[4][NI];
 #pragma unroll
-    for (int i = 0; i < NP / E; ++i) {
-      vt v;
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = lam[i * E + e];
-      reinterpret_cast<vt*>(sA + (size_t)tid * AP)[i] = v;
-    }
+          for (int q = 0; q < NI; ++q) {
+            av[u][q] = sA[(size_t)(t4 + u) * AP + aoff[q]];
+            bv[u][q] = sB[(size_t)(t4 + u) * BP + boff[q]];
+          }
 #pragma unroll
-    for (int i = 0; i < 2 * M / E; ++i) {
-      vt v;
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = u[i * E + e];
-      reinterpret_cast<vt*>(sB + (size_t)tid * BP)[i] = v;
+          for (int q = 0; q < NI; ++q)
+            acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
+      }
+    } else {
+      if (tid < N * M) {
+        const int n = tid / M, m = tid - n * M;
+        for (int tt = 0; tt < ntp; ++tt) {
+          const R lv = sA[(size_t)tt * AP + n];
+          num += lv * sB[(size_t)tt * BP + m];
+          den += lv * sB[(size_t)tt * BP + M + m];
+        }
+      }
     }
   }
-  __syncthreads();
-
-  R* out = gpart + ((size_t)f * d.S + s) * N * M * 2;
   if constexpr (sizeof(R) == 4) {
-    constexpr int NI = G::NI, NGR = G::NGR, MG = G::MG;
-    typedef float v4f __attribute__((ext_vector_type(4)));
-    const int sub = lane & 3;
-    v4f acc[NI];
-    int aoff[NI], boff[NI];
+    // Wave sums into LDS (over the P/y^2 rows), added in wave order into sND.
+    R* red = sB;  // [wave][NI][64][4]
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NI; ++q) {
-      acc[q] = v4f{0, 0, 0, 0};
-      const int blk = 16 * q + (lane >> 2);
-      const bool ok = blk < 2 * NGR * MG;
-      const int ng = blk % NGR, rest = blk / NGR, mg = rest % MG, uz = rest / MG;
-      aoff[q] = ok ? 4 * ng + sub : 0;
-      boff[q] = ok ? uz * M + 4 * mg + sub : 0;
-    }
-    const int half = ((ntp >> 1) + 3) & ~3;
-    const int fb = wave == 0 ? 0 : half, fe = wave == 0 ? min(half, ntp) : ntp;
-    for (int t4 = fb; t4 < fe; t4 += 4) {
-      R av[4][NI], bv[4][NI];
+    for (int q = 0; q < NI; ++q)
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < NI; ++q) {
-          av[u][q] = sA[(size_t)(t4 + u) * AP + aoff[q]];
-          bv[u][q] = sB[(size_t)(t4 + u) * BP + boff[q]];
-        }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < NI; ++q) acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
-    }
-    if (wave == 1)
-#pragma unroll
-      for (int q = 0; q < NI; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sRed[(q * 64 + lane) * 4 + r] = acc[q][r];
+      for (int r = 0; r < 4; ++r) red[((wave * NI + q) * 64 + lane) * 4 + r] = acc[q][r];
     __syncthreads();
     if (wave == 0)
 #pragma unroll
@@ -1227,21 +1258,22 @@ __global__ __launch_bounds__(kT) void k_g_f(Dims d, const R* __restrict__ lamin,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int n = 4 * ng + r;
-          if (n < N) out[(n * M + m) * 2 + uz] = acc[q][r] + sRed[(q * 64 + lane) * 4 + r];
+          R v = 0;
+#pragma unroll
+          for (int w = 0; w < kGT / 64; ++w) v += red[((w * NI + q) * 64 + lane) * 4 + r];
+          if (n < N) sND[(n * M + m) * 2 + uz] = v;
         }
       }
-  } else {
-    for (int o = tid; o < N * M; o += kT) {
-      const int n = o / M, m = o - n * M;
-      R num = 0, den = 0;
-      for (int tt = 0; tt < ntp; ++tt) {
-        const R lv = sA[(size_t)tt * AP + n];
-        num += lv * sB[(size_t)tt * BP + m];
-        den += lv * sB[(size_t)tt * BP + M + m];
-      }
-      out[o * 2 + 0] = num;
-      out[o * 2 + 1] = den;
+    __syncthreads();
+    if (tid < N * M) {
+      num = sND[tid * 2];
+      den = sND[tid * 2 + 1];
     }
+  }
+  if (tid < N * M) {
+    const R v = gv * sqrt(num / rmax(den, (R)d.eps));
+    if (!isfinite(v)) atomicOr(status, kStNonFinite);
+    g[(size_t)f * N * M + tid] = v;
   }
 }
 
@@ -1254,11 +1286,7 @@ struct Set {
     typedef GramShape<R, N, K, ML, L> G;
     return align_up(sizeof(R) * N * M, 16) + sizeof(R) * (size_t)d.SLP * (G::MP + G::OP);
   }
-  static size_t smem_g(const Dims& d) {
-    typedef GShape<R, N, K, ML, L> G;
-    return align_up(sizeof(R) * N * M, 16) + sizeof(R) * ((size_t)d.SLP * (G::AP + G::BP) + G::NI * 256);
-  }
-  static size_t max_smem(const Dims& d) { return smem_gram(d) > smem_g(d) ? smem_gram(d) : smem_g(d); }
+  static size_t max_smem(const Dims& d) { return smem_gram(d); }
 
   static hipError_t launch(const Dims& d, const Buffers& b, int kid, hipStream_t s) {
     const cx<R>* X = static_cast<const cx<R>*>(b.X);
@@ -1311,8 +1339,8 @@ struct Set {
                            static_cast<const R*>(b.AB), H, static_cast<R*>(b.Ht), static_cast<R*>(b.lam), b.status);
         break;
       case kFG:
-        hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), smem_g(d), s, d,
-                           static_cast<const R*>(b.lam), g, P, static_cast<R*>(b.gpart));
+        hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F), dim3(kGT), (GShape<R, N, K, ML, L>::smem()), s, d,
+                           static_cast<const R*>(b.lam), g, P, b.status);
         break;
       default:
         return hipErrorInvalidValue;

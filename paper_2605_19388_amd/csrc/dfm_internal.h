@@ -51,7 +51,7 @@ struct Buffers {
   void* Vpart;   // [F][S][VF] real: per-slice packed covariance sums
   void* Wpart;   // [F][S][N][K][2] real (generic kernels)
   void* Hpart;   // [FS][N][K][T][2] real (generic kernels)
-  void* gpart;   // [F][S][N][M][2] real
+  void* gpart;   // [F][S][N][M][2] real (generic kernels)
   double* logdet;   // [F][L]
   double* nllpart;  // [F][S]
   void* Qinv;       // [F][QF] complex double
@@ -64,8 +64,8 @@ struct Buffers {
 size_t workspace_bytes(const Dims& d, int dtype);
 void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 
-// Kernels.  Generic path: eight per iteration; specialised path: seven kF* plus the g
-// apply kernel of the generic path (kFLam and kFHt seed lambda and the copy of H).
+// Kernels.  Generic path: eight per iteration; specialised path: seven (kFLam and kFHt
+// seed lambda and the frame-major copy of H).
 enum KernelId {
   kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply,
   kFGram, kFIp, kFPw, kFWGemm, kFH, kFHGemm, kFG, kFLam, kFHt, kNumKernels

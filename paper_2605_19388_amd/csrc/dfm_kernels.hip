@@ -693,7 +693,7 @@ int stage_kernels(const Dims& d, int stage, int* kids) {
       case DFM_STAGE_IP: kids[0] = kFGram; kids[1] = kFIp; return 2;
       case DFM_STAGE_W: kids[0] = kFPw; kids[1] = kFWGemm; return 2;
       case DFM_STAGE_H: kids[0] = kFH; kids[1] = kFHGemm; return 2;
-      case DFM_STAGE_G: kids[0] = kFG; kids[1] = kKGApply; return 2;
+      case DFM_STAGE_G: kids[0] = kFG; return 1;
     }
     return 0;
   }

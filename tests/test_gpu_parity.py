@@ -74,7 +74,7 @@ STAGE_CASES = [
     (33, 130, (2, 2), 2, 4),
 ]
 
-FAST = ["k_gram_f", "k_ip_f", "k_pw_f", "k_wgemm_f", "k_h_f", "k_hgemm_f", "k_g_f", "k_gapply"]
+FAST = ["k_gram_f", "k_ip_f", "k_pw_f", "k_wgemm_f", "k_h_f", "k_hgemm_f", "k_g_f"]
 GENERIC = ["k_gram", "k_ip", "k_pw", "k_wapply", "k_h", "k_happly", "k_g", "k_gapply"]
 
 
