@@ -35,8 +35,12 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per F*T*M bin for each streaming kernel of the FP32 path
 # (complex64 X = 8 B, FP32 P = 4 B).  One iteration's schedule reads X twice and
-# writes P once and reads it twice: 28 B per bin.
-BYTES_PER_BIN = {"k_gram": 8.0, "k_pw": 12.0, "k_h": 4.0, "k_g": 4.0}
+# writes P once and reads it twice: 28 B per bin.  Shape-specialised kernels map onto the
+# same steps (k_gramd_f / k_gram_f: covariances; k_pw_f: powers and the W coefficients;
+# k_h_f: the H coefficients; k_g_f: the g update).
+BYTES_PER_BIN = {"k_gram": 8.0, "k_gramd": 8.0, "k_pw": 12.0, "k_h": 4.0, "k_g": 4.0}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_19388_amd", "csrc", "dfm_fast.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_paper_4x4.json")
 
 
 def log(*a):
@@ -55,7 +59,66 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-mb run into the traffic file and exit (no GPU needed)")
     return ap.parse_args()
+
+
+def source_digest():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def pmc_summary(fetch_csv, write_csv, copy_mb):
+    """Per-kernel HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    each scaled by what the same counter reads for the calibration copy of copy_mb MiB."""
+    import csv
+    import collections
+
+    def per_kernel(path):
+        vals = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            vals[name].append(float(r["Counter_Value"]))
+        return vals
+
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        vals = per_kernel(path)
+        copies = [v for k, vs in vals.items() if "copyBuffer" in k for v in vs]
+        if not copies:
+            raise SystemExit(f"{path}: no calibration copy found (run the profiled bench with --copy-mb)")
+        measured = max(copies)  # KiB the counter reports for the copy of copy_mb MiB
+        factor = copy_mb * 1024.0 / measured
+        out[counter] = {"calibration_kib": measured, "expected_kib": copy_mb * 1024.0, "factor": factor,
+                        "kernels": {short_name(k): statistics_mean(vs) * factor * 1024.0
+                                    for k, vs in vals.items() if k.startswith("void dfm::")}}
+    return out
+
+
+def statistics_mean(v):
+    return sum(v) / len(v)
+
+
+def short_name(symbol):
+    """'void dfm::fast::k_pw_f<float, 5, 16, 4, 4>(...)' -> 'k_pw_f'."""
+    return symbol.split("(")[0].replace("void ", "").split("<")[0].split("::")[-1]
+
+
+def load_traffic(kernel):
+    """Measured HBM bytes per launch of `kernel` from the committed counter summary, or None
+    if there is none or the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
 def cpu_baseline(w, X64, W0, H0, n_iter):
@@ -91,6 +154,18 @@ def _cpu_model():
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        copy_mb = args.copy_mb or 256
+        t = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], copy_mb)
+        kernels = sorted(set(t["FETCH_SIZE"]["kernels"]) | set(t["WRITE_SIZE"]["kernels"]))
+        doc = {"workload": "paper_4x4", "source_sha256": source_digest(), "copy_mb": copy_mb,
+               "calibration": {c: {k: v for k, v in t[c].items() if k != "kernels"} for c in t},
+               "kernels": {k: {"fetch_bytes": t["FETCH_SIZE"]["kernels"].get(k, 0.0),
+                               "write_bytes": t["WRITE_SIZE"]["kernels"].get(k, 0.0)} for k in kernels}}
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(doc, fh, indent=1)
+        print(json.dumps(doc, indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the method is sharded across GPUs only by running independent mixtures).", file=sys.stderr)
@@ -165,16 +240,17 @@ def main():
         f"{dominant}: {dom_ms * 1e3:.1f} us avg over {dom_n} launches")
 
     base = dominant[:-2] if dominant.endswith("_f") else dominant   # shape-specialised variants
+    traffic = load_traffic(dominant)
     if base in BYTES_PER_BIN:
         traffic_alg = BYTES_PER_BIN[base] * bins
         achieved = traffic_alg / (dom_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
                 "avg_us": round(dom_ms * 1e3, 3), "launches": dom_n,
                 "algorithmic_bytes_per_launch": traffic_alg}
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                "traffic": None, "kernel": dominant, "avg_us": round(dom_ms * 1e3, 3), "launches": dom_n}
+                "traffic": traffic, "kernel": dominant, "avg_us": round(dom_ms * 1e3, 3), "launches": dom_n}
 
     out = {"metric": METRIC, "value": round(value, 3), "unit": "iterations/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4),

@@ -52,6 +52,10 @@ static bool choose_fast(Dims& d, int dtype) {
     d.TB = 16;
     d.TBN = (d.T + 15) / 16;
     d.TP = (d.T + 15) & ~15;
+    const bool fp64_sums = dtype == DFM_C64 && (ml == 2 || ml == 4);  // k_gramd_f
+    d.SG = !fp64_sums ? d.S : 1;  // k_gramd_f: one workgroup per bin (frame slices supported)
+    d.SLG = (d.T + d.SG - 1) / d.SG;
+    d.VD = fp64_sums || dtype == DFM_C128;
     if (fast_max_smem(d, dtype) <= 64 * 1024) return true;
   }
   d.fast = -1;
@@ -77,6 +81,9 @@ static void choose_tiles(Dims& d, int dtype) {
   while (d.FB > 1 && r * d.FB * d.TB * d.N * 2 > budget) d.FB /= 2;
   d.FS = (d.F + d.FB - 1) / d.FB;
   d.TBN = (d.T + d.TB - 1) / d.TB;
+  d.SG = d.S;
+  d.SLG = d.SL;
+  d.VD = dtype == DFM_C128;
 }
 
 static dfm_status make_dims(const dfm_problem* p, Dims& d) {
@@ -121,7 +128,7 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   const size_t r = real_size(dtype);
   size_t n = 0;
   n += al(r * d.F * d.T * d.M);                        // P
-  n += al(r * d.F * d.S * d.VF);                       // Vpart
+  n += al((d.VD ? 8 : r) * (size_t)d.F * d.SG * d.VF);   // Vpart
   const bool fast = d.fast >= 0;
   n += al(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);    // Wpart
   n += al(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);  // Hpart
@@ -145,7 +152,7 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
     return q;
   };
   b.P = take(r * d.F * d.T * d.M);
-  b.Vpart = take(r * d.F * d.S * d.VF);
+  b.Vpart = take((d.VD ? 8 : r) * (size_t)d.F * d.SG * d.VF);
   const bool fast = d.fast >= 0;
   b.Wpart = take(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);
   b.Hpart = take(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);
@@ -313,7 +320,8 @@ const char* dfm_kernel_name(const dfm_plan* plan, int32_t kernel) {
   if (!plan) return nullptr;
   int kids[16];
   const int n = dfm::iteration_kernels(plan->d, kids);
-  return kernel >= 0 && kernel < n ? dfm::kernel_name(kids[kernel]) : nullptr;
+  if (kernel < 0 || kernel >= n) return nullptr;
+  return plan->d.fast >= 0 ? dfm::fast_kernel_name(plan->d, plan->dtype, kids[kernel]) : dfm::kernel_name(kids[kernel]);
 }
 
 dfm_status dfm_kernel_times(dfm_plan* plan, int32_t reps, double* avg_ms, void* stream) {

@@ -181,7 +181,7 @@ __device__ __forceinline__ bool inverse_column(cd (&A)[n][n + 1], int col, cd (&
 }
 
 template <typename R, int ML>
-__global__ __launch_bounds__(64) void k_ip_f(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict__ Q,
+__global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ Vpart, cx<R>* __restrict__ Q,
                                              double* __restrict__ logdet, int* __restrict__ status) {
   constexpr int ML2 = ML * ML, BPW = 64 / ML;  // blocks per wave
   static_assert(ML >= 1 && ML <= 4 && 64 % ML == 0, "lanes per block");
@@ -198,9 +198,9 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const R* __restrict__ Vpart
     double vs[ML2];
 #pragma unroll
     for (int j = 0; j < ML2; ++j) vs[j] = 0.0;
-    const R* vp = Vpart + (size_t)f * d.S * d.VF + (size_t)l * ML * ML2 + r * ML2;
-    for (int s = 0; s < d.S; ++s) {
-      R part[ML2];
+    const double* vp = Vpart + (size_t)f * d.SG * d.VF + (size_t)l * ML * ML2 + r * ML2;
+    for (int s = 0; s < d.SG; ++s) {
+      double part[ML2];
 #pragma unroll
       for (int j = 0; j < ML2; ++j) part[j] = vp[(size_t)s * d.VF + j];
 #pragma unroll
@@ -454,171 +454,110 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__
 }
 
 // ------------------------------------------------------------------------------------
-// Weighted covariances (eq. (14)), FP32, subarrays of M_l <= 4 mics.  A 128-frame slice is
-// taken in two passes of 64 frames so that the per-frame LDS rows of one pass (1/y_ftm for
-// every mic, then the L M_l^2 packed entries of x^(l) x^(l)H) stay small enough for about
-// seven workgroups per CU.  In each pass two threads share a frame, each forming 1/y and
-// the packed products for half of the subarrays; then the two waves take 32 frames each
-// on v_mfma_f32_4x4x1 (16 blocks = (subarray, 4 packed entries), rows = mu, one frame per
-// op), reading one 1/y and one product per lane and frame.  The waves' sums are combined
-// in LDS (over the product rows) after both passes.
-template <typename R, int N, int K, int ML, int L>
-struct Gram4Shape {
-  static constexpr int M = ML * L, ML2 = ML * ML, OF = L * ML2;
-  static constexpr int LH = (L + 1) / 2;           // subarrays per thread in the first half
-  static constexpr int MP = padded<R>(M), OP = padded<R>(OF);
-  static constexpr int JG4 = (ML2 + 3) / 4;        // groups of 4 packed entries per subarray
-  static constexpr int NG = (L * JG4 + 15) / 16;   // 4x4x1 ops per frame
-  static constexpr int PF = 64;                    // frames per pass
-};
+// Weighted covariances (eq. (14)) for subarrays of M_l <= 4 mics, FP32 inputs, FP64 sums.
+// One workgroup per frequency and kGDL lanes per subarray: lane j of subarray l takes
+// frames t = j, j + kGDL, ...; per frame it forms 1/y for the subarray's mics (FP32), the
+// packed entries of x^(l) x^(l)H in FP64 (exact: products of FP32 values) and adds
+// (1/y_mu) x x^H into M_l x M_l^2 FP64 registers; the lanes' sums are then added through LDS
+// in lane order (frames split into SG slices, one workgroup each).  FP32 sums over frames would leave rounding errors outside the dominant
+// directions of V, which the solve of eq. (15) amplifies by cond(V) -- large at the
+// lowest bins, where the mixing is nearly rank-deficient; FP64 sums keep the solve's
+// input at the precision of the FP64 reference.  Output: V[f][slice][packed entries], FP64,
+// /T not applied.
+constexpr int kGDL = 32;  // lanes per subarray
 
-template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(kT) void k_gram4_f(Dims d, const cx<R>* __restrict__ X,
-                                                const R* __restrict__ lamin, const R* __restrict__ g,
-                                                R* __restrict__ Vpart) {
-  typedef Gram4Shape<R, N, K, ML, L> G;
-  constexpr int M = G::M, ML2 = G::ML2, MP = G::MP, OP = G::OP, LH = G::LH, PF = G::PF;
-  constexpr int JG4 = G::JG4, NG = G::NG;
-  constexpr int E = V16<R>::E;
-  static_assert(sizeof(R) == 4 && (ML == 2 || ML == 4), "FP32, M_l of 2 or 4");
-  static_assert(N * M <= kT, "g of one frequency is staged one value per thread");
-  typedef float v4f __attribute__((ext_vector_type(4)));
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+template <int L>
+constexpr int gramd_threads() {
+  return (L * kGDL + 63) / 64 * 64;
+}
+
+template <int N, int K, int ML, int L>
+__global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx<float>* __restrict__ X,
+                                                               const float* __restrict__ lamin,
+                                                               const float* __restrict__ g,
+                                                               double* __restrict__ V) {
+  constexpr int M = ML * L, ML2 = ML * ML, NO = ML * ML2, NT = gramd_threads<L>();
+  constexpr int FB = 4;  // frames per load batch
+  static_assert(ML == 2 || ML == 4, "M_l of 2 or 4");
+  constexpr int OC = 16;                                 // outputs per LDS reduction chunk
+  __shared__ double red[NT * OC];
+  const int f = blockIdx.x, sl = blockIdx.y, tid = threadIdx.x;  // frequency, frame slice
+  const int l = min(tid / kGDL, L - 1), j = tid % kGDL;
+  const bool live = tid < L * kGDL;
   const int T = d.T;
-  const int f = blockIdx.x / d.S, s = blockIdx.x - f * d.S;
-  const int t0 = s * d.SL;
-  const int nt = min(d.SL, T - t0);
-  __shared__ __align__(16) R sg[N * M];
-  __shared__ __align__(16) R sInv[PF * MP];
-  __shared__ __align__(16) R sOp[PF * OP];
-  R* sRed = sOp;  // [NG][64][4] after the last pass
-  static_assert(NG * 256 <= PF * OP, "cross-wave sums fit in the product rows");
+  const int ts = sl * d.SLG, te = min(T, ts + d.SLG);  // this slice's frames
 
-  // This thread: frame tid / 2 of each pass, subarrays [l0, l0 + LH) (those < L).
-  const int tf = tid >> 1, h = tid & 1, l0 = h * LH;
-  R xv[2][LH][2 * ML], lam[2][N], gv = 0;
+  float gl[N][ML];
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const int tl = p * PF + tf;
-    const bool live = tl < nt;
+  for (int n = 0; n < N; ++n)
 #pragma unroll
-    for (int ll = 0; ll < LH; ++ll) {
-      const int l = min(l0 + ll, L - 1);
-      const R* src = reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + (live ? tl : 0)) * M + l * ML);
-      R tmp[2 * ML];
-      load16<R, 2 * ML>(tmp, src);
+    for (int mu = 0; mu < ML; ++mu) gl[n][mu] = g[((size_t)f * N + n) * M + l * ML + mu];
+  double acc[ML][ML2];
 #pragma unroll
-      for (int i = 0; i < 2 * ML; ++i) xv[p][ll][i] = live ? tmp[i] : (R)0;
+  for (int mu = 0; mu < ML; ++mu)
+#pragma unroll
+    for (int e = 0; e < ML2; ++e) acc[mu][e] = 0.0;
+
+  const float* xb = reinterpret_cast<const float*>(X + (size_t)f * T * M + l * ML);
+  const float* lb = lamin + (size_t)f * N * T;
+  for (int t0 = ts + j; t0 < te; t0 += FB * kGDL) {
+    float xv[FB][2 * ML], lam[FB][N];
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+      const int t = min(t0 + u * kGDL, te - 1);
+      load16<float, 2 * ML>(xv[u], xb + (size_t)t * 2 * M);
+#pragma unroll
+      for (int n = 0; n < N; ++n) lam[u][n] = lb[(size_t)n * T + t];
     }
+    sched_fence();
 #pragma unroll
-    for (int n = 0; n < N; ++n) lam[p][n] = live ? lamin[((size_t)f * N + n) * T + t0 + tl] : (R)0;
-  }
-  if (tid < N * M) gv = g[(size_t)f * N * M + tid];
-  sched_fence();
-  if (tid < N * M) sg[tid] = gv;
-
-  // Lane i, op group q: block b = 16 q + i / 4 = (subarray l, entry group jg); A row (mu) and
-  // B column (entry) = i % 4.
-  const int sub = lane & 3;
-  v4f acc[NG];
-  int aoff[NG], boff[NG];
-  bool aok[NG], bok[NG];  // A: row mu = sub of the block; B: packed entry j
-#pragma unroll
-  for (int q = 0; q < NG; ++q) {
-    acc[q] = v4f{0, 0, 0, 0};
-    const int b = 16 * q + (lane >> 2), l = b / JG4, jg = b - l * JG4, j = 4 * jg + sub;
-    aok[q] = l < L && sub < ML;
-    bok[q] = l < L && j < ML2;
-    aoff[q] = aok[q] ? l * ML + sub : 0;
-    boff[q] = bok[q] ? l * ML2 + j : 0;
-  }
-
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const int np = min(max(nt - p * PF, 0), PF);  // frames of this pass
-    __syncthreads();  // sg staged (first pass) / previous pass's rows consumed
-    if (np == 0) break;
-    const bool live = tf < np;
-#pragma unroll
-    for (int ll = 0; ll < LH; ++ll) {
-      const int l = l0 + ll;
-      if (l >= L) break;
-      R inv[ML];
+    for (int u = 0; u < FB; ++u) {
+      if (t0 + u * kGDL >= te) break;
+      double w[ML];
 #pragma unroll
       for (int mu = 0; mu < ML; ++mu) {
-        R y = 0;
+        float y = 0.0f;
 #pragma unroll
-        for (int n = 0; n < N; ++n) y += lam[p][n] * sg[n * M + l * ML + mu];
-        inv[mu] = live ? rcp(rmax(y, (R)d.eps)) : (R)0;
+        for (int n = 0; n < N; ++n) y += lam[u][n] * gl[n][mu];
+        w[mu] = (double)rcp(rmax(y, (float)d.eps));
       }
-      R op[ML2];
+      double xd[2 * ML], pr[ML2];
+#pragma unroll
+      for (int i = 0; i < 2 * ML; ++i) xd[i] = (double)xv[u][i];
 #pragma unroll
       for (int a = 0; a < ML; ++a) {
-        const R ar = xv[p][ll][2 * a], ai = xv[p][ll][2 * a + 1];
-        op[a] = ar * ar + ai * ai;
+        pr[a] = xd[2 * a] * xd[2 * a] + xd[2 * a + 1] * xd[2 * a + 1];
 #pragma unroll
         for (int b = a + 1; b < ML; ++b) {
-          const int j = ML + 2 * (a * ML - a * (a + 1) / 2 + (b - a - 1));
-          const R br = xv[p][ll][2 * b], bi = xv[p][ll][2 * b + 1];
-          op[j] = ar * br + ai * bi;
-          op[j + 1] = ai * br - ar * bi;
+          const int e = ML + 2 * (a * ML - a * (a + 1) / 2 + (b - a - 1));
+          pr[e] = xd[2 * a] * xd[2 * b] + xd[2 * a + 1] * xd[2 * b + 1];
+          pr[e + 1] = xd[2 * a + 1] * xd[2 * b] - xd[2 * a] * xd[2 * b + 1];
         }
       }
-      if (ML % E == 0) {
 #pragma unroll
-        for (int i = 0; i < ML / E; ++i) {
-          v4f v;
+      for (int mu = 0; mu < ML; ++mu)
 #pragma unroll
-          for (int e = 0; e < E; ++e) v[e] = inv[i * E + e];
-          *reinterpret_cast<v4f*>(sInv + tf * MP + l * ML + i * E) = v;
-        }
-      } else {
-#pragma unroll
-        for (int mu = 0; mu < ML; ++mu) sInv[tf * MP + l * ML + mu] = inv[mu];
-      }
-#pragma unroll
-      for (int i = 0; i < ML2 / E; ++i) {
-        v4f v;
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = op[i * E + e];
-        *reinterpret_cast<v4f*>(sOp + tf * OP + l * ML2 + i * E) = v;
-      }
-    }
-    __syncthreads();
-    // Frames [32 wave, 32 wave + 32) of the pass, rounded up to 4 (rows past np are zero).
-    const int fb = 32 * wave, fe = min(fb + 32, (np + 3) & ~3);
-    for (int t4 = fb; t4 < fe; t4 += 4) {
-      R av[4][NG], bv[4][NG];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < NG; ++q) {
-          const R a = sInv[(t4 + u) * MP + aoff[q]], b = sOp[(t4 + u) * OP + boff[q]];
-          av[u][q] = aok[q] ? a : (R)0;
-          bv[u][q] = bok[q] ? b : (R)0;
-        }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < NG; ++q) acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
+        for (int e = 0; e < ML2; ++e) acc[mu][e] += w[mu] * pr[e];
     }
   }
-  __syncthreads();  // both waves done with the product rows
-  if (wave == 1)
+
+  // Sum the kGDL lanes of each subarray, OC outputs at a time, in lane order.
+  double* out = V + ((size_t)f * d.SG + sl) * d.VF;
 #pragma unroll
-    for (int q = 0; q < NG; ++q)
+  for (int c0 = 0; c0 < NO; c0 += OC) {
+    __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sRed[(q * 64 + lane) * 4 + r] = acc[q][r];
-  __syncthreads();
-  if (wave == 0) {
-    R* out = Vpart + ((size_t)f * d.S + s) * d.VF;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      const int b = 16 * q + (lane >> 2), l = b / JG4, jg = b - l * JG4, j = 4 * jg + sub;
-      if (l < L && j < ML2)
-#pragma unroll
-        for (int r = 0; r < ML; ++r)
-          out[(size_t)l * ML * ML2 + r * ML2 + j] = acc[q][r] + sRed[(q * 64 + lane) * 4 + r];
+    for (int o = 0; o < OC; ++o) {
+      const int oo = c0 + o;
+      if (oo < NO) red[o * NT + tid] = live ? acc[oo / ML2][oo % ML2] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < L * OC; e += NT) {
+      const int ls = e / OC, o = e - ls * OC, oo = c0 + o;
+      if (oo >= NO) continue;
+      double s = 0.0;
+      for (int jj = 0; jj < kGDL; ++jj) s += red[o * NT + ls * kGDL + jj];
+      out[ls * NO + oo] = s;
     }
   }
 }
@@ -1306,8 +1245,8 @@ struct Set {
         break;
       case kFGram:
         if constexpr (sizeof(R) == 4 && (ML == 2 || ML == 4)) {
-          hipLaunchKernelGGL((k_gram4_f<R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), 0, s, d, X,
-                             static_cast<const R*>(b.lam), g, static_cast<R*>(b.Vpart));
+          hipLaunchKernelGGL((k_gramd_f<N, K, ML, L>), dim3(d.F, d.SG), dim3(gramd_threads<L>()), 0, s, d, X,
+                             static_cast<const R*>(b.lam), g, static_cast<double*>(b.Vpart));
         } else {
           hipLaunchKernelGGL((k_gram_f<R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d, X,
                              static_cast<const R*>(b.lam), g, static_cast<R*>(b.Vpart));
@@ -1316,7 +1255,7 @@ struct Set {
       case kFIp:
         if constexpr (ML <= 4) {
           hipLaunchKernelGGL((k_ip_f<R, ML>), dim3((d.F * L + 64 / ML - 1) / (64 / ML)), dim3(64), 0, s, d,
-                             static_cast<const R*>(b.Vpart), Q, b.logdet, b.status);
+                             static_cast<const double*>(b.Vpart), Q, b.logdet, b.status);
         } else {
           return launch_kernel(d, b, sizeof(R) == 4 ? DFM_C64 : DFM_C128, kKIp, s);
         }
@@ -1373,6 +1312,12 @@ size_t fast_max_smem(const Dims& d, int dtype) {
 #undef DFM_SMEM
   }
   return 0;
+}
+
+const char* fast_kernel_name(const Dims& d, int dtype, int kid) {
+  if (kid == kFGram && dtype == DFM_C64 && (d.ML == 2 || d.ML == 4)) return "k_gramd_f";
+  if (kid == kFIp && d.ML > 4) return kernel_name(kKIp);
+  return kernel_name(kid);
 }
 
 hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s) {

@@ -33,6 +33,9 @@ struct Dims {
   int ML;    // common subarray size when the partition is uniform, else 0
   int SLP;   // LDS row stride (elements) of per-frame arrays in the specialised kernels
   int TP;    // frames rounded up to 16: row length of the coefficient planes (specialised kernels)
+  int SG;    // slices of the covariance partials (FP64-sum kernel: SG slices of SLG frames; else S)
+  int SLG;   // frames per slice of the FP64-sum covariance kernel
+  int VD;    // 1 if the covariance partials are FP64
   int mics[kMaxL];  // M_l
   int moff[kMaxL];  // first mic of subarray l
   int qoff[kMaxL];  // offset of block l in a frequency's packed Q (complex units)
@@ -48,7 +51,7 @@ struct Buffers {
   void* W;
   void* H;
   void* P;       // [F][T][M] real: |Q x|^2 of the latest W sub-step
-  void* Vpart;   // [F][S][VF] real: per-slice packed covariance sums
+  void* Vpart;   // [F][SG][VF] packed covariance sums, FP64 if VD else the plan's real type
   void* Wpart;   // [F][S][N][K][2] real (generic kernels)
   void* Hpart;   // [FS][N][K][T][2] real (generic kernels)
   void* gpart;   // [F][S][N][M][2] real (generic kernels)
@@ -82,6 +85,7 @@ int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns 
 int fast_set_index(int N, int K, int ML, int L);
 size_t fast_max_smem(const Dims& d, int dtype);
 hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
+const char* fast_kernel_name(const Dims& d, int dtype, int kid);  // symbol family a kernel id runs
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s);
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
 hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);

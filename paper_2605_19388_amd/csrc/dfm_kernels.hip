@@ -522,8 +522,8 @@ __global__ __launch_bounds__(kBlock) void k_sep(Dims d, const cx<R>* __restrict_
 }
 
 // Full Hermitian covariances from the slice sums (diagnostic export of eq. (14)).
-template <typename R>
-__global__ void k_expand(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict__ V) {
+template <typename R, typename VT>
+__global__ void k_expand(Dims d, const VT* __restrict__ Vpart, cx<R>* __restrict__ V) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d.F * d.VF) return;
   const int f = idx / d.VF, r = idx - f * d.VF;
@@ -534,7 +534,7 @@ __global__ void k_expand(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict_
   int a, b, part;
   packed_pair(Ml, rl - mu * Ml * Ml, a, b, part);
   double acc = 0.0;
-  for (int s = 0; s < d.S; ++s) acc += (double)Vpart[((size_t)f * d.S + s) * d.VF + r];
+  for (int s = 0; s < d.SG; ++s) acc += (double)Vpart[((size_t)f * d.SG + s) * d.VF + r];
   const R v = (R)(acc / d.T);
   cx<R>* vb = V + (size_t)f * d.VC + d.voff[l] + mu * Ml * Ml;
   if (a == b) {
@@ -663,8 +663,12 @@ static hipError_t cov_impl(const Dims& d, const Buffers& b, void* V, hipStream_t
                        static_cast<const cx<R>*>(b.X), static_cast<const R*>(b.W), static_cast<const R*>(b.H),
                        static_cast<const R*>(b.g), static_cast<R*>(b.Vpart));
   }
-  hipLaunchKernelGGL(k_expand<R>, dim3(cdiv((size_t)d.F * d.VF, kBlock)), dim3(kBlock), 0, s, d,
-                     static_cast<const R*>(b.Vpart), static_cast<cx<R>*>(V));
+  if (d.VD)
+    hipLaunchKernelGGL((k_expand<R, double>), dim3(cdiv((size_t)d.F * d.VF, kBlock)), dim3(kBlock), 0, s, d,
+                       static_cast<const double*>(b.Vpart), static_cast<cx<R>*>(V));
+  else
+    hipLaunchKernelGGL((k_expand<R, R>), dim3(cdiv((size_t)d.F * d.VF, kBlock)), dim3(kBlock), 0, s, d,
+                       static_cast<const R*>(b.Vpart), static_cast<cx<R>*>(V));
   return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@ the same seeded inputs.  Tolerances:
 * FP32 end to end: 1e-4 relative on the cost and on each source's separated
   spectrogram, the bar the method is held to.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -74,7 +76,7 @@ STAGE_CASES = [
     (33, 130, (2, 2), 2, 4),
 ]
 
-FAST = ["k_gram_f", "k_ip_f", "k_pw_f", "k_wgemm_f", "k_h_f", "k_hgemm_f", "k_g_f"]
+FAST = ["k_gramd_f", "k_ip_f", "k_pw_f", "k_wgemm_f", "k_h_f", "k_hgemm_f", "k_g_f"]
 GENERIC = ["k_gram", "k_ip", "k_pw", "k_wapply", "k_h", "k_happly", "k_g", "k_gapply"]
 
 
@@ -170,6 +172,38 @@ def test_end_to_end_small_2x2(fp32):
     Sref = D.separate(X, *ref, mics)
     for n in range(N):
         assert rel(S[n], Sref[n]) < (1e-4 if fp32 else 1e-10), n
+
+
+# ------------------------------------------------------------------ end to end, paper_4x4 workload
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_4x4_oracle.npz")
+
+
+def test_end_to_end_paper_4x4_fp32():
+    """FP32 path at full size (F=513, T=625, four 4-mic subarrays, N=5, K=16), in the launch
+    configuration bench.py times, against the oracle's stored trajectory on the same rounded
+    inputs (tests/golden/make_paper_4x4.py): the cost at every checkpoint up to 100
+    iterations and 8192 sampled entries of the separated images, 1e-4 relative per source."""
+    ref = np.load(GOLDEN)
+    w = synth.make("paper_4x4")
+    mics, N, K = w["mics"], w["N"], w["K"]
+    X, Q, g, W, H = (as_precision(w[k], True) for k in ("X", "Q", "g", "W", "H"))
+    F, T, M = X.shape
+    p = plan(X, mics, N, K, Q, g, W, H, True)
+    assert p.kernel_names()[0] == "k_gramd_f"  # the specialised kernels bench.py times
+    done = 0
+    for c, cost in zip(ref["checkpoints"], ref["costs"]):
+        p.step(int(c) - done)
+        done = int(c)
+        got = p.nll()
+        assert nll_rel(got, cost, F, T, M) < 1e-4, (int(c), got, cost)
+    p.sync_status()
+    S = p.separate()
+    idx = torch.as_tensor(ref["sample_index"].astype(np.int64), device=S.device)
+    got = S[idx[0], idx[1], idx[2], idx[3]].cpu().numpy()
+    want = ref["sample_values"]
+    for n in range(N):
+        sel = ref["sample_index"][0] == n
+        assert rel(got[sel], want[sel]) < 1e-4, n
 
 
 # ------------------------------------------------------------------ invariants of the GPU result
