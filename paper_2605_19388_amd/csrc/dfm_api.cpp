@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -37,6 +38,15 @@ static int max_slice() {
 
 // Specialised path: uniform partition with a compiled (N, K, M_l) set.  Frames per slice:
 // the largest of max_slice(), ..., 16 whose LDS needs fit 64 KB in every kernel.
+// Compute units of the current device (the balanced covariance kernel sizes its grid to it).
+static int compute_units() {
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cu <= 0)
+    return 256;
+  return cu;
+}
+
 static bool choose_fast(Dims& d, int dtype) {
   int ml = d.mics[0];
   for (int l = 1; l < d.L; ++l)
@@ -52,10 +62,19 @@ static bool choose_fast(Dims& d, int dtype) {
     d.TB = 16;
     d.TBN = (d.T + 15) / 16;
     d.TP = (d.T + 15) & ~15;
-    const bool fp64_sums = dtype == DFM_C64 && (ml == 2 || ml == 4);  // k_gramd_f
-    d.SG = !fp64_sums ? d.S : 1;  // k_gramd_f: one workgroup per bin (frame slices supported)
-    d.SLG = (d.T + d.SG - 1) / d.SG;
-    d.VD = fp64_sums || dtype == DFM_C128;
+    // k_gramd_f: four workgroups per CU share the F*T frames equally; a bin then has one
+    // partial-sum slot per workgroup that touched it.
+    if (dtype == DFM_C64 && (ml == 2 || ml == 4)) {
+      const long long total = (long long)d.F * d.T;
+      const long long want = 4LL * compute_units();
+      d.GR = (int)std::max<long long>((total + want - 1) / want, 32);
+      d.GW = (int)((total + d.GR - 1) / d.GR);
+      d.SG = (d.T + d.GR - 1) / d.GR + 1;
+    } else {
+      d.GR = 0;
+      d.GW = 0;
+      d.SG = d.S;
+    }
     if (fast_max_smem(d, dtype) <= 64 * 1024) return true;
   }
   d.fast = -1;
@@ -82,8 +101,8 @@ static void choose_tiles(Dims& d, int dtype) {
   d.FS = (d.F + d.FB - 1) / d.FB;
   d.TBN = (d.T + d.TB - 1) / d.TB;
   d.SG = d.S;
-  d.SLG = d.SL;
-  d.VD = dtype == DFM_C128;
+  d.GR = 0;
+  d.GW = 0;
 }
 
 static dfm_status make_dims(const dfm_problem* p, Dims& d) {
@@ -128,7 +147,7 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   const size_t r = real_size(dtype);
   size_t n = 0;
   n += al(r * d.F * d.T * d.M);                        // P
-  n += al((d.VD ? 8 : r) * (size_t)d.F * d.SG * d.VF);   // Vpart
+  n += al(8 * (size_t)d.F * d.SG * d.VF);              // Vpart (FP64 sums)
   const bool fast = d.fast >= 0;
   n += al(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);    // Wpart
   n += al(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);  // Hpart
@@ -152,7 +171,7 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
     return q;
   };
   b.P = take(r * d.F * d.T * d.M);
-  b.Vpart = take((d.VD ? 8 : r) * (size_t)d.F * d.SG * d.VF);
+  b.Vpart = take(8 * (size_t)d.F * d.SG * d.VF);
   const bool fast = d.fast >= 0;
   b.Wpart = take(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);
   b.Hpart = take(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);

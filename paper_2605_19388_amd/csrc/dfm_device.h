@@ -53,6 +53,13 @@ __device__ __forceinline__ void packed_pair(int Ml, int j, int& a, int& b, int& 
   b = row + 1 + p;
 }
 
+// Partial-sum slots of bin f's covariances: the S frame slices, or, for the balanced
+// covariance kernel (ranges of GR flattened frames), one per workgroup that touched f.
+__device__ __forceinline__ int cov_slots(const Dims& d, int f) {
+  if (d.GR <= 0) return d.SG;
+  return (int)((((long long)f + 1) * d.T - 1) / d.GR - ((long long)f * d.T) / d.GR) + 1;
+}
+
 __device__ __forceinline__ int subarray_of_vidx(const Dims& d, int idx) {
   int l = 0;
   while (l + 1 < d.L && idx >= d.voff[l + 1]) ++l;

@@ -199,7 +199,8 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
 #pragma unroll
     for (int j = 0; j < ML2; ++j) vs[j] = 0.0;
     const double* vp = Vpart + (size_t)f * d.SG * d.VF + (size_t)l * ML * ML2 + r * ML2;
-    for (int s = 0; s < d.SG; ++s) {
+    const int ns = cov_slots(d, f);
+    for (int s = 0; s < ns; ++s) {
       double part[ML2];
 #pragma unroll
       for (int j = 0; j < ML2; ++j) part[j] = vp[(size_t)s * d.VF + j];
@@ -311,9 +312,9 @@ struct GramShape {
   static constexpr int OP = kPre ? padded<R>(OF) : padded<R>(2 * M);
 };
 
-template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__ X,
-                                               const R* __restrict__ lamin, const R* __restrict__ g,
+template <typename R, typename RI, int N, int K, int ML, int L>
+__global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<RI>* __restrict__ X,
+                                               const RI* __restrict__ lamin, const RI* __restrict__ g,
                                                R* __restrict__ Vpart) {
   typedef GramShape<R, N, K, ML, L> G;
   constexpr int M = G::M, ML2 = G::ML2, OF = G::OF, MP = G::MP, OP = G::OP;
@@ -337,16 +338,19 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__
   // One batch of loads: x and lambda at this thread's frame, one value of g.
   R xv[2 * M], lam[N], gv = 0;
   if (tid < nt) {
-    load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + tid) * M));
+    RI xin[2 * M];
+    load16<RI, 2 * M>(xin, reinterpret_cast<const RI*>(X + ((size_t)f * T + t0 + tid) * M));
 #pragma unroll
-    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
+    for (int i = 0; i < 2 * M; ++i) xv[i] = (R)xin[i];
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[n] = (R)lamin[((size_t)f * N + n) * T + t0 + tid];
   } else {  // padding frames contribute zero products
 #pragma unroll
     for (int i = 0; i < 2 * M; ++i) xv[i] = 0;
 #pragma unroll
     for (int n = 0; n < N; ++n) lam[n] = 0;
   }
-  if (tid < N * M) gv = g[(size_t)f * N * M + tid];
+  if (tid < N * M) gv = (R)g[(size_t)f * N * M + tid];
   sched_fence();
   if (tid < N * M) sg[tid] = gv;
   __syncthreads();
@@ -455,20 +459,49 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<R>* __restrict__
 
 // ------------------------------------------------------------------------------------
 // Weighted covariances (eq. (14)) for subarrays of M_l <= 4 mics, FP32 inputs, FP64 sums.
-// One workgroup per frequency and kGDL lanes per subarray: lane j of subarray l takes
-// frames t = j, j + kGDL, ...; per frame it forms 1/y for the subarray's mics (FP32), the
+// A fixed number of workgroups (two per CU) share the flattened (f, t) frames equally, so
+// every SIMD gets the same work; kGDH x kGDL lanes per subarray: lane j of row half h takes
+// frames t = j, j + kGDL, ... of each bin segment and sums the rows mu of that half; per frame it forms 1/y for the subarray's mics (FP32), the
 // packed entries of x^(l) x^(l)H in FP64 (exact: products of FP32 values) and adds
 // (1/y_mu) x x^H into M_l x M_l^2 FP64 registers; the lanes' sums are then added through LDS
-// in lane order (frames split into SG slices, one workgroup each).  FP32 sums over frames would leave rounding errors outside the dominant
+// in a fixed order, one slot per (bin, workgroup).  FP32 sums over frames would leave rounding errors outside the dominant
 // directions of V, which the solve of eq. (15) amplifies by cond(V) -- large at the
 // lowest bins, where the mixing is nearly rank-deficient; FP64 sums keep the solve's
 // input at the precision of the FP64 reference.  Output: V[f][slice][packed entries], FP64,
 // /T not applied.
 constexpr int kGDL = 32;  // lanes per subarray
 
+constexpr int kGDH = 1;   // lanes per frame (each sums ML / kGDH of the rows mu)
+
 template <int L>
 constexpr int gramd_threads() {
-  return (L * kGDL + 63) / 64 * 64;
+  return (kGDH * L * kGDL + 63) / 64 * 64;
+}
+
+// Sum of v[0..CUR) over the kGDL lanes of a subarray group by recursive halving: at each
+// step (lane mask MASK) a lane keeps one half of its values, sends the other half to its
+// partner and adds what it receives; once one value is left the remaining masks add it
+// outright.  The lane ends with the totals of outputs [off, off + CUR / 2^steps).  The
+// order of the additions is fixed, so the result is reproducible.
+template <int CUR, int MASK>
+__device__ __forceinline__ void lane_reduce(double* v, int j, int& off) {
+  if constexpr (MASK > 0) {
+    if constexpr (CUR >= 2) {
+      constexpr int h = CUR / 2;
+      const bool up = (j & MASK) != 0;
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const double lo = v[i], hi = v[i + h];
+        const double got = __shfl_xor(up ? lo : hi, MASK, kGDL);
+        v[i] = (up ? hi : lo) + got;
+      }
+      off += up ? h : 0;
+      lane_reduce<h, MASK / 2>(v, j, off);
+    } else {
+      v[0] += __shfl_xor(v[0], MASK, kGDL);
+      lane_reduce<CUR, MASK / 2>(v, j, off);
+    }
+  }
 }
 
 template <int N, int K, int ML, int L>
@@ -476,88 +509,98 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
                                                                const float* __restrict__ lamin,
                                                                const float* __restrict__ g,
                                                                double* __restrict__ V) {
-  constexpr int M = ML * L, ML2 = ML * ML, NO = ML * ML2, NT = gramd_threads<L>();
-  constexpr int FB = 4;  // frames per load batch
+  constexpr int M = ML * L, ML2 = ML * ML, MH = ML / kGDH, NO = MH * ML2;  // outputs per lane
+  constexpr int FB = 2;  // frames per load batch; the next batch is in flight during the current one
   static_assert(ML == 2 || ML == 4, "M_l of 2 or 4");
-  constexpr int OC = 16;                                 // outputs per LDS reduction chunk
-  __shared__ double red[NT * OC];
-  const int f = blockIdx.x, sl = blockIdx.y, tid = threadIdx.x;  // frequency, frame slice
-  const int l = min(tid / kGDL, L - 1), j = tid % kGDL;
-  const bool live = tid < L * kGDL;
+  const int tid = threadIdx.x;
+  const int h = tid / (L * kGDL), l = min(tid / kGDL % L, L - 1), j = tid % kGDL;  // row half, subarray, lane
+  const bool live = tid < kGDH * L * kGDL;
   const int T = d.T;
-  const int ts = sl * d.SLG, te = min(T, ts + d.SLG);  // this slice's frames
+  // This workgroup's share of the flattened (f, t) frames; it may span several bins, each
+  // summed as one segment into slot (workgroup - first workgroup of the bin).
+  const long long total = (long long)d.F * T;
+  const long long a0 = (long long)blockIdx.x * d.GR, a1 = min(total, a0 + d.GR);
+  for (long long i0 = a0; i0 < a1;) {
+    const int f = (int)(i0 / T);
+    const long long fend = min(a1, (long long)(f + 1) * T);
+    const int ts = (int)(i0 - (long long)f * T), te = (int)(fend - (long long)f * T);
+    const int slot = blockIdx.x - (int)(((long long)f * T) / d.GR);
+    i0 = fend;
 
-  float gl[N][ML];
+    float gl[N][MH];
 #pragma unroll
-  for (int n = 0; n < N; ++n)
+    for (int n = 0; n < N; ++n)
 #pragma unroll
-    for (int mu = 0; mu < ML; ++mu) gl[n][mu] = g[((size_t)f * N + n) * M + l * ML + mu];
-  double acc[ML][ML2];
+      for (int mu = 0; mu < MH; ++mu) gl[n][mu] = g[((size_t)f * N + n) * M + l * ML + min(h, kGDH - 1) * MH + mu];
+    double acc[NO];
 #pragma unroll
-  for (int mu = 0; mu < ML; ++mu)
-#pragma unroll
-    for (int e = 0; e < ML2; ++e) acc[mu][e] = 0.0;
+    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
 
-  const float* xb = reinterpret_cast<const float*>(X + (size_t)f * T * M + l * ML);
-  const float* lb = lamin + (size_t)f * N * T;
-  for (int t0 = ts + j; t0 < te; t0 += FB * kGDL) {
-    float xv[FB][2 * ML], lam[FB][N];
+    const float* xb = reinterpret_cast<const float*>(X + (size_t)f * T * M + l * ML);
+    const float* lb = lamin + (size_t)f * N * T;
+    float xv[FB][2 * ML], lam[FB][N], xn[FB][2 * ML], ln[FB][N];
+    auto fetch = [&](int t0, float (&x)[FB][2 * ML], float (&la)[FB][N]) {
 #pragma unroll
-    for (int u = 0; u < FB; ++u) {
-      const int t = min(t0 + u * kGDL, te - 1);
-      load16<float, 2 * ML>(xv[u], xb + (size_t)t * 2 * M);
+      for (int u = 0; u < FB; ++u) {
+        const int t = min(t0 + u * kGDL, te - 1);
+        load16<float, 2 * ML>(x[u], xb + (size_t)t * 2 * M);
 #pragma unroll
-      for (int n = 0; n < N; ++n) lam[u][n] = lb[(size_t)n * T + t];
-    }
-    sched_fence();
-#pragma unroll
-    for (int u = 0; u < FB; ++u) {
-      if (t0 + u * kGDL >= te) break;
-      double w[ML];
-#pragma unroll
-      for (int mu = 0; mu < ML; ++mu) {
-        float y = 0.0f;
-#pragma unroll
-        for (int n = 0; n < N; ++n) y += lam[u][n] * gl[n][mu];
-        w[mu] = (double)rcp(rmax(y, (float)d.eps));
+        for (int n = 0; n < N; ++n) la[u][n] = lb[(size_t)n * T + t];
       }
-      double xd[2 * ML], pr[ML2];
+    };
+    if (ts + j < te) fetch(ts + j, xv, lam);
+    for (int t0 = ts + j; t0 < te; t0 += FB * kGDL) {
+      if (t0 + FB * kGDL < te) fetch(t0 + FB * kGDL, xn, ln);
+      sched_fence();
 #pragma unroll
-      for (int i = 0; i < 2 * ML; ++i) xd[i] = (double)xv[u][i];
+      for (int u = 0; u < FB; ++u) {
+        if (t0 + u * kGDL >= te) break;
+        double w[MH];
 #pragma unroll
-      for (int a = 0; a < ML; ++a) {
-        pr[a] = xd[2 * a] * xd[2 * a] + xd[2 * a + 1] * xd[2 * a + 1];
+        for (int mu = 0; mu < MH; ++mu) {
+          float y = 0.0f;
 #pragma unroll
-        for (int b = a + 1; b < ML; ++b) {
-          const int e = ML + 2 * (a * ML - a * (a + 1) / 2 + (b - a - 1));
-          pr[e] = xd[2 * a] * xd[2 * b] + xd[2 * a + 1] * xd[2 * b + 1];
-          pr[e + 1] = xd[2 * a + 1] * xd[2 * b] - xd[2 * a] * xd[2 * b + 1];
+          for (int n = 0; n < N; ++n) y += lam[u][n] * gl[n][mu];
+          w[mu] = (double)rcp(rmax(y, (float)d.eps));
         }
+        double xd[2 * ML], pr[ML2];
+#pragma unroll
+        for (int i = 0; i < 2 * ML; ++i) xd[i] = (double)xv[u][i];
+#pragma unroll
+        for (int a = 0; a < ML; ++a) {
+          pr[a] = xd[2 * a] * xd[2 * a] + xd[2 * a + 1] * xd[2 * a + 1];
+#pragma unroll
+          for (int b = a + 1; b < ML; ++b) {
+            const int e = ML + 2 * (a * ML - a * (a + 1) / 2 + (b - a - 1));
+            pr[e] = xd[2 * a] * xd[2 * b] + xd[2 * a + 1] * xd[2 * b + 1];
+            pr[e + 1] = xd[2 * a + 1] * xd[2 * b] - xd[2 * a] * xd[2 * b + 1];
+          }
+        }
+#pragma unroll
+        for (int mu = 0; mu < MH; ++mu)
+#pragma unroll
+          for (int e = 0; e < ML2; ++e) acc[mu * ML2 + e] += w[mu] * pr[e];
       }
+      sched_fence();
 #pragma unroll
-      for (int mu = 0; mu < ML; ++mu)
+      for (int u = 0; u < FB; ++u) {
 #pragma unroll
-        for (int e = 0; e < ML2; ++e) acc[mu][e] += w[mu] * pr[e];
+        for (int i = 0; i < 2 * ML; ++i) xv[u][i] = xn[u][i];
+#pragma unroll
+        for (int n = 0; n < N; ++n) lam[u][n] = ln[u][n];
+      }
     }
-  }
 
-  // Sum the kGDL lanes of each subarray, OC outputs at a time, in lane order.
-  double* out = V + ((size_t)f * d.SG + sl) * d.VF;
+    // Totals over the subarray's lanes; lane j then holds outputs [off, off + NO / kGDL) (at
+    // least one; for NO < kGDL several lanes hold the same total and the first one writes).
+    int off = 0;
+    lane_reduce<NO, kGDL / 2>(acc, j, off);
+    constexpr int PER = NO >= kGDL ? NO / kGDL : 1;
+    constexpr int REP = NO >= kGDL ? 1 : kGDL / NO;  // lanes holding the same totals
+    if (live && j % REP == 0) {
+      double* out = V + ((size_t)f * d.SG + slot) * d.VF + (size_t)l * ML * ML2 + (size_t)h * NO + off;
 #pragma unroll
-  for (int c0 = 0; c0 < NO; c0 += OC) {
-    __syncthreads();
-#pragma unroll
-    for (int o = 0; o < OC; ++o) {
-      const int oo = c0 + o;
-      if (oo < NO) red[o * NT + tid] = live ? acc[oo / ML2][oo % ML2] : 0.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < L * OC; e += NT) {
-      const int ls = e / OC, o = e - ls * OC, oo = c0 + o;
-      if (oo >= NO) continue;
-      double s = 0.0;
-      for (int jj = 0; jj < kGDL; ++jj) s += red[o * NT + ls * kGDL + jj];
-      out[ls * NO + oo] = s;
+      for (int i = 0; i < PER; ++i) out[i] = acc[i];
     }
   }
 }
@@ -1221,11 +1264,14 @@ __global__ __launch_bounds__(kGT) void k_g_f(Dims d, const R* __restrict__ lamin
 template <typename R, int N, int K, int ML, int L>
 struct Set {
   static constexpr int M = ML * L;
+  // FP32 sets with M_l <= 4 sum the covariances with k_gramd_f (no dynamic LDS); every other
+  // set runs k_gram_f in FP64 on the plan's inputs.
+  static constexpr bool kGramD = sizeof(R) == 4 && (ML == 2 || ML == 4);
   static size_t smem_gram(const Dims& d) {
-    typedef GramShape<R, N, K, ML, L> G;
-    return align_up(sizeof(R) * N * M, 16) + sizeof(R) * (size_t)d.SLP * (G::MP + G::OP);
+    typedef GramShape<double, N, K, ML, L> G;
+    return align_up(sizeof(double) * N * M, 16) + sizeof(double) * (size_t)d.SLP * (G::MP + G::OP);
   }
-  static size_t max_smem(const Dims& d) { return smem_gram(d); }
+  static size_t max_smem(const Dims& d) { return kGramD ? 0 : smem_gram(d); }
 
   static hipError_t launch(const Dims& d, const Buffers& b, int kid, hipStream_t s) {
     const cx<R>* X = static_cast<const cx<R>*>(b.X);
@@ -1244,12 +1290,12 @@ struct Set {
                            static_cast<R*>(b.lam));
         break;
       case kFGram:
-        if constexpr (sizeof(R) == 4 && (ML == 2 || ML == 4)) {
-          hipLaunchKernelGGL((k_gramd_f<N, K, ML, L>), dim3(d.F, d.SG), dim3(gramd_threads<L>()), 0, s, d, X,
+        if constexpr (kGramD) {
+          hipLaunchKernelGGL((k_gramd_f<N, K, ML, L>), dim3(d.GW), dim3(gramd_threads<L>()), 0, s, d, X,
                              static_cast<const R*>(b.lam), g, static_cast<double*>(b.Vpart));
         } else {
-          hipLaunchKernelGGL((k_gram_f<R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d, X,
-                             static_cast<const R*>(b.lam), g, static_cast<R*>(b.Vpart));
+          hipLaunchKernelGGL((k_gram_f<double, R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d,
+                             X, static_cast<const R*>(b.lam), g, static_cast<double*>(b.Vpart));
         }
         break;
       case kFIp:

@@ -33,9 +33,9 @@ struct Dims {
   int ML;    // common subarray size when the partition is uniform, else 0
   int SLP;   // LDS row stride (elements) of per-frame arrays in the specialised kernels
   int TP;    // frames rounded up to 16: row length of the coefficient planes (specialised kernels)
-  int SG;    // slices of the covariance partials (FP64-sum kernel: SG slices of SLG frames; else S)
-  int SLG;   // frames per slice of the FP64-sum covariance kernel
-  int VD;    // 1 if the covariance partials are FP64
+  int SG;    // partial-sum slots per bin of the covariances (S slices, or balanced ranges, below)
+  int GR;    // k_gramd_f: flattened (f, t) frames per workgroup (0: per-slice partials)
+  int GW;    // k_gramd_f: workgroups
   int mics[kMaxL];  // M_l
   int moff[kMaxL];  // first mic of subarray l
   int qoff[kMaxL];  // offset of block l in a frequency's packed Q (complex units)
@@ -51,7 +51,7 @@ struct Buffers {
   void* W;
   void* H;
   void* P;       // [F][T][M] real: |Q x|^2 of the latest W sub-step
-  void* Vpart;   // [F][SG][VF] packed covariance sums, FP64 if VD else the plan's real type
+  void* Vpart;   // [F][SG][VF] double: packed covariance sums (FP64 on every path)
   void* Wpart;   // [F][S][N][K][2] real (generic kernels)
   void* Hpart;   // [FS][N][K][T][2] real (generic kernels)
   void* gpart;   // [F][S][N][M][2] real (generic kernels)

@@ -24,7 +24,7 @@ namespace dfm {
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_gram(Dims d, const cx<R>* __restrict__ X, const R* __restrict__ W,
                                                  const R* __restrict__ H, const R* __restrict__ g,
-                                                 R* __restrict__ Vpart) {
+                                                 double* __restrict__ Vpart) {
   const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
   const int t0 = s * d.SL;
   const int nt = min(d.SL, d.T - t0);
@@ -50,7 +50,9 @@ __global__ __launch_bounds__(kBlock) void k_gram(Dims d, const cx<R>* __restrict
   }
   __syncthreads();
 
-  R* out = Vpart + ((size_t)f * d.S + s) * d.VF;
+  // Sums in FP64 of exact products (the solve of eq. (15) amplifies summation error by
+  // cond(V), which is large for nearly rank-deficient mixing).
+  double* out = Vpart + ((size_t)f * d.S + s) * d.VF;
   for (int idx = tid; idx < d.VF; idx += kBlock) {
     const int l = subarray_of_vidx(d, idx);
     const int Ml = d.mics[l];
@@ -59,12 +61,13 @@ __global__ __launch_bounds__(kBlock) void k_gram(Dims d, const cx<R>* __restrict
     int a, b, part;
     packed_pair(Ml, r - mu * Ml * Ml, a, b, part);
     const int o = d.moff[l];
-    R acc = 0;
+    double acc = 0.0;
     for (int tl = 0; tl < nt; ++tl) {
-      const R w = sinv[tl * d.M + o + mu];
+      const double w = sinv[tl * d.M + o + mu];
       const cx<R> xa = sx[tl * d.M + o + a];
       const cx<R> xb = sx[tl * d.M + o + b];
-      const R v = part == 0 ? xa.re * xb.re + xa.im * xb.im : xa.im * xb.re - xa.re * xb.im;
+      const double ar = xa.re, ai = xa.im, br = xb.re, bi = xb.im;
+      const double v = part == 0 ? ar * br + ai * bi : ai * br - ar * bi;
       acc += w * v;
     }
     out[idx] = acc;
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_gram(Dims d, const cx<R>* __restrict
 // solve A b = e_mu, b <- b / sqrt(max(Re b^H V_mu b, eps)), row mu of Q <- b^H.
 // Finally ln|det Q_fl| (used by the cost (13)).
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_ip(Dims d, const R* __restrict__ Vpart, cx<R>* __restrict__ Q,
+__global__ __launch_bounds__(kBlock) void k_ip(Dims d, const double* __restrict__ Vpart, cx<R>* __restrict__ Q,
                                                double* __restrict__ logdet, int* __restrict__ status) {
   const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, bd = blockDim.x;
   const int Ml = d.mics[l];
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_ip(Dims d, const R* __restrict__ Vpa
   const double invT = 1.0 / d.T;
 
   for (int mu = 0; mu < Ml; ++mu) {
-    const R* vp = Vpart + (size_t)f * d.S * d.VF + d.voff[l] + mu * Ml * Ml;
+    const double* vp = Vpart + (size_t)f * d.S * d.VF + d.voff[l] + mu * Ml * Ml;
     for (int j = tid; j < Ml * Ml; j += bd) {
       double acc = 0.0;
       for (int s = 0; s < d.S; ++s) acc += (double)vp[(size_t)s * d.VF + j];
@@ -534,7 +537,7 @@ __global__ void k_expand(Dims d, const VT* __restrict__ Vpart, cx<R>* __restrict
   int a, b, part;
   packed_pair(Ml, rl - mu * Ml * Ml, a, b, part);
   double acc = 0.0;
-  for (int s = 0; s < d.SG; ++s) acc += (double)Vpart[((size_t)f * d.SG + s) * d.VF + r];
+  for (int s = 0; s < cov_slots(d, f); ++s) acc += (double)Vpart[((size_t)f * d.SG + s) * d.VF + r];
   const R v = (R)(acc / d.T);
   cx<R>* vb = V + (size_t)f * d.VC + d.voff[l] + mu * Ml * Ml;
   if (a == b) {
@@ -592,11 +595,11 @@ static hipError_t kernel_impl(const Dims& d, const Buffers& b, int kid, hipStrea
   switch (kid) {
     case kKGram:
       hipLaunchKernelGGL(k_gram<R>, tiles, dim3(kBlock), smem_gram<R>(d), s, d, X, W, H, g,
-                         static_cast<R*>(b.Vpart));
+                         static_cast<double*>(b.Vpart));
       break;
     case kKIp:
       hipLaunchKernelGGL(k_ip<R>, dim3(d.F, d.L), dim3(ip_threads(d)), 0, s, d,
-                         static_cast<const R*>(b.Vpart), Q, b.logdet, b.status);
+                         static_cast<const double*>(b.Vpart), Q, b.logdet, b.status);
       break;
     case kKPw:
       hipLaunchKernelGGL(k_pw<R>, tiles, dim3(kBlock), smem_pw<R>(d), s, d, X, Q, W, H, g, P,
@@ -661,14 +664,10 @@ static hipError_t cov_impl(const Dims& d, const Buffers& b, void* V, hipStream_t
   } else {
     hipLaunchKernelGGL(k_gram<R>, dim3(d.F, d.S), dim3(kBlock), smem_gram<R>(d), s, d,
                        static_cast<const cx<R>*>(b.X), static_cast<const R*>(b.W), static_cast<const R*>(b.H),
-                       static_cast<const R*>(b.g), static_cast<R*>(b.Vpart));
+                       static_cast<const R*>(b.g), static_cast<double*>(b.Vpart));
   }
-  if (d.VD)
-    hipLaunchKernelGGL((k_expand<R, double>), dim3(cdiv((size_t)d.F * d.VF, kBlock)), dim3(kBlock), 0, s, d,
-                       static_cast<const double*>(b.Vpart), static_cast<cx<R>*>(V));
-  else
-    hipLaunchKernelGGL((k_expand<R, R>), dim3(cdiv((size_t)d.F * d.VF, kBlock)), dim3(kBlock), 0, s, d,
-                       static_cast<const R*>(b.Vpart), static_cast<cx<R>*>(V));
+  hipLaunchKernelGGL((k_expand<R, double>), dim3(cdiv((size_t)d.F * d.VF, kBlock)), dim3(kBlock), 0, s, d,
+                     static_cast<const double*>(b.Vpart), static_cast<cx<R>*>(V));
   return hipGetLastError();
 }
 
