@@ -1260,6 +1260,160 @@ __global__ __launch_bounds__(kGT) void k_g_f(Dims d, const R* __restrict__ lamin
 }
 
 // ------------------------------------------------------------------------------------
+// Cost (13) and the per-subarray Wiener filter for the specialised sets (M_l <= 4).
+
+// Q_fl^{-1} (FP64, for the Wiener filter) and ln|det Q_fl| (for the cost) with M_l lanes per
+// (f, l) block: lane r eliminates [Q_fl | e_r] (partial pivoting) for column r.
+template <typename R, int ML>
+__global__ __launch_bounds__(64) void k_qinv_f(Dims d, const cx<R>* __restrict__ Q, cd* __restrict__ Qinv,
+                                               double* __restrict__ logdet, int* __restrict__ status) {
+  constexpr int ML2 = ML * ML, BPW = 64 / ML;
+  const int lane = threadIdx.x, blk = lane / ML, r = lane - blk * ML;
+  const int idx = blockIdx.x * BPW + blk;
+  if (idx >= d.F * d.L) return;
+  const int f = idx / d.L, l = idx - f * d.L;
+  const cx<R>* qb = Q + (size_t)f * d.QF + l * ML2;
+  cd A[ML][ML + 1], x[ML];
+#pragma unroll
+  for (int a = 0; a < ML; ++a)
+#pragma unroll
+    for (int c = 0; c < ML; ++c) A[a][c] = {(double)qb[a * ML + c].re, (double)qb[a * ML + c].im};
+  double ld;
+  const bool ok = inverse_column<ML>(A, r, x, ld);
+  cd* out = Qinv + (size_t)f * d.QF + l * ML2;
+#pragma unroll
+  for (int a = 0; a < ML; ++a) out[a * ML + r] = x[a];
+  if (r == 0) logdet[idx] = ok ? ld : -INFINITY;
+  if (!ok && r == 0) atomicOr(status, kStSingular);
+}
+
+// Data part of the cost (13) per (f, slice): sum over frames and mics of |Q x|^2 / y + ln y,
+// one frame per thread, FP64 sums.
+template <typename R, int N, int K, int ML, int L>
+__global__ __launch_bounds__(kT) void k_nll_f(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+                                              const R* __restrict__ lamin, const R* __restrict__ g,
+                                              double* __restrict__ nllpart) {
+  constexpr int M = ML * L, ML2 = ML * ML, QF = L * ML2;
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int T = d.T, t0 = s * d.SL, nt = min(d.SL, T - t0);
+  __shared__ cx<R> sQ[QF];
+  __shared__ R sg[N * M];
+  __shared__ double red[kT / 64];
+  R xv[2 * M], lam[N];
+  const bool live = tid < nt;
+  if (live) {
+    load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + tid) * M));
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
+  }
+  for (int i = tid; i < QF; i += kT) sQ[i] = Q[(size_t)f * QF + i];
+  for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
+  sched_fence();
+  __syncthreads();
+  double acc = 0.0;
+  if (live) {
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int mu = 0; mu < ML; ++mu) {
+        R zr = 0, zi = 0;
+#pragma unroll
+        for (int c = 0; c < ML; ++c) {
+          const cx<R> q = sQ[l * ML2 + mu * ML + c];
+          const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
+          zr += q.re * xr - q.im * xi;
+          zi += q.re * xi + q.im * xr;
+        }
+        R y = 0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + l * ML + mu];
+        y = rmax(y, (R)d.eps);
+        acc += (double)((zr * zr + zi * zi) / y) + log((double)y);
+      }
+  }
+  // Workgroup sum in a fixed order: wave sums by shuffles, then the waves in order.
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kT / 64; ++w) sum += red[w];
+    nllpart[(size_t)f * d.S + s] = sum;
+  }
+}
+
+// Source images at every subarray, S_n = Q^{-1} diag(lambda_n g_n / y) Q x, one frame per thread.
+template <typename R, int N, int K, int ML, int L>
+__global__ __launch_bounds__(kT) void k_sep_f(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+                                              const cd* __restrict__ Qinv, const R* __restrict__ lamin,
+                                              const R* __restrict__ g, cx<R>* __restrict__ S) {
+  constexpr int M = ML * L, ML2 = ML * ML, QF = L * ML2;
+  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int T = d.T, t0 = s * d.SL, nt = min(d.SL, T - t0);
+  __shared__ cx<R> sQ[QF], sQi[QF];
+  __shared__ R sg[N * M];
+  R xv[2 * M], lam[N];
+  const bool live = tid < nt;
+  if (live) {
+    load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + tid) * M));
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
+  }
+  for (int i = tid; i < QF; i += kT) {
+    sQ[i] = Q[(size_t)f * QF + i];
+    const cd qi = Qinv[(size_t)f * QF + i];
+    sQi[i] = {(R)qi.re, (R)qi.im};
+  }
+  for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
+  sched_fence();
+  __syncthreads();
+  if (!live) return;
+  const int t = t0 + tid;
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    R zr[ML], zi[ML], iy[ML];
+#pragma unroll
+    for (int mu = 0; mu < ML; ++mu) {
+      R ar = 0, ai = 0;
+#pragma unroll
+      for (int c = 0; c < ML; ++c) {
+        const cx<R> q = sQ[l * ML2 + mu * ML + c];
+        const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
+        ar += q.re * xr - q.im * xi;
+        ai += q.re * xi + q.im * xr;
+      }
+      zr[mu] = ar;
+      zi[mu] = ai;
+      R y = 0;
+#pragma unroll
+      for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + l * ML + mu];
+      iy[mu] = (R)1 / rmax(y, (R)d.eps);
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      R out[2 * ML];
+#pragma unroll
+      for (int a = 0; a < ML; ++a) {
+        R vr = 0, vi = 0;
+#pragma unroll
+        for (int mu = 0; mu < ML; ++mu) {
+          const R gain = lam[n] * sg[n * M + l * ML + mu] * iy[mu];
+          const cx<R> q = sQi[l * ML2 + a * ML + mu];
+          const R ur = gain * zr[mu], ui = gain * zi[mu];
+          vr += q.re * ur - q.im * ui;
+          vi += q.re * ui + q.im * ur;
+        }
+        out[2 * a] = vr;
+        out[2 * a + 1] = vi;
+      }
+      store16<R, 2 * ML>(reinterpret_cast<R*>(S + (((size_t)n * d.F + f) * T + t) * M + l * ML), out);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // LDS budgets (bytes) and launches of one compiled set.
 template <typename R, int N, int K, int ML, int L>
 struct Set {
@@ -1272,6 +1426,29 @@ struct Set {
     return align_up(sizeof(double) * N * M, 16) + sizeof(double) * (size_t)d.SLP * (G::MP + G::OP);
   }
   static size_t max_smem(const Dims& d) { return kGramD ? 0 : smem_gram(d); }
+
+  // Cost or Wiener filter at the end of a run: lambda for the current W, H, then Q^{-1} and
+  // ln|det Q|, then the per-frame kernel.
+  static hipError_t finish(const Dims& d, const Buffers& b, bool separate, void* S, hipStream_t s) {
+    if constexpr (ML <= 4) {
+      hipError_t e = launch(d, b, kFLam, s);
+      if (e != hipSuccess) return e;
+      const cx<R>* X = static_cast<const cx<R>*>(b.X);
+      const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
+      hipLaunchKernelGGL((k_qinv_f<R, ML>), dim3((d.F * L + 64 / ML - 1) / (64 / ML)), dim3(64), 0, s, d, Q,
+                         static_cast<cd*>(b.Qinv), b.logdet, b.status);
+      if (separate)
+        hipLaunchKernelGGL((k_sep_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), 0, s, d, X, Q,
+                           static_cast<const cd*>(b.Qinv), static_cast<const R*>(b.lam), static_cast<const R*>(b.g),
+                           static_cast<cx<R>*>(S));
+      else
+        hipLaunchKernelGGL((k_nll_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), 0, s, d, X, Q,
+                           static_cast<const R*>(b.lam), static_cast<const R*>(b.g), b.nllpart);
+      return hipGetLastError();
+    } else {
+      return hipErrorNotSupported;
+    }
+  }
 
   static hipError_t launch(const Dims& d, const Buffers& b, int kid, hipStream_t s) {
     const cx<R>* X = static_cast<const cx<R>*>(b.X);
@@ -1339,6 +1516,18 @@ struct Set {
 // Compiled sets (index, N, K, M_l, L); index = Dims::fast.
 #define DFM_FAST_SETS(X) \
   X(0, 2, 4, 2, 2) X(1, 5, 16, 4, 4) X(2, 5, 16, 16, 1) X(3, 3, 16, 4, 2) X(4, 8, 16, 4, 3)
+
+hipError_t fast_finish(const Dims& d, const Buffers& b, int dtype, bool separate, void* S, hipStream_t s) {
+  switch (d.fast) {
+#define DFM_FINISH(i, n, k, ml, l)                                                          \
+  case i:                                                                                   \
+    return dtype == DFM_C64 ? fast::Set<float, n, k, ml, l>::finish(d, b, separate, S, s)   \
+                            : fast::Set<double, n, k, ml, l>::finish(d, b, separate, S, s);
+    DFM_FAST_SETS(DFM_FINISH)
+#undef DFM_FINISH
+  }
+  return hipErrorInvalidValue;
+}
 
 int fast_set_index(int N, int K, int ML, int L) {
 #define DFM_MATCH(i, n, k, ml, l) \

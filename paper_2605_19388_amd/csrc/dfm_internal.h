@@ -86,6 +86,8 @@ int fast_set_index(int N, int K, int ML, int L);
 size_t fast_max_smem(const Dims& d, int dtype);
 hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
 const char* fast_kernel_name(const Dims& d, int dtype, int kid);  // symbol family a kernel id runs
+// Cost (13) partials or the Wiener filter with the specialised kernels (M_l <= 4).
+hipError_t fast_finish(const Dims& d, const Buffers& b, int dtype, bool separate, void* S, hipStream_t s);
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s);
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
 hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);

@@ -716,10 +716,12 @@ int iteration_kernels(const Dims& d, int* kids) {
 }
 
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s) {
+  if (d.fast >= 0 && d.ML <= 4) return fast_finish(d, b, dtype, false, nullptr, s);
   return dtype == DFM_C64 ? nll_impl<float>(d, b, s) : nll_impl<double>(d, b, s);
 }
 
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s) {
+  if (d.fast >= 0 && d.ML <= 4) return fast_finish(d, b, dtype, true, S, s);
   return dtype == DFM_C64 ? sep_impl<float>(d, b, S, s) : sep_impl<double>(d, b, S, s);
 }
 
