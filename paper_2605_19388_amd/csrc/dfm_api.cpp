@@ -157,8 +157,7 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   n += al(16 * d.F * d.QF);                            // Qinv
   n += al(64);                                         // status
   n += al(fast ? r * d.F * d.T * d.N : 0);             // lambda
-  n += al(fast ? r * d.T * d.N * d.K : 0);             // frame-major H
-  n += al(fast ? r * 2 * d.N * (size_t)d.F * d.TP : 0);  // coefficient planes
+  n += al(fast ? r * 2 * d.N * (size_t)d.F * d.TP : 0);  // coefficient planes [2N][TBN][F][16]
   return n;
 }
 
@@ -181,7 +180,6 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   b.Qinv = take(16 * d.F * d.QF);
   b.status = reinterpret_cast<int*>(take(64));
   b.lam = fast ? take(r * d.F * d.T * d.N) : nullptr;
-  b.Ht = fast ? take(r * d.T * d.N * d.K) : nullptr;
   b.AB = fast ? take(r * 2 * d.N * (size_t)d.F * d.TP) : nullptr;
 }
 
@@ -269,11 +267,9 @@ dfm_status dfm_init(dfm_plan** out, const dfm_problem* p, const void* X, void* Q
 dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream) {
   if (!plan || n_iter < 0) return DFM_E_ARG;
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  // The specialised kernels read a frame-major copy of H and lambda = W H, which the H
-  // update and the eq. (10) kernel then keep current; seed both from the caller's state.
-  if (n_iter > 0 && plan->d.fast >= 0 &&
-      (dfm::run_kernel(plan, dfm::kFHt, s) != hipSuccess || dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess))
-    return DFM_E_HIP;
+  // The specialised kernels read lambda = W H, which the W and H updates then keep
+  // current; seed it from the caller's state.
+  if (n_iter > 0 && plan->d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess) return DFM_E_HIP;
   for (int it = 0; it < n_iter; ++it)
     for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G; ++stage)
       if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
@@ -283,11 +279,9 @@ dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream) {
 dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream) {
   if (!plan || stage < DFM_STAGE_IP || stage > DFM_STAGE_G) return DFM_E_ARG;
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  // A sub-step may follow a change of the state by the caller: refresh the frame-major H
-  // and lambda = W H that the specialised kernels read.
-  if (plan->d.fast >= 0 &&
-      (dfm::run_kernel(plan, dfm::kFHt, s) != hipSuccess || dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess))
-    return DFM_E_HIP;
+  // A sub-step may follow a change of the state by the caller: refresh lambda = W H, which
+  // the specialised kernels read.
+  if (plan->d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess) return DFM_E_HIP;
   if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
   return DFM_OK;
 }

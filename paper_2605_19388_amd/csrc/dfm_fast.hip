@@ -7,27 +7,25 @@
 // are issued as one batch behind a scheduling barrier (left alone, the scheduler trades
 // them for occupancy and waits on each load in turn).
 //
-// One iteration is eight kernels: the five below, k_happly_f, and the generic W and g
-// apply kernels, which sum the per-tile partials in a fixed order (so every result is
-// deterministic run to run) and update W and g.  Finishing the reductions inside the
-// streaming kernels with a last-arriving workgroup was measured slower on gfx950: the
-// device-scope release/acquire it needs writes back and invalidates L2 in every
-// workgroup.
+// One iteration is seven kernels, each a plain launch on the caller's stream:
 //
-//   k_ht_f    frame-major copy of H (once per call; afterwards the H update keeps it).
-//   k_lam_f   lambda = W H at every frame (once per call; afterwards k_g_f refreshes it).
-//   k_gram_f  tile (f, time slice), 128 threads.  1/y per frame on the vector units,
-//             then the weighted covariances of eq. (14) as a real contraction over
-//             frames on the matrix cores (v_mfma 16x16x4: rows = mu, columns = packed
-//             Hermitian entries of x x^H, K = 4 frames).
-//   k_ip_f    one lane per (f, subarray): FP64 IP sweep of eqs. (15)-(16) (M_l <= 4;
-//             larger blocks use the cooperative generic kernel).
-//   k_pw_f    tile (f, time slice), 128 threads.  P = |Q x|^2 and the per-frame sums of
-//             eq. (8); the contraction with H over frames reads H staged in LDS.
-//   k_h_f     2 x 16 bins x 16 frames per 4-wave workgroup.  lambda = W H and the sum
-//             over frequencies of eq. (9) are both 16x16x4 matrix-core contractions.
-//   k_happly_f  H update of eq. (9) from the frequency-group partials (H and its copy).
-//   k_g_f     tile (f, time slice), 128 threads.  Sums of eq. (10).
+//   k_gramd_f  covariances V of eq. (14) for M_l <= 4 in FP32 (FP64 sums), a fixed grid
+//              sharing the flattened (f, t) frames; k_gram_f (matrix cores) otherwise.
+//   k_ip_f     FP64 IP sweep of eqs. (15)-(16), M_l lanes per (f, subarray) block (M_l <= 4;
+//              larger blocks use the cooperative generic kernel).
+//   k_pw_f     P = |Q x|^2 and the per-frame coefficient planes of eq. (8), one frame per thread.
+//   k_wgemm_f  sums over frames of eq. (8) on the matrix cores, the W update and lambda = W H.
+//   k_h_f      per-frame coefficient planes of eq. (9) with the new lambda.
+//   k_hgemm_f  sums over bins of eq. (9) on the matrix cores, the H update and lambda = W H.
+//   k_g_f      one workgroup per bin: the sums over frames of eq. (10) and the g update.
+//
+// Every reduction finishes in a fixed order inside one kernel (wave sums added in wave
+// order in LDS, partial-sum slots added in slot order), so results are identical run to
+// run; no floating-point atomics.  Finishing a reduction split over workgroups with a
+// last-arriving workgroup instead was measured slower on gfx950: the device-scope
+// release/acquire it needs writes back and invalidates L2 in every workgroup.  k_lam_f
+// forms lambda for the caller's W and H before a run; the cost (13) and the Wiener filter
+// have their own kernels at the end of the file.
 #include <hip/hip_runtime.h>
 
 #include "dfm_device.h"
@@ -605,25 +603,6 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
   }
 }
 
-// Frame-major copy of the activations: Ht[t][n*K + k] = H[n][k][t].
-template <typename R, int NK>
-__global__ __launch_bounds__(kT) void k_ht_f(Dims d, const R* __restrict__ H, R* __restrict__ Ht) {
-  const int t = blockIdx.x * kT + threadIdx.x;
-  if (t >= d.T) return;
-  R hv[NK];
-#pragma unroll
-  for (int i = 0; i < NK; ++i) hv[i] = H[(size_t)i * d.T + t];
-  sched_fence();
-  constexpr int E = V16<R>::E;
-#pragma unroll
-  for (int i = 0; i < NK / E; ++i) {
-    typename V16<R>::type v;
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = hv[i * E + e];
-    reinterpret_cast<typename V16<R>::type*>(Ht + (size_t)t * NK)[i] = v;
-  }
-}
-
 // lambda[f][n][t] = sum_k W[n][f][k] H[n][k][t] (eq. (2)) on the matrix cores: one 16 x 16
 // tile (rows f, columns t) per wave, contraction over the bases four at a time.
 // Hn: the activations of source n for the tile's 16 frames, [4 * ceil(K/4)][16] in LDS,
@@ -672,88 +651,154 @@ __global__ __launch_bounds__(64 * kLamWaves) void k_lam_f(Dims d, const R* __res
 }
 
 
+// Coefficient planes AB[p][tt][f][16]: value p (a_n for p = n, b_n for p = N + n) of bin f
+// and frame t = 16 tt + (t % 16).  The sums over frames and over bins read them as 16 x 16
+// tiles, each a contiguous 1 KB block.
+__device__ __forceinline__ size_t ab_index(const Dims& d, int p, int f, int t) {
+  return (((size_t)p * d.TBN + (t >> 4)) * d.F + f) * 16 + (t & 15);
+}
+
 // ------------------------------------------------------------------------------------
-// P = |Q x|^2 and the per-bin coefficients of eq. (8) for every (f, t) of a slice:
-// a_n = sum_m g_nm P_m / y_m^2 and b_n = sum_m g_nm / y_m, written as planes
-// AB[n][f][t] and AB[N + n][f][t] for the sums over frames in k_wgemm_f.
+// P = |Q x|^2 and the per-bin coefficients of eq. (8) for every (f, t) of two slices:
+// a_n = sum_m g_nm P_m / y_m^2 and b_n = sum_m g_nm / y_m, written to the coefficient
+// planes (values n and N + n) for the sums over frames in k_wgemm_f.  Each thread takes
+// one frame of each slice (grid (F, ceil(S / 2))); the loads of both frames are issued up
+// front, so the second frame's data arrives while the first is processed (a thread per
+// frame would run every wave's loads and then every wave's arithmetic in lockstep).
 template <typename R, int N, int K, int ML, int L>
 __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
                                              const R* __restrict__ lamin, const R* __restrict__ g,
                                              R* __restrict__ P, R* __restrict__ AB) {
   constexpr int M = ML * L, ML2 = ML * ML, QF = L * ML2;
+  constexpr int QPT = (QF + kT - 1) / kT, GPT = (N * M + kT - 1) / kT;
   static_assert((2 * M) % V16<R>::E == 0 && M % V16<R>::E == 0, "rows must fill 16-byte vectors");
-  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int f = blockIdx.x, tid = threadIdx.x;
   const int T = d.T;
-  const int t0 = s * d.SL;
-  const int nt = min(d.SL, T - t0);
   __shared__ cx<R> sQ[QF];
   __shared__ R sg[N * M];
 
-  // One batch of loads: x and lambda at this thread's frame.
-  R xv[2 * M], lam[N];
-  const bool live = tid < nt;
-  if (live) {
-    load16<R, 2 * M>(xv, reinterpret_cast<const R*>(X + ((size_t)f * T + t0 + tid) * M));
+  // Q and g of the bin first (the LDS writes wait for them only), then both frames.
+  cx<R> qv[QPT];
+  R gv[GPT];
 #pragma unroll
-    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
+  for (int j = 0; j < QPT; ++j) {
+    const int i = tid + j * kT;
+    if (i < QF) qv[j] = Q[(size_t)f * QF + i];
   }
-  for (int i = tid; i < QF; i += kT) sQ[i] = Q[(size_t)f * QF + i];
-  for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) {
+    const int i = tid + j * kT;
+    if (i < N * M) gv[j] = g[(size_t)f * N * M + i];
+  }
+  R xv[2][2 * M], lam[2][N];
+  int tf[2];
+  bool live[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int s = 2 * blockIdx.y + u, t0 = s * d.SL;
+    live[u] = s < d.S && tid < min(d.SL, T - t0);
+    tf[u] = live[u] ? t0 + tid : T - 1;  // dead lanes load a valid frame and store nothing
+    load16<R, 2 * M>(xv[u], reinterpret_cast<const R*>(X + ((size_t)f * T + tf[u]) * M));
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[u][n] = lamin[((size_t)f * N + n) * T + tf[u]];
+  }
   sched_fence();
-  __syncthreads();
-  if (!live) return;
-
-  R a[N], b[N], pv[M];
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
-    a[n] = 0;
-    b[n] = 0;
+  for (int j = 0; j < QPT; ++j) {
+    const int i = tid + j * kT;
+    if (i < QF) sQ[i] = qv[j];
   }
 #pragma unroll
-  for (int l = 0; l < L; ++l) {
+  for (int j = 0; j < GPT; ++j) {
+    const int i = tid + j * kT;
+    if (i < N * M) sg[i] = gv[j];
+  }
+  __syncthreads();
+
 #pragma unroll
-    for (int mu = 0; mu < ML; ++mu) {
-      R zr = 0, zi = 0;
+  for (int u = 0; u < 2; ++u) {
+    if (!live[u]) continue;
+    R a[N], b[N], pv[M];
 #pragma unroll
-      for (int c = 0; c < ML; ++c) {
-        const cx<R> q = sQ[l * ML2 + mu * ML + c];
-        const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
-        zr += q.re * xr - q.im * xi;
-        zi += q.re * xi + q.im * xr;
-      }
-      const int m = l * ML + mu;
-      const R p = zr * zr + zi * zi;
-      pv[m] = p;
-      R y = 0;
+    for (int n = 0; n < N; ++n) {
+      a[n] = 0;
+      b[n] = 0;
+    }
 #pragma unroll
-      for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
-      const R iy = rcp(rmax(y, (R)d.eps));
-      const R piy2 = p * iy * iy;
+    for (int l = 0; l < L; ++l) {
 #pragma unroll
-      for (int n = 0; n < N; ++n) {
-        a[n] += sg[n * M + m] * piy2;
-        b[n] += sg[n * M + m] * iy;
+      for (int mu = 0; mu < ML; ++mu) {
+        R zr = 0, zi = 0;
+#pragma unroll
+        for (int c = 0; c < ML; ++c) {
+          const cx<R> q = sQ[l * ML2 + mu * ML + c];
+          const R xr = xv[u][2 * (l * ML + c)], xi = xv[u][2 * (l * ML + c) + 1];
+          zr += q.re * xr - q.im * xi;
+          zi += q.re * xi + q.im * xr;
+        }
+        const int m = l * ML + mu;
+        const R p = zr * zr + zi * zi;
+        pv[m] = p;
+        R y = 0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) y += lam[u][n] * sg[n * M + m];
+        const R iy = rcp(rmax(y, (R)d.eps));
+        const R piy2 = p * iy * iy;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+          a[n] += sg[n * M + m] * piy2;
+          b[n] += sg[n * M + m] * iy;
+        }
       }
     }
-  }
-  const int t = t0 + tid;
-  store16<R, M>(P + ((size_t)f * T + t) * M, pv);
+    const int t = tf[u];
+    store16<R, M>(P + ((size_t)f * T + t) * M, pv);
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
-    AB[((size_t)n * d.F + f) * d.TP + t] = a[n];
-    AB[((size_t)(N + n) * d.F + f) * d.TP + t] = b[n];
+    for (int n = 0; n < N; ++n) {
+      AB[ab_index(d, n, f, t)] = a[n];
+      AB[ab_index(d, N + n, f, t)] = b[n];
+    }
   }
 }
 
 // ------------------------------------------------------------------------------------
 // Sums over frames or frequencies of the coefficient planes on the 16x16x4 matrix cores,
-// with the multiplicative update applied in the same kernel.  A workgroup has kGW waves;
-// the contraction range is dealt out to the waves in chunks of 16 (four 4-deep steps).
-// Every operand a wave needs, for the sums and for the lambda tiles that follow the
-// update, is loaded in one batch of up to kGB chunks and kGB tiles; the waves'
-// accumulators are then summed in LDS in wave order.
+// with the multiplicative update applied in the same kernel.  A workgroup has kGW waves and
+// owns one source and 16 bins (W update) or 16 frames (H update); the contraction range is
+// dealt out to the waves in chunks of 16 (four 4-deep steps).
+//
+// Plane layout AB[p][tt][f][16] (p = n for a_n, N + n for b_n): every 16 bins x 16 frames
+// tile is a contiguous 1 KB block, so a wave reads one tile with one 16-byte-per-lane load
+// (W update), and a 16-frame column of all bins is one contiguous run (H update).  The
+// operand that all chunks share (H[n] for the W update, W[n] for the H update) is staged in
+// LDS once per workgroup with contiguous loads (in windows when it does not fit) and read
+// from there both by the sums and by the lambda tiles after the update.  The waves'
+// accumulators are summed in LDS in wave order.
 constexpr int kGW = 8;  // waves per workgroup
-constexpr int kGB = 6;  // chunks (and lambda tiles) per wave and load batch
+constexpr int kGB = 6;  // chunks per wave and load batch
+
+// LDS of the two GEMM kernels: a fixed part (wave sums, the 16 updated rows) and a window of
+// the shared operand that fits in the rest of 64 KB.
+template <typename R, int K>
+struct GemmLds {
+  static constexpr int KT = (K + 15) / 16, KP = 4 * ((K + 3) / 4);
+  static constexpr size_t fixed = sizeof(R) * (kGW * 2 * KT * 256 + 16 * KP);
+  static constexpr size_t budget = 64 * 1024 - fixed - 256;
+  // W update: H window of TW frames, rows k < KP, row stride TW + 4.
+  static constexpr int TWMAX = ((int)(budget / (sizeof(R) * KP)) - 4) / 16 * 16;
+  static constexpr int HRW = (KP + kGW - 1) / kGW, HRC = (TWMAX + 63) / 64;  // per-lane staging
+  // H update: W window of FW bins, row stride WS.
+  static constexpr int WS = KP + 4;
+  static constexpr int FWMAX = (int)(budget / (sizeof(R) * WS)) / 16 * 16;
+  static constexpr int WNE = (FWMAX * KP + 64 * kGW - 1) / (64 * kGW);  // per-thread staging
+  __host__ __device__ static int tw(const Dims& d) { return d.TP < TWMAX ? d.TP : TWMAX; }
+  __host__ __device__ static int fw(const Dims& d) {
+    const int fp = (d.F + 15) & ~15;
+    return fp < FWMAX ? fp : FWMAX;
+  }
+  static size_t wgemm_smem(const Dims& d) { return sizeof(R) * KP * (size_t)(tw(d) + 4); }
+  static size_t hgemm_smem(const Dims& d) { return sizeof(R) * WS * (size_t)fw(d); }
+};
 
 // Wave sums -> LDS as red[wave][which][tile][row][col], rows/cols of the 16 x 16 tiles.
 template <typename R, int NT>
@@ -783,25 +828,51 @@ __device__ __forceinline__ void sum_tiles(const R* red, int kt, int row, int col
 // Bases update, eq. (8), for one source n and 16 bins: num/den[f][k] = sum_t (a, b)[f][t] H[k][t]
 // (rows f, columns k, contraction over frames), W <- W sqrt(num / max(den, eps)); then
 // lambda = W H for the new W at these bins and every frame (the H sums read it).
+// LDS window: sH[k][t - w0] = H[n][k][t] for w0 <= t < w0 + TW, row stride TW + 4 (16-byte
+// rows in distinct bank groups), zero beyond T and K.
 template <typename R, int N, int K>
-__global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restrict__ AB, const R* __restrict__ Ht,
+__global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restrict__ AB, const R* __restrict__ H,
                                                       R* __restrict__ W, R* __restrict__ lam,
                                                       int* __restrict__ status) {
-  constexpr int NK = N * K, KT = (K + 15) / 16, KS = (K + 3) / 4;
+  typedef GemmLds<R, K> G;
+  constexpr int KT = G::KT, KP = G::KP, KS = KP / 4;
   static_assert(KT <= 2, "bases per source");
   typedef typename Mma<R>::v4 v4;
   typedef R v4r __attribute__((ext_vector_type(4)));
   __shared__ R red[kGW * 2 * KT * 256];
-  __shared__ R sWn[16 * 4 * KS];  // new W of the 16 bins, [f][k], zero beyond K and F
+  __shared__ R sWn[16 * KP];  // new W of the 16 bins, [f][k], zero beyond K and F
+  extern __shared__ __align__(16) unsigned char dyn[];
+  R* sH = reinterpret_cast<R*>(dyn);
   const int n = blockIdx.x, f0 = blockIdx.y * 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane & 15, kk = lane >> 4;
-  const int T = d.T, F = d.F;
+  const int T = d.T, F = d.F, TP = d.TP;
+  const int TW = G::tw(d), TS = TW + 4;
   const int fr = min(f0 + i, F - 1);  // rows beyond F are computed on a valid row and dropped
-  const R* arow = AB + ((size_t)n * F + fr) * d.TP;
-  const R* brow = AB + ((size_t)(N + n) * F + fr) * d.TP;
-  const R* hcol = Ht + n * K;
-  const int nch = (T + 15) / 16;  // chunks of 16 frames = lambda tiles of 16 frames
+  const R* an = AB + ((size_t)n * d.TBN * F + fr) * 16 + 4 * kk;
+  const R* bn = AB + ((size_t)(N + n) * d.TBN * F + fr) * 16 + 4 * kk;
+  const R* hn = H + (size_t)n * K * T;
+  const size_t tstride = (size_t)F * 16;  // one 16-frame tile further
+
+  // Window [w0, w0 + nw) of H[n] -> sH: wave w stages rows w, w + kGW, ...; every load is
+  // issued before the first LDS write.
+  auto stage = [&](int w0, int nw) {
+    R v[G::HRW][G::HRC];
+#pragma unroll
+    for (int q = 0; q < G::HRW; ++q)
+#pragma unroll
+      for (int r = 0; r < G::HRC; ++r) {
+        const int k = wave + q * kGW, tl = lane + 64 * r, t = w0 + tl;
+        v[q][r] = (k < K && tl < nw && t < T) ? hn[(size_t)k * T + t] : (R)0;
+      }
+#pragma unroll
+    for (int q = 0; q < G::HRW; ++q)
+#pragma unroll
+      for (int r = 0; r < G::HRC; ++r) {
+        const int k = wave + q * kGW, tl = lane + 64 * r;
+        if (k < KP && tl < nw) sH[k * TS + tl] = v[q][r];
+      }
+  };
 
   v4 accN[KT], accD[KT];
 #pragma unroll
@@ -809,54 +880,50 @@ __global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restric
     accN[kt] = v4{0, 0, 0, 0};
     accD[kt] = v4{0, 0, 0, 0};
   }
-  R hb[kGB][KS];  // B operands of this wave's lambda tiles (first batch)
-  for (int c0 = wave; c0 < nch; c0 += kGW * kGB) {
+  for (int w0 = 0; w0 < TP; w0 += TW) {
+    const int nw = min(TW, TP - w0), cb = w0 / 16, ce = cb + nw / 16;
+    if (w0 > 0) __syncthreads();  // the previous window is consumed
     v4r av[kGB], bv[kGB];
-    R hv[kGB][KT][4];
+    auto load = [&](int c0) {
 #pragma unroll
-    for (int u = 0; u < kGB; ++u) {
-      const int cc = min(c0 + u * kGW, nch - 1);
-      const int tq = cc * 16 + 4 * kk;  // step s covers frame tq + s
-      av[u] = *reinterpret_cast<const v4r*>(arow + tq);
-      bv[u] = *reinterpret_cast<const v4r*>(brow + tq);
-#pragma unroll
-      for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-          const int k = kt * 16 + i, t = min(tq + st, T - 1);
-          hv[u][kt][st] = hcol[(size_t)t * NK + (k < K ? k : 0)];
-        }
-      if (c0 == wave) {
-        const int t = min(cc * 16 + i, T - 1);
-#pragma unroll
-        for (int st = 0; st < KS; ++st) {
-          const int k = 4 * st + kk;
-          hb[u][st] = hcol[(size_t)t * NK + (k < K ? k : 0)];
-        }
+      for (int u = 0; u < kGB; ++u) {
+        const int cc = min(c0 + u * kGW, ce - 1);
+        av[u] = *reinterpret_cast<const v4r*>(an + cc * tstride);
+        bv[u] = *reinterpret_cast<const v4r*>(bn + cc * tstride);
       }
-    }
-    sched_fence();
+    };
+    load(cb + wave);  // first batch in flight while the window is staged
+    stage(w0, nw);
+    __syncthreads();
+    for (int c0 = cb + wave; c0 < ce; c0 += kGW * kGB) {
+      if (c0 != cb + wave) {
+        load(c0);
+        sched_fence();
+      }
 #pragma unroll
-    for (int u = 0; u < kGB; ++u) {
-      const int c = c0 + u * kGW;
-      const int tq = c * 16 + 4 * kk;
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const bool ok = c < nch && tq + st < T;
-        const R a = ok ? av[u][st] : (R)0, b = ok ? bv[u][st] : (R)0;
+      for (int u = 0; u < kGB; ++u) {
+        const int c = c0 + u * kGW;
+        const int tl = (min(c, ce - 1) - cb) * 16 + 4 * kk;  // this lane's frames w0 + tl .. + 3
 #pragma unroll
         for (int kt = 0; kt < KT; ++kt) {
-          const R h = kt * 16 + i < K ? hv[u][kt][st] : (R)0;
-          accN[kt] = Mma<R>::run(a, h, accN[kt]);
-          accD[kt] = Mma<R>::run(b, h, accD[kt]);
+          const int k = kt * 16 + i;
+          const v4r h4 = *reinterpret_cast<const v4r*>(sH + (k < KP ? k : 0) * TS + tl);
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const bool ok = c < ce && w0 + tl + st < T;
+            const R a = ok ? av[u][st] : (R)0, b = ok ? bv[u][st] : (R)0;
+            const R h = k < K ? h4[st] : (R)0;
+            accN[kt] = Mma<R>::run(a, h, accN[kt]);
+            accD[kt] = Mma<R>::run(b, h, accD[kt]);
+          }
         }
       }
     }
   }
   spill_tiles<R, KT>(red, wave, lane, accN, accD);
   __syncthreads();
-  for (int e = tid; e < 16 * 4 * KS; e += 64 * kGW) {
-    const int fi = e / (4 * KS), k = e - fi * (4 * KS), f = f0 + fi;
+  for (int e = tid; e < 16 * KP; e += 64 * kGW) {
+    const int fi = e / KP, k = e - fi * KP, f = f0 + fi;
     R w = 0;
     if (k < K && f < F) {
       R num, den;
@@ -870,30 +937,22 @@ __global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restric
   }
   __syncthreads();
 
-  // lambda[f][n][t] for the 16 bins: rows f (A = new W from LDS), columns t (B = H), over k.
+  // lambda[f][n][t] for the 16 bins: rows f (A = new W from LDS), columns t (B = H from the
+  // window), over k.  With one window, H is still staged.
   R wa[KS];
 #pragma unroll
-  for (int st = 0; st < KS; ++st) wa[st] = sWn[i * 4 * KS + 4 * st + kk];
-  for (int c0 = wave; c0 < nch; c0 += kGW * kGB) {
-    if (c0 != wave) {  // batches after the first (more than kGW * kGB tiles)
-#pragma unroll
-      for (int u = 0; u < kGB; ++u) {
-        const int t = min(min(c0 + u * kGW, nch - 1) * 16 + i, T - 1);
-#pragma unroll
-        for (int st = 0; st < KS; ++st) {
-          const int k = 4 * st + kk;
-          hb[u][st] = hcol[(size_t)t * NK + (k < K ? k : 0)];
-        }
-      }
-      sched_fence();
+  for (int st = 0; st < KS; ++st) wa[st] = sWn[i * KP + 4 * st + kk];
+  for (int w0 = 0; w0 < TP; w0 += TW) {
+    const int nw = min(TW, TP - w0), cb = w0 / 16, ce = cb + nw / 16;
+    if (TW < TP) {
+      __syncthreads();
+      stage(w0, nw);
+      __syncthreads();
     }
-#pragma unroll
-    for (int u = 0; u < kGB; ++u) {
-      const int c = c0 + u * kGW;
-      if (c >= nch) break;
+    for (int c = cb + wave; c < ce; c += kGW) {
       v4 acc = {0, 0, 0, 0};
 #pragma unroll
-      for (int st = 0; st < KS; ++st) acc = Mma<R>::run(wa[st], 4 * st + kk < K ? hb[u][st] : (R)0, acc);
+      for (int st = 0; st < KS; ++st) acc = Mma<R>::run(wa[st], sH[(4 * st + kk) * TS + (c - cb) * 16 + i], acc);
       const int t = c * 16 + i;
       if (t < T)
 #pragma unroll
@@ -906,76 +965,115 @@ __global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restric
 }
 
 // Per-bin coefficients of eq. (9) with lambda for the new W: a'_n = sum_m g_nm P_m / y_m^2,
-// b'_n = sum_m g_nm / y_m, written as planes for the sums over frequencies in k_hgemm_f.
+// b'_n = sum_m g_nm / y_m, written to the coefficient planes for the sums over frequencies
+// in k_hgemm_f.  Two frames per thread, as in k_pw_f.
 template <typename R, int N, int K, int ML, int L>
 __global__ __launch_bounds__(kT) void k_h_f(Dims d, const R* __restrict__ lamin, const R* __restrict__ g,
                                             const R* __restrict__ P, R* __restrict__ AB) {
-  constexpr int M = ML * L;
+  constexpr int M = ML * L, GPT = (N * M + kT - 1) / kT;
   static_assert(M % V16<R>::E == 0, "rows must fill 16-byte vectors");
-  const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int f = blockIdx.x, tid = threadIdx.x;
   const int T = d.T;
-  const int t0 = s * d.SL;
-  const int nt = min(d.SL, T - t0);
   __shared__ R sg[N * M];
-  R pv[M], lam[N];
-  const bool live = tid < nt;
-  if (live) {
-    load16<R, M>(pv, P + ((size_t)f * T + t0 + tid) * M);
+  R gv[GPT];
 #pragma unroll
-    for (int n = 0; n < N; ++n) lam[n] = lamin[((size_t)f * N + n) * T + t0 + tid];
+  for (int j = 0; j < GPT; ++j) {
+    const int i = tid + j * kT;
+    if (i < N * M) gv[j] = g[(size_t)f * N * M + i];
   }
-  for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
+  R pv[2][M], lam[2][N];
+  int tf[2];
+  bool live[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int s = 2 * blockIdx.y + u, t0 = s * d.SL;
+    live[u] = s < d.S && tid < min(d.SL, T - t0);
+    tf[u] = live[u] ? t0 + tid : T - 1;
+    load16<R, M>(pv[u], P + ((size_t)f * T + tf[u]) * M);
+#pragma unroll
+    for (int n = 0; n < N; ++n) lam[u][n] = lamin[((size_t)f * N + n) * T + tf[u]];
+  }
   sched_fence();
-  __syncthreads();
-  if (!live) return;
-  R a[N], b[N];
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
-    a[n] = 0;
-    b[n] = 0;
+  for (int j = 0; j < GPT; ++j) {
+    const int i = tid + j * kT;
+    if (i < N * M) sg[i] = gv[j];
   }
+  __syncthreads();
 #pragma unroll
-  for (int m = 0; m < M; ++m) {
-    R y = 0;
-#pragma unroll
-    for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
-    const R iy = rcp(rmax(y, (R)d.eps));
-    const R piy2 = pv[m] * iy * iy;
+  for (int u = 0; u < 2; ++u) {
+    if (!live[u]) continue;
+    R a[N], b[N];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-      a[n] += sg[n * M + m] * piy2;
-      b[n] += sg[n * M + m] * iy;
+      a[n] = 0;
+      b[n] = 0;
     }
-  }
-  const int t = t0 + tid;
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
-    AB[((size_t)n * d.F + f) * d.TP + t] = a[n];
-    AB[((size_t)(N + n) * d.F + f) * d.TP + t] = b[n];
+    for (int m = 0; m < M; ++m) {
+      R y = 0;
+#pragma unroll
+      for (int n = 0; n < N; ++n) y += lam[u][n] * sg[n * M + m];
+      const R iy = rcp(rmax(y, (R)d.eps));
+      const R piy2 = pv[u][m] * iy * iy;
+#pragma unroll
+      for (int n = 0; n < N; ++n) {
+        a[n] += sg[n * M + m] * piy2;
+        b[n] += sg[n * M + m] * iy;
+      }
+    }
+    const int t = tf[u];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      AB[ab_index(d, n, f, t)] = a[n];
+      AB[ab_index(d, N + n, f, t)] = b[n];
+    }
   }
 }
 
 // Activation update, eq. (9), for one source n and 16 frames: num/den[k][t] = sum_f W[f][k]
-// (a', b')[f][t] (rows k, columns t, contraction over bins), H <- H sqrt(num / max(den, eps))
-// (H and its frame-major copy); then lambda = W H for the new H at these frames and every
-// bin (the g sums and the next iteration read it).
+// (a', b')[f][t] (rows k, columns t, contraction over bins), H <- H sqrt(num / max(den, eps));
+// then lambda = W H for the new H at these frames and every bin (the g sums and the next
+// iteration read it).  Step st of chunk c takes bins c * 16 + 4 st + kk, so each 4-byte
+// plane load of a wave is one contiguous 256-byte run.  LDS window: sW[f - f0][k] =
+// W[n][f][k] for f0 <= f < f0 + FW, row stride KP + 4, zero beyond F and K.
 template <typename R, int N, int K>
 __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restrict__ W, const R* __restrict__ AB,
-                                                      R* __restrict__ H, R* __restrict__ Ht, R* __restrict__ lam,
+                                                      R* __restrict__ H, R* __restrict__ lam,
                                                       int* __restrict__ status) {
-  constexpr int NK = N * K, KT = (K + 15) / 16, KS = (K + 3) / 4;
+  typedef GemmLds<R, K> G;
+  constexpr int KT = G::KT, KP = G::KP, KS = KP / 4, WS = G::WS;
   static_assert(KT <= 2, "bases per source");
   typedef typename Mma<R>::v4 v4;
   __shared__ R red[kGW * 2 * KT * 256];
-  __shared__ R sHn[4 * KS * 16];  // new H of the 16 frames, [k][t], zero beyond K and T
-  const int n = blockIdx.x, t0 = blockIdx.y * 16;
+  __shared__ R sHn[KP * 16];  // new H of the 16 frames, [k][t], zero beyond K and T
+  extern __shared__ __align__(16) unsigned char dyn[];
+  R* sW = reinterpret_cast<R*>(dyn);
+  const int n = blockIdx.x, tt = blockIdx.y, t0 = tt * 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane & 15, kk = lane >> 4;
   const int T = d.T, F = d.F;
-  const R* ap = AB + (size_t)n * F * d.TP + t0 + i;
-  const R* bp = AB + (size_t)(N + n) * F * d.TP + t0 + i;
-  const R* wp = W + (size_t)n * F * K;
-  const int nch = (F + 15) / 16;  // chunks of 16 bins = lambda tiles of 16 bins
+  const int FP = (F + 15) & ~15, FW = G::fw(d);
+  const R* ap = AB + ((size_t)n * d.TBN + tt) * F * 16 + i;
+  const R* bp = AB + ((size_t)(N + n) * d.TBN + tt) * F * 16 + i;
+  const R* wn = W + (size_t)n * F * K;
+  const bool tok = t0 + i < T;
+
+  // Window [f0, f0 + nf) of W[n] -> sW, flat over (bin, basis); every load is issued before
+  // the first LDS write.
+  auto stage = [&](int f0, int nf) {
+    R v[G::WNE];
+#pragma unroll
+    for (int q = 0; q < G::WNE; ++q) {
+      const int e = tid + q * 64 * kGW, fl = e / KP, k = e - fl * KP, f = f0 + fl;
+      v[q] = (fl < nf && f < F && k < K) ? wn[(size_t)f * K + k] : (R)0;
+    }
+#pragma unroll
+    for (int q = 0; q < G::WNE; ++q) {
+      const int e = tid + q * 64 * kGW, fl = e / KP, k = e - fl * KP;
+      if (fl < nf) sW[fl * WS + k] = v[q];
+    }
+  };
 
   v4 accN[KT], accD[KT];
 #pragma unroll
@@ -983,54 +1081,53 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
     accN[kt] = v4{0, 0, 0, 0};
     accD[kt] = v4{0, 0, 0, 0};
   }
-  R wl[kGB][KS];  // A operands of this wave's lambda tiles (first batch)
-  for (int c0 = wave; c0 < nch; c0 += kGW * kGB) {
-    R wa[kGB][KT][4], av[kGB][4], bv[kGB][4];
+  for (int f0 = 0; f0 < FP; f0 += FW) {
+    const int nf = min(FW, FP - f0), cb = f0 / 16, ce = cb + nf / 16;
+    if (f0 > 0) __syncthreads();  // the previous window is consumed
+    R av[kGB][4], bv[kGB][4];
+    auto load = [&](int c0) {
 #pragma unroll
-    for (int u = 0; u < kGB; ++u) {
-      const int cc = min(c0 + u * kGW, nch - 1);
-      const int fq = cc * 16 + 4 * kk;  // step s covers bin fq + s
+      for (int u = 0; u < kGB; ++u) {
+        const int cc = min(c0 + u * kGW, ce - 1);
 #pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int f = min(fq + st, F - 1);
-        av[u][st] = ap[(size_t)f * d.TP];
-        bv[u][st] = bp[(size_t)f * d.TP];
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt) {
-          const int k = kt * 16 + i;
-          wa[u][kt][st] = wp[(size_t)f * K + (k < K ? k : 0)];
+        for (int st = 0; st < 4; ++st) {
+          const int f = min(cc * 16 + 4 * st + kk, F - 1);
+          av[u][st] = ap[(size_t)f * 16];
+          bv[u][st] = bp[(size_t)f * 16];
         }
       }
-      if (c0 == wave) {
-        const int f = min(cc * 16 + i, F - 1);
-#pragma unroll
-        for (int st = 0; st < KS; ++st) {
-          const int k = 4 * st + kk;
-          wl[u][st] = wp[(size_t)f * K + (k < K ? k : 0)];
-        }
+    };
+    load(cb + wave);  // first batch in flight while the window is staged
+    stage(f0, nf);
+    __syncthreads();
+    for (int c0 = cb + wave; c0 < ce; c0 += kGW * kGB) {
+      if (c0 != cb + wave) {
+        load(c0);
+        sched_fence();
       }
-    }
-    sched_fence();
 #pragma unroll
-    for (int u = 0; u < kGB; ++u) {
-      const int c = c0 + u * kGW;
-      const int fq = c * 16 + 4 * kk;
+      for (int u = 0; u < kGB; ++u) {
+        const int c = c0 + u * kGW;
+        const int fl = (min(c, ce - 1) - cb) * 16;
 #pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const bool ok = c < nch && fq + st < F;
-        const R a = ok ? av[u][st] : (R)0, b = ok ? bv[u][st] : (R)0;
+        for (int st = 0; st < 4; ++st) {
+          const int f = c * 16 + 4 * st + kk;
+          const bool ok = c < ce && f < F && tok;
+          const R a = ok ? av[u][st] : (R)0, b = ok ? bv[u][st] : (R)0;
 #pragma unroll
-        for (int kt = 0; kt < KT; ++kt) {
-          const R w = kt * 16 + i < K ? wa[u][kt][st] : (R)0;
-          accN[kt] = Mma<R>::run(w, a, accN[kt]);
-          accD[kt] = Mma<R>::run(w, b, accD[kt]);
+          for (int kt = 0; kt < KT; ++kt) {
+            const int k = kt * 16 + i;
+            const R w = k < K ? sW[(fl + 4 * st + kk) * WS + (k < K ? k : 0)] : (R)0;
+            accN[kt] = Mma<R>::run(w, a, accN[kt]);
+            accD[kt] = Mma<R>::run(w, b, accD[kt]);
+          }
         }
       }
     }
   }
   spill_tiles<R, KT>(red, wave, lane, accN, accD);
   __syncthreads();
-  for (int e = tid; e < 4 * KS * 16; e += 64 * kGW) {
+  for (int e = tid; e < KP * 16; e += 64 * kGW) {
     const int k = e >> 4, tl = e & 15, t = t0 + tl;
     R h = 0;
     if (k < K && t < T) {
@@ -1040,36 +1137,27 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
       h = H[idx] * sqrt(num / rmax(den, (R)d.eps));
       if (!isfinite(h)) atomicOr(status, kStNonFinite);
       H[idx] = h;
-      Ht[(size_t)t * NK + n * K + k] = h;
     }
     sHn[e] = h;
   }
   __syncthreads();
 
-  // lambda[f][n][t] for the 16 frames: rows f (A = W), columns t (B = new H from LDS), over k.
+  // lambda[f][n][t] for the 16 frames: rows f (A = W from the window), columns t (B = new H
+  // from LDS), over k.  With one window, W is still staged.
   R hb[KS];
 #pragma unroll
   for (int st = 0; st < KS; ++st) hb[st] = sHn[(4 * st + kk) * 16 + i];
-  for (int c0 = wave; c0 < nch; c0 += kGW * kGB) {
-    if (c0 != wave) {  // batches after the first (more than kGW * kGB tiles)
-#pragma unroll
-      for (int u = 0; u < kGB; ++u) {
-        const int f = min(min(c0 + u * kGW, nch - 1) * 16 + i, F - 1);
-#pragma unroll
-        for (int st = 0; st < KS; ++st) {
-          const int k = 4 * st + kk;
-          wl[u][st] = wp[(size_t)f * K + (k < K ? k : 0)];
-        }
-      }
-      sched_fence();
+  for (int f0 = 0; f0 < FP; f0 += FW) {
+    const int nf = min(FW, FP - f0), cb = f0 / 16, ce = cb + nf / 16;
+    if (FW < FP) {
+      __syncthreads();
+      stage(f0, nf);
+      __syncthreads();
     }
-#pragma unroll
-    for (int u = 0; u < kGB; ++u) {
-      const int c = c0 + u * kGW;
-      if (c >= nch) break;
+    for (int c = cb + wave; c < ce; c += kGW) {
       v4 acc = {0, 0, 0, 0};
 #pragma unroll
-      for (int st = 0; st < KS; ++st) acc = Mma<R>::run(4 * st + kk < K ? wl[u][st] : (R)0, hb[st], acc);
+      for (int st = 0; st < KS; ++st) acc = Mma<R>::run(sW[((c - cb) * 16 + i) * WS + 4 * st + kk], hb[st], acc);
       const int t = t0 + i;
       if (t < T)
 #pragma unroll
@@ -1458,10 +1546,6 @@ struct Set {
     R* H = static_cast<R*>(b.H);
     R* P = static_cast<R*>(b.P);
     switch (kid) {
-      case kFHt:
-        hipLaunchKernelGGL((k_ht_f<R, N * K>), dim3((d.T + kT - 1) / kT), dim3(kT), 0, s, d, H,
-                           static_cast<R*>(b.Ht));
-        break;
       case kFLam:
         hipLaunchKernelGGL((k_lam_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kLamWaves), 0, s, d, W, H,
                            static_cast<R*>(b.lam));
@@ -1484,21 +1568,22 @@ struct Set {
         }
         break;
       case kFPw:
-        hipLaunchKernelGGL((k_pw_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), 0, s, d, X, Q,
+        hipLaunchKernelGGL((k_pw_f<R, N, K, ML, L>), dim3(d.F, (d.S + 1) / 2), dim3(kT), 0, s, d, X, Q,
                            static_cast<const R*>(b.lam), g, P, static_cast<R*>(b.AB));
         break;
       case kFWGemm:
-        hipLaunchKernelGGL((k_wgemm_f<R, N, K>), dim3(N, (d.F + 15) / 16), dim3(64 * kGW), 0, s, d,
-                           static_cast<const R*>(b.AB), static_cast<const R*>(b.Ht), W, static_cast<R*>(b.lam),
-                           b.status);
+        hipLaunchKernelGGL((k_wgemm_f<R, N, K>), dim3(N, (d.F + 15) / 16), dim3(64 * kGW),
+                           (GemmLds<R, K>::wgemm_smem(d)), s, d, static_cast<const R*>(b.AB), H, W,
+                           static_cast<R*>(b.lam), b.status);
         break;
       case kFH:
-        hipLaunchKernelGGL((k_h_f<R, N, K, ML, L>), dim3(d.F, d.S), dim3(kT), 0, s, d,
+        hipLaunchKernelGGL((k_h_f<R, N, K, ML, L>), dim3(d.F, (d.S + 1) / 2), dim3(kT), 0, s, d,
                            static_cast<const R*>(b.lam), g, P, static_cast<R*>(b.AB));
         break;
       case kFHGemm:
-        hipLaunchKernelGGL((k_hgemm_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kGW), 0, s, d, W,
-                           static_cast<const R*>(b.AB), H, static_cast<R*>(b.Ht), static_cast<R*>(b.lam), b.status);
+        hipLaunchKernelGGL((k_hgemm_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kGW),
+                           (GemmLds<R, K>::hgemm_smem(d)), s, d, W, static_cast<const R*>(b.AB), H,
+                           static_cast<R*>(b.lam), b.status);
         break;
       case kFG:
         hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F), dim3(kGT), (GShape<R, N, K, ML, L>::smem()), s, d,

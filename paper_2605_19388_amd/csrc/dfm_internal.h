@@ -60,18 +60,17 @@ struct Buffers {
   void* Qinv;       // [F][QF] complex double
   int* status;      // sticky status word
   void* lam;           // [F][N][T] real: lambda = W H of the specialised kernels
-  void* Ht;            // [T][N*K] real: frame-major copy of H of the specialised kernels
-  void* AB;            // [2N][F][TP] real: per-bin MM coefficients of the specialised kernels
+  void* AB;            // [2N][TBN][F][16] real: per-bin MM coefficients of the specialised kernels
 };
 
 size_t workspace_bytes(const Dims& d, int dtype);
 void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 
-// Kernels.  Generic path: eight per iteration; specialised path: seven (kFLam and kFHt
-// seed lambda and the frame-major copy of H).
+// Kernels.  Generic path: eight per iteration; specialised path: seven (kFLam seeds
+// lambda = W H).
 enum KernelId {
   kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply,
-  kFGram, kFIp, kFPw, kFWGemm, kFH, kFHGemm, kFG, kFLam, kFHt, kNumKernels
+  kFGram, kFIp, kFPw, kFWGemm, kFH, kFHGemm, kFG, kFLam, kNumKernels
 };
 
 // Launchers (return hipSuccess or the first launch error).

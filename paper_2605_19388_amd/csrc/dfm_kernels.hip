@@ -657,8 +657,7 @@ static hipError_t cov_impl(const Dims& d, const Buffers& b, void* V, hipStream_t
   // The plan's own covariance kernel (both write the same packed slice-sum layout).
   if (d.fast >= 0) {
     const int dt = sizeof(R) == 4 ? DFM_C64 : DFM_C128;
-    hipError_t e = fast_launch(d, b, dt, kFHt, s);
-    if (e == hipSuccess) e = fast_launch(d, b, dt, kFLam, s);
+    hipError_t e = fast_launch(d, b, dt, kFLam, s);
     if (e == hipSuccess) e = fast_launch(d, b, dt, kFGram, s);
     if (e != hipSuccess) return e;
   } else {
@@ -685,7 +684,7 @@ const char* kernel_name(int kid) {
   static const char* names[kNumKernels] = {"k_gram",   "k_ip",    "k_pw",    "k_wapply",  "k_h",
                                            "k_happly", "k_g",     "k_gapply", "k_gram_f", "k_ip_f",
                                            "k_pw_f",   "k_wgemm_f", "k_h_f",  "k_hgemm_f", "k_g_f",
-                                           "k_lam_f",  "k_ht_f"};
+                                           "k_lam_f"};
   return kid >= 0 && kid < kNumKernels ? names[kid] : nullptr;
 }
 
