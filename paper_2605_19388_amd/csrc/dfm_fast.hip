@@ -674,8 +674,10 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
   static_assert((2 * M) % V16<R>::E == 0 && M % V16<R>::E == 0, "rows must fill 16-byte vectors");
   const int f = blockIdx.x, tid = threadIdx.x;
   const int T = d.T;
+  constexpr int E = V16<R>::E, PS = M + E;  // sP row stride: 16-byte rows in distinct bank groups
   __shared__ cx<R> sQ[QF];
   __shared__ R sg[N * M];
+  __shared__ __align__(16) R sP[kT * PS];  // P of the workgroup's frames, staged for contiguous stores
 
   // Q and g of the bin first (the LDS writes wait for them only), then both frames.
   cx<R> qv[QPT];
@@ -715,9 +717,12 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
   }
   __syncthreads();
 
+  typedef typename V16<R>::type vt;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    if (!live[u]) continue;
+    const int s = 2 * blockIdx.y + u, t0 = s * d.SL, nt = s < d.S ? min(d.SL, T - t0) : 0;
+    if (nt <= 0) break;
+    if (live[u]) {  // (a branch per frame also keeps the two frames' arithmetic apart)
     R a[N], b[N], pv[M];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
@@ -752,12 +757,31 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
       }
     }
     const int t = tf[u];
-    store16<R, M>(P + ((size_t)f * T + t) * M, pv);
+    {
 #pragma unroll
-    for (int n = 0; n < N; ++n) {
-      AB[ab_index(d, n, f, t)] = a[n];
-      AB[ab_index(d, N + n, f, t)] = b[n];
+      for (int n = 0; n < N; ++n) {
+        AB[ab_index(d, n, f, t)] = a[n];
+        AB[ab_index(d, N + n, f, t)] = b[n];
+      }
+#pragma unroll
+      for (int i = 0; i < M / E; ++i) {
+        vt v;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = pv[i * E + e];
+        *reinterpret_cast<vt*>(sP + tid * PS + i * E) = v;
+      }
     }
+    }
+    // P rows of the slice's frames are contiguous in memory: store them through LDS so that
+    // each wave writes whole 1 KB runs (per-frame 16-byte stores would reach L2 as separate
+    // partial-line writes).
+    __syncthreads();
+    R* pout = P + ((size_t)f * T + t0) * M;
+    for (int c = tid; c < nt * (M / E); c += kT) {
+      const int fr = c / (M / E), part = c - fr * (M / E);
+      *reinterpret_cast<vt*>(pout + (size_t)c * E) = *reinterpret_cast<const vt*>(sP + fr * PS + part * E);
+    }
+    __syncthreads();
   }
 }
 
