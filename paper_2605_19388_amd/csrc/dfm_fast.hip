@@ -561,23 +561,24 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
           for (int n = 0; n < N; ++n) y += lam[u][n] * gl[n][mu];
           w[mu] = (double)rcp(rmax(y, (float)d.eps));
         }
-        double xd[2 * ML], pr[ML2];
+        double xd[2 * ML];
 #pragma unroll
         for (int i = 0; i < 2 * ML; ++i) xd[i] = (double)xv[u][i];
+        // Each packed entry goes into the M_l accumulators as soon as it is formed.
+        auto add = [&](int e, double v) {
+#pragma unroll
+          for (int mu = 0; mu < MH; ++mu) acc[mu * ML2 + e] += w[mu] * v;
+        };
 #pragma unroll
         for (int a = 0; a < ML; ++a) {
-          pr[a] = xd[2 * a] * xd[2 * a] + xd[2 * a + 1] * xd[2 * a + 1];
+          add(a, xd[2 * a] * xd[2 * a] + xd[2 * a + 1] * xd[2 * a + 1]);
 #pragma unroll
           for (int b = a + 1; b < ML; ++b) {
             const int e = ML + 2 * (a * ML - a * (a + 1) / 2 + (b - a - 1));
-            pr[e] = xd[2 * a] * xd[2 * b] + xd[2 * a + 1] * xd[2 * b + 1];
-            pr[e + 1] = xd[2 * a + 1] * xd[2 * b] - xd[2 * a] * xd[2 * b + 1];
+            add(e, xd[2 * a] * xd[2 * b] + xd[2 * a + 1] * xd[2 * b + 1]);
+            add(e + 1, xd[2 * a + 1] * xd[2 * b] - xd[2 * a] * xd[2 * b + 1]);
           }
         }
-#pragma unroll
-        for (int mu = 0; mu < MH; ++mu)
-#pragma unroll
-          for (int e = 0; e < ML2; ++e) acc[mu * ML2 + e] += w[mu] * pr[e];
       }
       sched_fence();
 #pragma unroll
@@ -1400,7 +1401,8 @@ __global__ __launch_bounds__(64) void k_qinv_f(Dims d, const cx<R>* __restrict__
 }
 
 // Data part of the cost (13) per (f, slice): sum over frames and mics of |Q x|^2 / y + ln y,
-// one frame per thread, FP64 sums.
+// one frame per thread; each term in the working precision (its rounding error, relative
+// 1e-7 in FP32, averages out over the F T M terms), the sums in FP64.
 template <typename R, int N, int K, int ML, int L>
 __global__ __launch_bounds__(kT) void k_nll_f(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
                                               const R* __restrict__ lamin, const R* __restrict__ g,
@@ -1440,7 +1442,7 @@ __global__ __launch_bounds__(kT) void k_nll_f(Dims d, const cx<R>* __restrict__ 
 #pragma unroll
         for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + l * ML + mu];
         y = rmax(y, (R)d.eps);
-        acc += (double)((zr * zr + zi * zi) / y) + log((double)y);
+        acc += (double)((zr * zr + zi * zi) / y) + (double)log(y);
       }
   }
   // Workgroup sum in a fixed order: wave sums by shuffles, then the waves in order.
