@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
+    ap.add_argument("--mixtures", type=int, default=1,
+                    help="B > 1: per-kernel durations with the Infinity Cache cold, from B copies of the "
+                         "mixture stepped round-robin one iteration at a time (prints its own JSON line)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of a "
                          "--copy-mb run into the traffic file and exit (no GPU needed)")
@@ -152,8 +155,87 @@ def _cpu_model():
     return "unknown"
 
 
+def cold_mixtures(args):
+    """Kernel durations with the 256 MB Infinity Cache cold.
+
+    One mixture's working set (X 41 MB, P 20.5 MB, planes, lambda: about 80 MB at paper_4x4)
+    stays cache-resident from kernel to kernel, so the default run measures cache-assisted
+    bandwidth.  Here B plans, each with its own device copy of the mixture, are stepped
+    round-robin one iteration at a time: between two uses of one plan's data the other B - 1
+    plans move (B - 1) x ~150 MB, so with B = 8 every launch reads and writes HBM.  Each kernel
+    is timed with events around its own launches on every plan.  step(1) also refreshes
+    lambda once per call (one extra kernel per iteration, included in `iterations_per_s`).
+    """
+    import numpy as np
+    import torch
+
+    from paper_2605_19388_amd import DistributedFastMNMF, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    B, rounds = args.mixtures, max(args.steps, 2) * 4
+    w = synth.make(args.workload)
+    F, T, M, N, K, mics = w["F"], w["T"], w["M"], w["N"], w["K"], w["mics"]
+    X32 = w["X"].astype(np.complex64)
+    dev = torch.device("cuda:0")
+    plans = [DistributedFastMNMF(X32, mics, N, K, W=w["W"].astype(np.float32), H=w["H"].astype(np.float32),
+                                 Q=w["Q"].astype(np.complex64), g=w["g"].astype(np.float32), device=dev)
+             for _ in range(B)]
+    names = plans[0].kernel_names()
+    plans[0].step(2)
+    warm = plans[0].kernel_times(reps=args.kernel_reps)
+    log(f"[bench] {B} copies of {w['name']}; warm per-kernel us: " +
+        ", ".join(f"{k}={v * 1e3:.1f}" for k, v in warm.items()))
+
+    def rounds_of(n):
+        for _ in range(n):
+            for p in plans:
+                p.step(1)
+
+    rounds_of(2)
+    torch.cuda.synchronize()
+    cold = {}
+    for k in names:
+        for p in plans:
+            p.profile_kernel(k, max_launches=rounds + 4)
+        rounds_of(rounds)
+        torch.cuda.synchronize()
+        tot, n = 0.0, 0
+        for p in plans:
+            ms, cnt = p.profile_read()
+            p.profile_kernel(None)
+            tot += ms * cnt
+            n += cnt
+        cold[k] = tot / max(n, 1)
+        log(f"[bench] {k}: cold {cold[k] * 1e3:.2f} us (warm {warm[k] * 1e3:.2f}) over {n} launches")
+    t0 = time.perf_counter()
+    rounds_of(rounds)
+    torch.cuda.synchronize()
+    ips = rounds * B / (time.perf_counter() - t0)
+    for p in plans:
+        p.sync_status()
+    bins = F * T * M
+    roof = {}
+    for k, ms in cold.items():
+        base = k[:-2] if k.endswith("_f") else k
+        if base in BYTES_PER_BIN:
+            gbs = BYTES_PER_BIN[base] * bins / (ms * 1e-3) / 1e9
+            roof[k] = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"mode": "cold_mixtures", "workload": w["name"], "mixtures": B, "rounds": rounds,
+           "iterations_per_s": round(ips, 1),
+           "per_kernel_us_cold": {k: round(v * 1e3, 2) for k, v in cold.items()},
+           "per_kernel_us_warm": {k: round(v * 1e3, 2) for k, v in warm.items()},
+           "iteration_us_cold": round(sum(cold.values()) * 1e3, 2),
+           "iteration_us_warm": round(sum(warm.values()) * 1e3, 2),
+           "roofline_cold": roof}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.mixtures > 1:
+        cold_mixtures(args)
+        return
     if args.pmc_summary:
         copy_mb = args.copy_mb or 256
         t = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], copy_mb)

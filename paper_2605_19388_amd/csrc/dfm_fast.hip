@@ -457,16 +457,16 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<RI>* __restrict_
 
 // ------------------------------------------------------------------------------------
 // Weighted covariances (eq. (14)) for subarrays of M_l <= 4 mics, FP32 inputs, FP64 sums.
-// A fixed number of workgroups (two per CU) share the flattened (f, t) frames equally, so
-// every SIMD gets the same work; kGDH x kGDL lanes per subarray: lane j of row half h takes
-// frames t = j, j + kGDL, ... of each bin segment and sums the rows mu of that half; per frame it forms 1/y for the subarray's mics (FP32), the
-// packed entries of x^(l) x^(l)H in FP64 (exact: products of FP32 values) and adds
-// (1/y_mu) x x^H into M_l x M_l^2 FP64 registers; the lanes' sums are then added through LDS
-// in a fixed order, one slot per (bin, workgroup).  FP32 sums over frames would leave rounding errors outside the dominant
-// directions of V, which the solve of eq. (15) amplifies by cond(V) -- large at the
-// lowest bins, where the mixing is nearly rank-deficient; FP64 sums keep the solve's
-// input at the precision of the FP64 reference.  Output: V[f][slice][packed entries], FP64,
-// /T not applied.
+// A fixed number of workgroups (four per CU) share the flattened (f, t) frames equally, so
+// every SIMD gets the same work; kGDL lanes per subarray: lane j takes frames j, j + kGDL,
+// ... of each bin segment of the workgroup's share.  Per frame it forms 1/y for the
+// subarray's mics (FP32), the packed entries of x^(l) x^(l)H in FP64 (exact: products of
+// FP32 values) and adds (1/y_mu) x x^H into M_l x M_l^2 FP64 registers; the lanes' sums are
+// then added through LDS in a fixed order, one slot per (bin, workgroup).  FP32 sums over
+// frames would leave rounding errors outside the dominant directions of V, which the solve
+// of eq. (15) amplifies by cond(V) -- large at the lowest bins, where the mixing is nearly
+// rank-deficient; FP64 sums keep the solve's input at the precision of the FP64 reference.
+// Output: V[f][slot][packed entries], FP64, /T not applied.
 constexpr int kGDL = 32;  // lanes per subarray
 
 constexpr int kGDH = 1;   // lanes per frame (each sums ML / kGDH of the rows mu)
@@ -476,32 +476,6 @@ constexpr int gramd_threads() {
   return (kGDH * L * kGDL + 63) / 64 * 64;
 }
 
-// Sum of v[0..CUR) over the kGDL lanes of a subarray group by recursive halving: at each
-// step (lane mask MASK) a lane keeps one half of its values, sends the other half to its
-// partner and adds what it receives; once one value is left the remaining masks add it
-// outright.  The lane ends with the totals of outputs [off, off + CUR / 2^steps).  The
-// order of the additions is fixed, so the result is reproducible.
-template <int CUR, int MASK>
-__device__ __forceinline__ void lane_reduce(double* v, int j, int& off) {
-  if constexpr (MASK > 0) {
-    if constexpr (CUR >= 2) {
-      constexpr int h = CUR / 2;
-      const bool up = (j & MASK) != 0;
-#pragma unroll
-      for (int i = 0; i < h; ++i) {
-        const double lo = v[i], hi = v[i + h];
-        const double got = __shfl_xor(up ? lo : hi, MASK, kGDL);
-        v[i] = (up ? hi : lo) + got;
-      }
-      off += up ? h : 0;
-      lane_reduce<h, MASK / 2>(v, j, off);
-    } else {
-      v[0] += __shfl_xor(v[0], MASK, kGDL);
-      lane_reduce<CUR, MASK / 2>(v, j, off);
-    }
-  }
-}
-
 template <int N, int K, int ML, int L>
 __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx<float>* __restrict__ X,
                                                                const float* __restrict__ lamin,
@@ -509,7 +483,10 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
                                                                double* __restrict__ V) {
   constexpr int M = ML * L, ML2 = ML * ML, MH = ML / kGDH, NO = MH * ML2;  // outputs per lane
   constexpr int FB = 2;  // frames per load batch; the next batch is in flight during the current one
+  constexpr int RH = NO < kGDL ? NO : kGDL, RS = RH + 2;  // outputs per reduction pass, LDS row stride
   static_assert(ML == 2 || ML == 4, "M_l of 2 or 4");
+  static_assert(kGDH == 1 && NO % RH == 0 && RH % 2 == 0 && (RS / 2) % 2 == 1, "reduction passes");
+  __shared__ __align__(16) double red[gramd_threads<L>() * RS];
   const int tid = threadIdx.x;
   const int h = tid / (L * kGDL), l = min(tid / kGDL % L, L - 1), j = tid % kGDL;  // row half, subarray, lane
   const bool live = tid < kGDH * L * kGDL;
@@ -590,16 +567,21 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
       }
     }
 
-    // Totals over the subarray's lanes; lane j then holds outputs [off, off + NO / kGDL) (at
-    // least one; for NO < kGDL several lanes hold the same total and the first one writes).
-    int off = 0;
-    lane_reduce<NO, kGDL / 2>(acc, j, off);
-    constexpr int PER = NO >= kGDL ? NO / kGDL : 1;
-    constexpr int REP = NO >= kGDL ? 1 : kGDL / NO;  // lanes holding the same totals
-    if (live && j % REP == 0) {
-      double* out = V + ((size_t)f * d.SG + slot) * d.VF + (size_t)l * ML * ML2 + (size_t)h * NO + off;
+    // Totals over the subarray's lanes, RH outputs per pass: every lane writes its partial
+    // sums as one padded LDS row, then lane j of the subarray adds column j over the
+    // subarray's rows in lane order (a fixed order, so the sums are reproducible).
 #pragma unroll
-      for (int i = 0; i < PER; ++i) out[i] = acc[i];
+    for (int ps = 0; ps < NO / RH; ++ps) {
+      __syncthreads();  // the previous pass's rows are consumed
+#pragma unroll
+      for (int i = 0; i < RH; i += 2)
+        *reinterpret_cast<double2*>(red + tid * RS + i) = double2{acc[ps * RH + i], acc[ps * RH + i + 1]};
+      __syncthreads();
+      if (live && j < RH) {
+        double sum = 0.0;
+        for (int q = 0; q < kGDL; ++q) sum += red[(l * kGDL + q) * RS + j];
+        V[((size_t)f * d.SG + slot) * d.VF + (size_t)l * NO + ps * RH + j] = sum;
+      }
     }
   }
 }
