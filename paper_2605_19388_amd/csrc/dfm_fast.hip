@@ -133,7 +133,8 @@ __device__ __forceinline__ void hpd_solve(const cd (&A)[n][n], const cd (&dinv)[
 template <int n>
 __device__ __forceinline__ bool inverse_column(cd (&A)[n][n + 1], int col, cd (&x)[n], double& logabs) {
   bool ok = true;
-  logabs = 0.0;
+  double pivprod = 1.0;  // product of the |pivot|^2 (one log at the end)
+  cd pinv[n];            // pivot inverses, reused by the back substitution
 #pragma unroll
   for (int r = 0; r < n; ++r) A[r][n] = {r == col ? 1.0 : 0.0, 0.0};
 #pragma unroll
@@ -159,21 +160,22 @@ __device__ __forceinline__ bool inverse_column(cd (&A)[n][n + 1], int col, cd (&
       }
     }
     if (best == 0.0) ok = false;
-    logabs += best == 0.0 ? 0.0 : 0.5 * log(best);
-    const cd inv = best == 0.0 ? cd{0.0, 0.0} : cinv(A[p][p]);
+    pivprod *= best == 0.0 ? 1.0 : best;
+    pinv[p] = best == 0.0 ? cd{0.0, 0.0} : cinv(A[p][p]);
 #pragma unroll
     for (int r = p + 1; r < n; ++r) {
-      const cd fac = cmul(A[r][p], inv);
+      const cd fac = cmul(A[r][p], pinv[p]);
 #pragma unroll
       for (int c = p + 1; c <= n; ++c) A[r][c] = csub(A[r][c], cmul(fac, A[p][c]));
     }
   }
+  logabs = 0.5 * log(pivprod);
 #pragma unroll
   for (int r = n - 1; r >= 0; --r) {
     cd acc = A[r][n];
 #pragma unroll
     for (int c = r + 1; c < n; ++c) acc = csub(acc, cmul(A[r][c], x[c]));
-    x[r] = cabs2(A[r][r]) == 0.0 ? cd{0.0, 0.0} : cmul(acc, cinv(A[r][r]));
+    x[r] = cmul(acc, pinv[r]);
   }
   return ok;
 }
@@ -190,6 +192,15 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
   const bool live = idx < d.F * d.L;
   const int f = live ? idx / d.L : 0, l = live ? idx - f * d.L : 0;
 
+  // Q_fl (every lane of the block) and this lane's row of it, loaded with the covariance
+  // slots so that both arrive in one round trip.
+  // Every load is 16 bytes wide: the block of Q and the slots are 16-byte aligned (and gfx950
+  // keeps at most 63 loads in flight per wave, so narrower loads would take two round trips).
+  cx<R>* qb = Q + (size_t)f * d.QF + l * ML2;
+  R qv[2 * ML2], qr[2 * ML];  // interleaved (re, im)
+  load16<R, 2 * ML2>(qv, reinterpret_cast<const R*>(qb));
+  load16<R, 2 * ML>(qr, reinterpret_cast<const R*>(qb + r * ML));  // r is not a compile-time index
+
   // V_r = (sum over slices) / T, Hermitian from its packed entries.
   cd V[ML][ML];
   {
@@ -198,13 +209,22 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
     for (int j = 0; j < ML2; ++j) vs[j] = 0.0;
     const double* vp = Vpart + (size_t)f * d.SG * d.VF + (size_t)l * ML * ML2 + r * ML2;
     const int ns = cov_slots(d, f);
-    for (int s = 0; s < ns; ++s) {
-      double part[ML2];
+    constexpr int SU = 3;  // slots loaded together (the covariance kernel's grid touches at most 3)
+    double part[SU][ML2];
 #pragma unroll
-      for (int j = 0; j < ML2; ++j) part[j] = vp[(size_t)s * d.VF + j];
+    for (int s = 0; s < SU; ++s) {
+      load16<double, ML2>(part[s], vp + (size_t)(s < ns ? s : 0) * d.VF);
 #pragma unroll
-      for (int j = 0; j < ML2; ++j) vs[j] += (double)part[j];
+      for (int j = 0; j < ML2; ++j) part[s][j] = s < ns ? part[s][j] : 0.0;
     }
+    sched_fence();  // every load above in flight before the first use
+#pragma unroll
+    for (int s = 0; s < SU; ++s)
+#pragma unroll
+      for (int j = 0; j < ML2; ++j) vs[j] += part[s][j];
+    for (int s = SU; s < ns; ++s)
+#pragma unroll
+      for (int j = 0; j < ML2; ++j) vs[j] += vp[(size_t)s * d.VF + j];
     // Packed order: the M_l diagonal entries, then (Re, Im) of V[a][b], a < b, row-major.
     const double invT = 1.0 / d.T;
 #pragma unroll
@@ -221,24 +241,18 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
   cd vdinv[ML];
   const bool vok = hpd_factor<ML>(V, vdinv);
 
-  // Q_fl (every lane of the block), column r of its inverse, ln|det Q_fl|.
-  cx<R>* qb = Q + (size_t)f * d.QF + l * ML2;
-  cd A[ML][ML + 1], row[ML];
+  // Column r of Q_fl^{-1} and ln|det Q_fl| (every sweep from Q itself, so a run resumed from
+  // the state is bitwise identical to an uninterrupted one).
+  cd A[ML][ML + 1], row[ML], ci[ML];
 #pragma unroll
   for (int a = 0; a < ML; ++a)
 #pragma unroll
-    for (int c = 0; c < ML; ++c) {
-      const cx<R> v = qb[a * ML + c];
-      A[a][c] = {(double)v.re, (double)v.im};
-    }
+    for (int c = 0; c < ML; ++c) A[a][c] = {(double)qv[2 * (a * ML + c)], (double)qv[2 * (a * ML + c) + 1]};
 #pragma unroll
-  for (int c = 0; c < ML; ++c) {
-    const cx<R> v = qb[r * ML + c];  // this lane's row (r is not a compile-time index)
-    row[c] = {(double)v.re, (double)v.im};
-  }
-  cd ci[ML];
+  for (int c = 0; c < ML; ++c) row[c] = {(double)qr[2 * c], (double)qr[2 * c + 1]};
   double ld;
   const bool qok = inverse_column<ML>(A, r, ci, ld);
+  double wprod = 1.0;
 
 #pragma unroll
   for (int mu = 0; mu < ML; ++mu) {
@@ -272,13 +286,15 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
       const cd fac = cmul(bq, cinv(w));
 #pragma unroll
       for (int k = 0; k < ML; ++k) ci[k] = csub(ci[k], cmul(sC[blk][k], fac));
-      ld += 0.5 * log(cabs2(w));
+      wprod *= cabs2(w);
     }
     __syncthreads();
   }
+  ld += 0.5 * log(wprod);  // one log for the M_l factors |b^H c|^2 (each O(1) after eq. (16))
   if (!live) return;
 #pragma unroll
   for (int c = 0; c < ML; ++c) qb[r * ML + c] = {(R)row[c].re, (R)row[c].im};
+
   if (r == 0) logdet[idx] = qok ? ld : -INFINITY;
 }
 
