@@ -62,11 +62,12 @@ static bool choose_fast(Dims& d, int dtype) {
     d.TB = 16;
     d.TBN = (d.T + 15) / 16;
     d.TP = (d.T + 15) & ~15;
-    // k_gramd_f: four workgroups per CU share the F*T frames equally; a bin then has one
-    // partial-sum slot per workgroup that touched it.
+    // k_gramd_f: as many workgroups as fit on the chip at once share the F*T frames equally;
+    // a bin then has one partial-sum slot per workgroup that touched it.
     if (dtype == DFM_C64 && (ml == 2 || ml == 4)) {
       const long long total = (long long)d.F * d.T;
-      const long long want = 4LL * compute_units();
+      const int per_cu = fast_gramd_blocks_per_cu(d);
+      const long long want = (long long)(per_cu > 0 ? per_cu : 2) * compute_units();
       d.GR = (int)std::max<long long>((total + want - 1) / want, 32);
       d.GW = (int)((total + d.GR - 1) / d.GR);
       d.SG = (d.T + d.GR - 1) / d.GR + 1;

@@ -473,8 +473,8 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<RI>* __restrict_
 
 // ------------------------------------------------------------------------------------
 // Weighted covariances (eq. (14)) for subarrays of M_l <= 4 mics, FP32 inputs, FP64 sums.
-// A fixed number of workgroups (four per CU) share the flattened (f, t) frames equally, so
-// every SIMD gets the same work; kGDL lanes per subarray: lane j takes frames j, j + kGDL,
+// As many workgroups as fit on the chip at once share the flattened (f, t) frames equally,
+// so every SIMD gets the same work; kGDL lanes per subarray: lane j takes frames j, j + kGDL,
 // ... of each bin segment of the workgroup's share.  Per frame it forms 1/y for the
 // subarray's mics (FP32), the packed entries of x^(l) x^(l)H in FP64 (exact: products of
 // FP32 values) and adds (1/y_mu) x x^H into M_l x M_l^2 FP64 registers; the lanes' sums are
@@ -1538,6 +1538,18 @@ struct Set {
     return align_up(sizeof(double) * N * M, 16) + sizeof(double) * (size_t)d.SLP * (G::MP + G::OP);
   }
   static size_t max_smem(const Dims& d) { return kGramD ? 0 : smem_gram(d); }
+  // Workgroups of k_gramd_f resident per CU (registers and LDS), or 0 if unknown.
+  static int gramd_blocks_per_cu() {
+    if constexpr (kGramD) {
+      int n = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gramd_f<N, K, ML, L>, gramd_threads<L>(), 0) !=
+          hipSuccess)
+        return 0;
+      return n;
+    } else {
+      return 0;
+    }
+  }
 
   // Cost or Wiener filter at the end of a run: lambda for the current W, H, then Q^{-1} and
   // ln|det Q|, then the per-frame kernel.
@@ -1644,6 +1656,17 @@ int fast_set_index(int N, int K, int ML, int L) {
   DFM_FAST_SETS(DFM_MATCH)
 #undef DFM_MATCH
   return -1;
+}
+
+int fast_gramd_blocks_per_cu(const Dims& d) {
+  switch (d.fast) {
+#define DFM_OCC(i, n, k, ml, l) \
+  case i:                      \
+    return fast::Set<float, n, k, ml, l>::gramd_blocks_per_cu();
+    DFM_FAST_SETS(DFM_OCC)
+#undef DFM_OCC
+  }
+  return 0;
 }
 
 size_t fast_max_smem(const Dims& d, int dtype) {
