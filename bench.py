@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FastMNMF iterations/sec (F·T·M bins/s) at 4×4 mics N=5; % MFMA/HBM peak"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # dense FP64 (vector and matrix cores) of MI355X
 
 # Algorithmic HBM bytes per F*T*M bin for each streaming kernel of the FP32 path
 # (complex64 X = 8 B, FP32 P = 4 B).  One iteration's schedule reads X twice and
@@ -322,7 +323,7 @@ def main():
         f"{dominant}: {dom_ms * 1e3:.1f} us avg over {dom_n} launches")
 
     base = dominant[:-2] if dominant.endswith("_f") else dominant   # shape-specialised variants
-    traffic = load_traffic(dominant)
+    traffic = load_traffic(dominant) if w["name"] == "paper_4x4" else None  # counters taken on paper_4x4
     if base in BYTES_PER_BIN:
         traffic_alg = BYTES_PER_BIN[base] * bins
         achieved = traffic_alg / (dom_ms * 1e-3) / 1e9
@@ -334,6 +335,16 @@ def main():
         roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
                 "traffic": traffic, "kernel": dominant, "avg_us": round(dom_ms * 1e3, 3), "launches": dom_n}
 
+    # The contraction of eq. (14) runs on the FP64 matrix cores (16x16x4) when a subarray has
+    # more than four mics: price it against the FP64 MFMA peak at the flops of eq. (14) as
+    # written (a complex multiply-add is 8 flops, sum over subarrays of M_l^3 per frame).
+    gram_mfma = None
+    if "k_gram_f" in ktimes and max(mics) > 4:
+        flops = 8.0 * sum(ml ** 3 for ml in mics) * F * T
+        tf = flops / (ktimes["k_gram_f"] * 1e-3) / 1e12
+        gram_mfma = {"bound": "mfma", "kernel": "k_gram_f", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4), "flops_per_launch": flops,
+                     "avg_us": round(ktimes["k_gram_f"] * 1e3, 2)}
     out = {"metric": METRIC, "value": round(value, 3), "unit": "iterations/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -344,6 +355,8 @@ def main():
            "bins_per_s": round(value * bins, 1),
            "per_kernel_us": {k: round(v * 1e3, 2) for k, v in ktimes.items()},
            "roofline": roof}
+    if gram_mfma:
+        out["roofline_gram"] = gram_mfma
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(w, X32.astype(np.complex128), W32.astype(np.float64),

@@ -19,6 +19,8 @@ Workloads (names are what they are, sizes in the name):
   in [0, 20] samples per (source, mic) and a gain in [0.5, 2] per
   (subarray, source); with five sources every 4-mic subarray is locally
   underdetermined, as in the paper's five-source condition (Sec. IV-A).
+* ``paper_16`` -- the same recording (drawn exactly as ``paper_4x4``) with one
+  16-mic block: the conventional, non-distributed method (L = 1).
 
 Sources: s_ftn ~ CN(0, (W*_n H*_n)_ft) with W*_n ~ Gamma(1,1)[F,K] and
 H*_n ~ Gamma(1,1)[K,T]; x_ft = sum_n a_fn s_ftn + CN(0, 1e-3 I).
@@ -63,6 +65,10 @@ WORKLOADS = {
                           mixing="iid", seed=0, iters=10),
     "paper_4x4": Workload("paper_4x4", F=513, T=625, mics=(4, 4, 4, 4), N=5, K=16,
                           mixing="delay", seed=1, iters=100),
+    # The same recording as paper_4x4 (drawn with its four-subarray steering), separated
+    # with one 16-mic block: the conventional FastMNMF the paper compares against.
+    "paper_16": Workload("paper_16", F=513, T=625, mics=(16,), N=5, K=16,
+                         mixing="delay", seed=1, iters=100, extra={"data_mics": (4, 4, 4, 4)}),
 }
 
 
@@ -132,7 +138,7 @@ def make(workload, seed: int | None = None, T: int | None = None, F: int | None 
     seed = wl.seed if seed is None else seed
     F = wl.F if F is None else F
     T = wl.T if T is None else T
-    X = mixture(F, T, wl.mics, wl.N, wl.K, seed, mixing=wl.mixing, noise=wl.noise)
+    X = mixture(F, T, wl.extra.get("data_mics", wl.mics), wl.N, wl.K, seed, mixing=wl.mixing, noise=wl.noise)
     Q, g, W, H = initial_state(F, T, wl.mics, wl.N, wl.K, seed + 1)
     return dict(X=X, Q=Q, g=g, W=W, H=H, mics=tuple(wl.mics), N=wl.N, K=wl.K,
                 F=F, T=T, M=wl.M, name=wl.name, iters=wl.iters)
