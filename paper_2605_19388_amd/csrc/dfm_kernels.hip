@@ -74,83 +74,134 @@ __global__ __launch_bounds__(kBlock) void k_gram(Dims d, const cx<R>* __restrict
   }
 }
 
-// IP sweep over the rows of one subarray block Q_fl, eqs. (15)-(16), in FP64.
-// Block (f, l).  For mu = 0..M_l-1: V_mu from the slice sums, A = Q V_mu,
-// solve A b = e_mu, b <- b / sqrt(max(Re b^H V_mu b, eps)), row mu of Q <- b^H.
-// Finally ln|det Q_fl| (used by the cost (13)).
+// IP sweep over the rows of one subarray block Q_fl, eqs. (15)-(16), in FP64; block (f, l).
+// (Q V_mu) b = e_mu is solved as V_mu b = c with c = Q^{-1} e_mu (the same system, Q being
+// nonsingular).  Q^{-1} comes from Q once per sweep (Gauss-Jordan elimination with partial
+// pivoting); then for mu = 0..M_l-1: V_mu from the slot sums, V_mu b = c by Gauss-Jordan
+// elimination without pivoting (V_mu is Hermitian positive definite), b <- b / sqrt(max(b^H c,
+// eps)) (b^H c = b^H V_mu b, eq. (16)), row mu of Q <- b^H, and with u^H = b^H Q^{-1} the
+// rank-1 update Q^{-1} <- Q^{-1} - c (u^H - e_mu^T) / (b^H c) of the inverse for the new row;
+// ln|det Q_fl| (for the cost (13)) from the pivots of Q and ln|b^H c| of each row.  Every
+// elimination step updates all rows at once, one element per thread.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_ip(Dims d, const double* __restrict__ Vpart, cx<R>* __restrict__ Q,
                                                double* __restrict__ logdet, int* __restrict__ status) {
   const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, bd = blockDim.x;
-  const int Ml = d.mics[l];
-  const int ld = Ml + 1;
-  __shared__ cd sQ[kMaxMl * kMaxMl];
-  __shared__ cd sV[kMaxMl * kMaxMl];
-  __shared__ cd sA[kMaxMl * (kMaxMl + 1)];
-  __shared__ cd sb[kMaxMl];
-  __shared__ double s_logabs;
-  __shared__ int s_sing;
+  const int Ml = d.mics[l], l2 = 2 * Ml, lv = Ml + 1;
+  __shared__ cd sQ[kMaxMl * kMaxMl];      // Q, rows replaced as the sweep goes
+  __shared__ cd sI[kMaxMl * 2 * kMaxMl];  // [Q | I] -> columns Ml .. 2 Ml - 1: Q^{-1}
+  __shared__ cd sV[kMaxMl * (kMaxMl + 1)];  // [V_mu | c]
+  __shared__ cd sc[kMaxMl], sb[kMaxMl], su[kMaxMl];
+  __shared__ double s_logabs, s_w2;
+  __shared__ int s_sing, s_ok;
 
   cx<R>* qb = Q + (size_t)f * d.QF + d.qoff[l];
-  for (int i = tid; i < Ml * Ml; i += bd) sQ[i] = {(double)qb[i].re, (double)qb[i].im};
+  for (int i = tid; i < Ml * l2; i += bd) {
+    const int r = i / l2, c = i - r * l2;
+    const cd q = c < Ml ? cd{(double)qb[r * Ml + c].re, (double)qb[r * Ml + c].im} : cd{c - Ml == r ? 1.0 : 0.0, 0.0};
+    sI[i] = q;
+    if (c < Ml) sQ[r * Ml + c] = q;
+  }
+  __syncthreads();
+  eliminate(sI, l2, Ml, l2, &s_logabs, &s_sing);
+  if (s_sing) {  // Q itself singular: keep it, report it (uniform: read after the last barrier)
+    if (tid == 0) {
+      atomicOr(status, kStSingular);
+      logdet[(size_t)f * d.L + l] = -INFINITY;
+    }
+    return;
+  }
+  // Back substitution, one thread per column of the inverse.
+  for (int c = tid; c < Ml; c += bd)
+    for (int r = Ml - 1; r >= 0; --r) {
+      cd acc = sI[r * l2 + Ml + c];
+      for (int j = r + 1; j < Ml; ++j) acc = csub(acc, cmul(sI[r * l2 + j], sI[j * l2 + Ml + c]));
+      sI[r * l2 + Ml + c] = cabs2(sI[r * l2 + r]) == 0.0 ? cd{0.0, 0.0} : cmul(acc, cinv(sI[r * l2 + r]));
+    }
+  auto qinv = [&](int r, int c) -> cd& { return sI[r * l2 + Ml + c]; };
   const double invT = 1.0 / d.T;
 
   for (int mu = 0; mu < Ml; ++mu) {
-    const double* vp = Vpart + (size_t)f * d.S * d.VF + d.voff[l] + mu * Ml * Ml;
+    __syncthreads();  // Q^{-1} (and the previous row's update) complete
+    const double* vp = Vpart + (size_t)f * d.SG * d.VF + d.voff[l] + mu * Ml * Ml;
+    const int ns = cov_slots(d, f);
     for (int j = tid; j < Ml * Ml; j += bd) {
       double acc = 0.0;
-      for (int s = 0; s < d.S; ++s) acc += (double)vp[(size_t)s * d.VF + j];
+      for (int s = 0; s < ns; ++s) acc += vp[(size_t)s * d.VF + j];
       acc *= invT;
       int a, b, part;
       packed_pair(Ml, j, a, b, part);
       if (a == b) {
-        sV[a * Ml + a] = {acc, 0.0};
+        sV[a * lv + a] = {acc, 0.0};
       } else if (part == 0) {
-        sV[a * Ml + b].re = acc;
-        sV[b * Ml + a].re = acc;
+        sV[a * lv + b].re = acc;
+        sV[b * lv + a].re = acc;
       } else {
-        sV[a * Ml + b].im = acc;
-        sV[b * Ml + a].im = -acc;
+        sV[a * lv + b].im = acc;
+        sV[b * lv + a].im = -acc;
       }
     }
+    for (int r = tid; r < Ml; r += bd) {
+      sc[r] = qinv(r, mu);
+      sV[r * lv + Ml] = qinv(r, mu);
+    }
+    if (tid == 0) s_ok = 1;
     __syncthreads();
+    // Gauss-Jordan on [V_mu | c]: step p clears column p above and below the pivot.  A step
+    // reads row p and column p only, which it does not write.
+    for (int p = 0; p < Ml; ++p) {
+      const cd pv = sV[p * lv + p];
+      if (cabs2(pv) == 0.0) {  // same value in every thread: uniform exit
+        if (tid == 0) s_ok = 0;
+        break;
+      }
+      const cd inv = cinv(pv);
+      const int w = Ml - p;  // columns p + 1 .. Ml
+      for (int i = tid; i < (Ml - 1) * w; i += bd) {
+        const int rr = i / w, r = rr < p ? rr : rr + 1, c = p + 1 + (i - rr * w);
+        sV[r * lv + c] = csub(sV[r * lv + c], cmul(cmul(sV[r * lv + p], inv), sV[p * lv + c]));
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (s_ok)
+      for (int r = tid; r < Ml; r += bd) sb[r] = cmul(sV[r * lv + Ml], cinv(sV[r * lv + r]));
+    __syncthreads();
+    if (tid == 0) {
+      bool ok = s_ok != 0;
+      if (ok) {
+        cd bc = {0.0, 0.0};
+        for (int r = 0; r < Ml; ++r) bc = cadd(bc, cmul(cconj(sb[r]), sc[r]));
+        const double scl = 1.0 / sqrt(bc.re > d.eps ? bc.re : d.eps);
+        for (int r = 0; r < Ml; ++r) sb[r] = {sb[r].re * scl, sb[r].im * scl};
+        s_w2 = cabs2(bc) * scl * scl;  // |b^H c|^2 after the scaling
+        ok = s_w2 > 0.0;
+      }
+      s_ok = ok;
+      if (!ok) atomicOr(status, kStSingular);  // row kept; reported as DFM_E_SINGULAR
+    }
+    __syncthreads();
+    if (!s_ok) continue;
+    for (int c = tid; c < Ml; c += bd) {
+      sQ[mu * Ml + c] = cconj(sb[c]);
+      cd acc = {0.0, 0.0};  // u_c = (b^H Q^{-1})_c
+      for (int k = 0; k < Ml; ++k) acc = cadd(acc, cmul(cconj(sb[k]), qinv(k, c)));
+      su[c] = acc;
+    }
+    __syncthreads();
+    const cd winv = cinv(su[mu]);  // 1 / (b^H c)
     for (int i = tid; i < Ml * Ml; i += bd) {
       const int r = i / Ml, c = i - r * Ml;
-      cd acc = {0.0, 0.0};
-      for (int j = 0; j < Ml; ++j) acc = cadd(acc, cmul(sQ[r * Ml + j], sV[j * Ml + c]));
-      sA[r * ld + c] = acc;
+      const cd uc = c == mu ? csub(su[c], cd{1.0, 0.0}) : su[c];
+      qinv(r, c) = csub(qinv(r, c), cmul(sc[r], cmul(uc, winv)));
     }
-    for (int r = tid; r < Ml; r += bd) sA[r * ld + Ml] = {r == mu ? 1.0 : 0.0, 0.0};
-    __syncthreads();
-    eliminate(sA, ld, Ml, Ml + 1, &s_logabs, &s_sing);
-    if (tid == 0) {
-      if (s_sing) {
-        atomicOr(status, kStSingular);  // row kept; the host reports DFM_E_SINGULAR
-      } else {
-        for (int r = Ml - 1; r >= 0; --r) {
-          cd acc = sA[r * ld + Ml];
-          for (int c = r + 1; c < Ml; ++c) acc = csub(acc, cmul(sA[r * ld + c], sb[c]));
-          sb[r] = cmul(acc, cinv(sA[r * ld + r]));
-        }
-        double sv = 0.0;
-        for (int a = 0; a < Ml; ++a) {
-          cd vb = {0.0, 0.0};
-          for (int b = 0; b < Ml; ++b) vb = cadd(vb, cmul(sV[a * Ml + b], sb[b]));
-          sv += sb[a].re * vb.re + sb[a].im * vb.im;
-        }
-        const double sc = 1.0 / sqrt(sv > d.eps ? sv : d.eps);
-        for (int c = 0; c < Ml; ++c) sQ[mu * Ml + c] = {sb[c].re * sc, -sb[c].im * sc};
-      }
-    }
-    __syncthreads();
+    if (tid == 0) s_logabs += 0.5 * log(s_w2);
   }
+  __syncthreads();
   for (int i = tid; i < Ml * Ml; i += bd) {
     qb[i].re = (R)sQ[i].re;
     qb[i].im = (R)sQ[i].im;
-    sA[(i / Ml) * Ml + i % Ml] = {(double)qb[i].re, (double)qb[i].im};
   }
-  __syncthreads();
-  eliminate(sA, Ml, Ml, Ml, &s_logabs, &s_sing);
   if (tid == 0) logdet[(size_t)f * d.L + l] = s_logabs;
 }
 
@@ -442,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_logdet(Dims d, const cx<R>* __restri
   for (int i = tid; i < Ml * Ml; i += blockDim.x) sA[i] = {(double)qb[i].re, (double)qb[i].im};
   __syncthreads();
   eliminate(sA, Ml, Ml, Ml, &s_logabs, &s_sing);
-  if (tid == 0) logdet[(size_t)f * d.L + l] = s_sing ? -INFINITY : s_logabs;
+  if (tid == 0) logdet[(size_t)f * d.L + l] = s_logabs;
 }
 
 // Q_fl^{-1} in FP64 by Gauss-Jordan on [Q | I].  Block (f, l).
