@@ -48,3 +48,13 @@ def test_delay_mixing_is_unit_modulus_times_gain():
     # at f = 0 all mics of one subarray see the same gain-weighted sum: ratio between mics is real
     r = X[0, :, 1] / X[0, :, 0]
     assert np.allclose(r.imag, 0.0, atol=1e-9)
+
+
+def test_conventional_workload_shares_the_recording():
+    """paper_16 separates the very recording of paper_4x4 with one 16-mic block (L = 1)."""
+    a = synth.make("paper_4x4", T=40, F=33)
+    b = synth.make("paper_16", T=40, F=33)
+    assert np.array_equal(a["X"], b["X"])
+    assert b["mics"] == (16,) and b["Q"].shape == (33, 256)
+    assert np.array_equal(b["Q"][:, ::17], np.ones((33, 16)))  # identity block
+    assert np.array_equal(a["W"], b["W"]) and np.array_equal(a["H"], b["H"])
