@@ -137,8 +137,10 @@ dfm_status dfm_sync_status(dfm_plan* plan, void* stream);
 
 /* ---- Measurement (not part of the method; used to price kernels against the roofline).
  * The kernels of one iteration of a plan are numbered 0 .. dfm_kernel_count(plan)-1 in
- * launch order (eight; the streaming kernels are shape-specialised for uniform
- * partitions with a compiled (N, K, M_l, L) set). */
+ * launch order (seven or eight; the streaming kernels are shape-specialised for
+ * uniform partitions with a compiled (N, K, M_l, L) set).  Where the covariance
+ * kernel of the next iteration finishes the g update, the kernel that finishes
+ * the last one runs once per dfm_step call and is not among them. */
 int32_t dfm_kernel_count(const dfm_plan* plan);
 /* Static name of kernel i of the plan's iteration, or NULL if out of range. */
 const char* dfm_kernel_name(const dfm_plan* plan, int32_t kernel);

@@ -76,6 +76,13 @@ static bool choose_fast(Dims& d, int dtype) {
       d.GW = 0;
       d.SG = d.S;
     }
+    // k_g_f: four workgroups per CU share the F*T frames equally.
+    {
+      const long long total = (long long)d.F * d.T, want = 4LL * compute_units();
+      d.GGR = (int)std::max<long long>((total + want - 1) / want, 16);
+      d.GGW = (int)((total + d.GGR - 1) / d.GGR);
+      d.GGS = (d.T + d.GGR - 1) / d.GGR + 1;
+    }
     if (fast_max_smem(d, dtype) <= 64 * 1024) return true;
   }
   d.fast = -1;
@@ -152,7 +159,8 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   const bool fast = d.fast >= 0;
   n += al(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);    // Wpart
   n += al(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);  // Hpart
-  n += al(fast ? 0 : r * d.F * d.S * d.N * d.M * 2);    // gpart
+  n += al(fast ? r * d.F * d.GGS * d.N * d.M * 2 : r * d.F * d.S * d.N * d.M * 2);  // gpart
+  n += al(fast ? r * d.F * d.N * d.M : 0);              // gsnap
   n += al(8 * d.F * d.L);                              // logdet
   n += al(8 * d.F * d.S);                              // nllpart
   n += al(16 * d.F * d.QF);                            // Qinv
@@ -175,7 +183,8 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   const bool fast = d.fast >= 0;
   b.Wpart = take(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);
   b.Hpart = take(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);
-  b.gpart = take(fast ? 0 : r * d.F * d.S * d.N * d.M * 2);
+  b.gpart = take(fast ? r * d.F * d.GGS * d.N * d.M * 2 : r * d.F * d.S * d.N * d.M * 2);
+  b.gsnap = fast ? take(r * d.F * d.N * d.M) : nullptr;
   b.logdet = reinterpret_cast<double*>(take(8 * d.F * d.L));
   b.nllpart = reinterpret_cast<double*>(take(8 * d.F * d.S));
   b.Qinv = take(16 * d.F * d.QF);
@@ -271,10 +280,17 @@ dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream) {
   // The specialised kernels read lambda = W H, which the W and H updates then keep
   // current; seed it from the caller's state.
   if (n_iter > 0 && plan->d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess) return DFM_E_HIP;
-  for (int it = 0; it < n_iter; ++it)
-    for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G; ++stage)
-      if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
-  return DFM_OK;
+  // Where the g update ends in k_g_f's partial sums (dfm::g_update_deferred), the next
+  // iteration's covariance kernel finishes it, and k_gfin_f after the last one.
+  const bool defer = dfm::g_update_deferred(plan->d);
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
+    plan->d.gpend = defer && it > 0;
+    for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G && e == hipSuccess; ++stage) e = dfm::run_stage(plan, stage, s);
+  }
+  plan->d.gpend = 0;
+  if (e == hipSuccess && defer && n_iter > 0) e = dfm::run_kernel(plan, dfm::kFGFin, s);
+  return e == hipSuccess ? DFM_OK : DFM_E_HIP;
 }
 
 dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream) {
@@ -284,6 +300,8 @@ dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream) {
   // the specialised kernels read.
   if (plan->d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess) return DFM_E_HIP;
   if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
+  if (stage == DFM_STAGE_G && dfm::g_update_deferred(plan->d) && dfm::run_kernel(plan, dfm::kFGFin, s) != hipSuccess)
+    return DFM_E_HIP;
   return DFM_OK;
 }
 

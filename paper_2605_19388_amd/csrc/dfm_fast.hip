@@ -17,7 +17,8 @@
 //   k_wgemm_f  sums over frames of eq. (8) on the matrix cores, the W update and lambda = W H.
 //   k_h_f      per-frame coefficient planes of eq. (9) with the new lambda.
 //   k_hgemm_f  sums over bins of eq. (9) on the matrix cores, the H update and lambda = W H.
-//   k_g_f      one workgroup per bin: the sums over frames of eq. (10) and the g update.
+//   k_g_f      equal ranges of the F*T frames per workgroup: partial sums over frames of eq. (10);
+//   k_gfin_f   the g update from each bin's partials.
 //
 // Every reduction finishes in a fixed order inside one kernel (wave sums added in wave
 // order in LDS, partial-sum slots added in slot order), so results are identical run to
@@ -487,6 +488,36 @@ constexpr int kGDL = 32;  // lanes per subarray
 
 constexpr int kGDH = 1;   // lanes per frame (each sums ML / kGDH of the rows mu)
 
+// g <- g sqrt(num / max(den, eps)) of eq. (10) for one (f, n, m): num and den are the sums of
+// the bin's `need` partials of k_g_f (stride 2 N M, den at offset N M), added in slot order with
+// four slots' loads in flight at a time.  Every kernel that finishes the g update calls this, so
+// they agree bit for bit.
+template <typename R>
+__device__ __forceinline__ R g_updated(const R* __restrict__ part, int need, int NM, R gv, R eps) {
+  R nu = 0, de = 0;
+  for (int s0 = 0; s0 < need; s0 += 4) {
+    R pn[4], pd[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int sl = min(s0 + u, need - 1);
+      pn[u] = part[(size_t)sl * 2 * NM];
+      pd[u] = part[(size_t)sl * 2 * NM + NM];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (s0 + u < need) {
+        nu += pn[u];
+        de += pd[u];
+      }
+  }
+  return gv * sqrt(nu / rmax(de, eps));
+}
+
+// Partial-sum slots of bin f in k_g_f's equal ranges of Dims::GGR frames.
+__device__ __forceinline__ int g_slots(const Dims& d, int f) {
+  return (f * d.T + d.T - 1) / d.GGR - (f * d.T) / d.GGR + 1;
+}
+
 template <int L>
 constexpr int gramd_threads() {
   return (kGDH * L * kGDL + 63) / 64 * 64;
@@ -495,7 +526,9 @@ constexpr int gramd_threads() {
 template <int N, int K, int ML, int L>
 __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx<float>* __restrict__ X,
                                                                const float* __restrict__ lamin,
-                                                               const float* __restrict__ g,
+                                                               float* __restrict__ g,
+                                                               const float* __restrict__ gpart,
+                                                               const float* __restrict__ gsnap,
                                                                double* __restrict__ V) {
   constexpr int M = ML * L, ML2 = ML * ML, MH = ML / kGDH, NO = MH * ML2;  // outputs per lane
   constexpr int FB = 2;  // frames per load batch; the next batch is in flight during the current one
@@ -503,6 +536,7 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
   static_assert(ML == 2 || ML == 4, "M_l of 2 or 4");
   static_assert(kGDH == 1 && NO % RH == 0 && RH % 2 == 0 && (RS / 2) % 2 == 1, "reduction passes");
   __shared__ __align__(16) double red[gramd_threads<L>() * RS];
+  __shared__ float sg[N * M];  // the bin's g when a g update is pending
   const int tid = threadIdx.x;
   const int h = tid / (L * kGDL), l = min(tid / kGDL % L, L - 1), j = tid % kGDL;  // row half, subarray, lane
   const bool live = tid < kGDH * L * kGDL;
@@ -518,15 +552,6 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
     const int slot = blockIdx.x - (int)(((long long)f * T) / d.GR);
     i0 = fend;
 
-    float gl[N][MH];
-#pragma unroll
-    for (int n = 0; n < N; ++n)
-#pragma unroll
-      for (int mu = 0; mu < MH; ++mu) gl[n][mu] = g[((size_t)f * N + n) * M + l * ML + min(h, kGDH - 1) * MH + mu];
-    double acc[NO];
-#pragma unroll
-    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
-
     const float* xb = reinterpret_cast<const float*>(X + (size_t)f * T * M + l * ML);
     const float* lb = lamin + (size_t)f * N * T;
     float xv[FB][2 * ML], lam[FB][N], xn[FB][2 * ML], ln[FB][N];
@@ -539,7 +564,32 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
         for (int n = 0; n < N; ++n) la[u][n] = lb[(size_t)n * T + t];
       }
     };
-    if (ts + j < te) fetch(ts + j, xv, lam);
+    if (ts + j < te) fetch(ts + j, xv, lam);  // the first frames' loads fly during the g below
+    // g of the bin.  With an update pending (Dims::gpend), each workgroup finishes it from the
+    // previous g update's partials and copy of g, neither of which this kernel writes; the
+    // workgroup holding the bin's first frame stores the result.
+    const float* gsrc = g + (size_t)f * N * M;
+    if (d.gpend) {
+      constexpr int NM = N * M;
+      static_assert(NM <= gramd_threads<L>(), "one thread per g entry");
+      if (tid < NM) {
+        const float v = g_updated<float>(gpart + (size_t)f * d.GGS * 2 * NM + tid, g_slots(d, f), NM,
+                                         gsnap[(size_t)f * NM + tid], (float)d.eps);
+        sg[tid] = v;
+        if (ts == 0) g[(size_t)f * NM + tid] = v;
+      }
+      __syncthreads();
+      gsrc = sg;
+    }
+    float gl[N][MH];
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+      for (int mu = 0; mu < MH; ++mu) gl[n][mu] = gsrc[n * M + l * ML + min(h, kGDH - 1) * MH + mu];
+    double acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+
     for (int t0 = ts + j; t0 < te; t0 += FB * kGDL) {
       if (t0 + FB * kGDL < te) fetch(t0 + FB * kGDL, xn, ln);
       sched_fence();
@@ -1193,181 +1243,125 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
 }
 
 // ------------------------------------------------------------------------------------
-// Diagonal SCM update, eq. (10), one workgroup per frequency: num/den[n][m] =
-// sum_t lambda_n (P_m / y_m^2, 1 / y_m) over every frame, then g <- g sqrt(num / max(den, eps)).
-// Frames are taken in passes of GShape::PF, one thread per frame: 1/y and P/y^2 are formed
-// and stored frame-major in LDS with lambda (read), while the next pass's P and lambda are
-// already in flight; the sums over the pass then run, in FP32, on the 4x4x1 matrix-core
-// blocks (block = (4 sources, 4 mics, numerator or denominator), one op per frame, frames
-// dealt to the four waves), in FP64 on the vector units.  The waves' sums are added in
-// wave order in LDS.
-constexpr int kGT = 256;  // threads of the g-update workgroup
+// Diagonal SCM update, eq. (10): num/den[n][m] = sum_t lambda_n (P_m / y_m^2, 1 / y_m) over
+// every frame, then g <- g sqrt(num / max(den, eps)).  The F*T frames are dealt out in equal
+// contiguous ranges of Dims::GGR to Dims::GGW workgroups (a range may run into the next bins).
+// A lane owns one mic of one frame per step (64 / M frames per wave), keeps the 2N sums of its
+// mic in registers, and loads the next batch of P and lambda while it computes the current one.
+// A workgroup adds its lanes' sums in a fixed order through LDS into one partial per bin it
+// touched (slot = its rank among the bin's workgroups).  The g update itself (each bin's partials
+// added in slot order) is finished by k_gfin_f or, inside a run of iterations, by the next
+// iteration's k_gramd_f, which applies it to the copy of g kept here.  (Finishing a bin in the last workgroup to reach it would need a
+// device-scope fence per workgroup, which on this chip writes back and invalidates the L2 of
+// the workgroup's XCD; that made the kernel ten times slower.)
+constexpr int kGT = 256;  // threads of a g-update workgroup
+constexpr int kGU = 2;    // steps per batch of loads
 
-template <typename R, int N, int K, int ML, int L>
+template <typename R, int N, int M>
 struct GShape {
-  static constexpr int M = ML * L;
-  static constexpr int NP = (N + 3) & ~3;
-  static constexpr int AP = padded<R>(NP);     // LDS row of lambda
-  static constexpr int BP = padded<R>(2 * M);  // LDS row of P/y^2 then 1/y
-  static constexpr int NGR = NP / 4, MG = M / 4;
-  static constexpr int NI = (2 * NGR * MG + 15) / 16;
-  static constexpr int PF = sizeof(R) == 4 ? 256 : 128;  // frames per pass
-  static constexpr size_t smem() {
-    return (sizeof(R) * N * M + 15) / 16 * 16 + sizeof(R) * (size_t)PF * (AP + BP) + sizeof(R) * 2 * N * M;
-  }
+  static constexpr int FPW = 64 / M;              // frames per wave and step
+  static constexpr int FS = (kGT / 64) * FPW;     // frames per workgroup and step
+  static constexpr int RED = (kGT / 64) * 2 * N * 64;  // LDS: the lanes' sums
 };
 
 template <typename R, int N, int K, int ML, int L>
-__global__ __launch_bounds__(kGT) void k_g_f(Dims d, const R* __restrict__ lamin, R* __restrict__ g,
-                                             const R* __restrict__ P, int* __restrict__ status) {
-  typedef GShape<R, N, K, ML, L> G;
-  constexpr int M = G::M, NP = G::NP, AP = G::AP, BP = G::BP, PF = G::PF;
-  constexpr int E = V16<R>::E;
-  static_assert(M % 4 == 0 && M % E == 0 && NP % E == 0 && N * M <= kGT, "shape");
-  static_assert(G::NI * 256 * 4 <= PF * BP, "cross-wave sums fit in the P/y^2 rows");
-  static_assert(G::smem() <= 64 * 1024, "LDS of the g-update workgroup");
-  typedef typename V16<R>::type vt;
-  const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__global__ __launch_bounds__(kGT) void k_g_f(Dims d, const R* __restrict__ lamin, const R* __restrict__ g,
+                                             const R* __restrict__ P, R* __restrict__ gpart, R* __restrict__ gsnap) {
+  constexpr int M = ML * L;
+  typedef GShape<R, N, M> G;
+  constexpr int FPW = G::FPW, FS = G::FS, NM = N * M;
+  static_assert(FPW >= 1 && 2 * NM <= kGT, "shape");
+  __shared__ R red[G::RED];  // [wave][2N][64]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = lane / M, m = lane - j * M;  // frame within the wave's step, mic
+  const bool lane_ok = j < FPW;
+  const int me = wave * FPW + j;  // frame offset within a workgroup step
   const int T = d.T;
-  extern __shared__ __align__(16) unsigned char smem[];
-  R* sg = reinterpret_cast<R*>(smem);
-  R* sA = reinterpret_cast<R*>(smem + align_up(sizeof(R) * N * M, 16));  // [PF][AP]
-  R* sB = sA + (size_t)PF * AP;                                            // [PF][BP]
-  R* sND = sB + (size_t)PF * BP;                                           // [N*M][2]
-
-  // Operands of the first pass (this thread's frame), g of the frequency.
-  R pv[M], lam[NP];
-  auto fetch = [&](int t) {
-    const bool live = tid < PF && t < T;
+  const R eps = (R)d.eps;
+  const int a = blockIdx.x * d.GGR, b = min(a + d.GGR, d.F * T);
+  for (int s0 = a; s0 < b;) {
+    const int f = s0 / T, e = min(b, (f + 1) * T);
+    const int t0 = s0 - f * T, t1 = e - f * T;
+    s0 = e;
+    // The workgroup holding the bin's first frame keeps a copy of the g this update multiplies.
+    if (t0 == 0 && tid < NM) gsnap[(size_t)f * NM + tid] = g[(size_t)f * NM + tid];
+    R gm[N], num[N], den[N];
 #pragma unroll
-    for (int n = 0; n < NP; ++n) lam[n] = (live && n < N) ? lamin[((size_t)f * N + n) * T + t] : (R)0;
-    if (live) {
-      load16<R, M>(pv, P + ((size_t)f * T + t) * M);
-    } else {
-#pragma unroll
-      for (int m = 0; m < M; ++m) pv[m] = 0;
+    for (int n = 0; n < N; ++n) {
+      gm[n] = g[((size_t)f * N + n) * M + m];
+      num[n] = 0;
+      den[n] = 0;
     }
-  };
-  fetch(tid);
-  R gv = 0;
-  if (tid < N * M) gv = g[(size_t)f * N * M + tid];
-  sched_fence();
-  if (tid < N * M) sg[tid] = gv;
-
-  typedef float v4f __attribute__((ext_vector_type(4)));
-  constexpr int NI = G::NI, NGR = G::NGR, MG = G::MG;
-  const int sub = lane & 3;
-  v4f acc[NI];
-  int aoff[NI], boff[NI];
+    const R* Pf = P + (size_t)f * T * M + m;
+    const R* Lf = lamin + (size_t)f * N * T;
+    // Loads of one batch (kGU steps); frames past the range read the range's last frame.
+    auto fetch = [&](int tb, R(&pv)[kGU], R(&lv)[kGU][N]) {
 #pragma unroll
-  for (int q = 0; q < NI; ++q) {
-    acc[q] = v4f{0, 0, 0, 0};
-    const int blk = 16 * q + (lane >> 2);
-    const bool ok = blk < 2 * NGR * MG;
-    const int ng = blk % NGR, rest = blk / NGR, mg = rest % MG, uz = rest / MG;
-    aoff[q] = ok ? 4 * ng + sub : 0;
-    boff[q] = ok ? uz * M + 4 * mg + sub : 0;
-  }
-  R num = 0, den = 0;  // FP64 path: thread o = n * M + m
-
-  for (int t0 = 0; t0 < T; t0 += PF) {
-    const int np = min(PF, T - t0);
-    __syncthreads();  // sg staged / previous pass's rows consumed
-    if (tid < PF) {
-      const bool live = tid < np;
-      R u[2 * M];
+      for (int u = 0; u < kGU; ++u) {
+        const int t = min(tb + u * FS + me, t1 - 1);
+        pv[u] = Pf[(size_t)t * M];
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
+        for (int n = 0; n < N; ++n) lv[u][n] = Lf[(size_t)n * T + t];
+      }
+    };
+    R pa[kGU], la[kGU][N], pb[kGU], lb[kGU][N];
+    fetch(t0, pa, la);
+    for (int tb = t0; tb < t1; tb += kGU * FS) {
+      fetch(tb + kGU * FS, pb, lb);
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
+        const bool live = lane_ok && tb + u * FS + me < t1;
         R y = 0;
 #pragma unroll
-        for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
-        const R iy = live ? rcp(rmax(y, (R)d.eps)) : (R)0;
-        u[m] = pv[m] * iy * iy;
-        u[M + m] = iy;
-      }
+        for (int n = 0; n < N; ++n) y += la[u][n] * gm[n];
+        const R iy = live ? rcp(rmax(y, eps)) : (R)0;
+        const R w = pa[u] * iy * iy;
 #pragma unroll
-      for (int i = 0; i < NP / E; ++i) {
-        vt v;
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = lam[i * E + e];
-        reinterpret_cast<vt*>(sA + (size_t)tid * AP)[i] = v;
-      }
-#pragma unroll
-      for (int i = 0; i < 2 * M / E; ++i) {
-        vt v;
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = u[i * E + e];
-        reinterpret_cast<vt*>(sB + (size_t)tid * BP)[i] = v;
-      }
-    }
-    if (t0 + PF < T) fetch(t0 + PF + tid);  // next pass, in flight during the sums
-    __syncthreads();
-    const int ntp = (np + 3) & ~3;  // rows past np hold zeros
-    if constexpr (sizeof(R) == 4) {
-      constexpr int FW = PF / 4;  // frames per wave
-      const int fb = wave * FW, fe = min(fb + FW, ntp);
-      for (int t4 = fb; t4 < fe; t4 += 4) {
-        R av[4][NI], bv[4][NI];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int q = 0; q < NI; ++q) {
-            av[u][q] = sA[(size_t)(t4 + u) * AP + aoff[q]];
-            bv[u][q] = sB[(size_t)(t4 + u) * BP + boff[q]];
-          }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int q = 0; q < NI; ++q)
-            acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u][q], bv[u][q], acc[q], 0, 0, 0);
-      }
-    } else {
-      if (tid < N * M) {
-        const int n = tid / M, m = tid - n * M;
-        for (int tt = 0; tt < ntp; ++tt) {
-          const R lv = sA[(size_t)tt * AP + n];
-          num += lv * sB[(size_t)tt * BP + m];
-          den += lv * sB[(size_t)tt * BP + M + m];
+        for (int n = 0; n < N; ++n) {
+          num[n] += la[u][n] * w;
+          den[n] += la[u][n] * iy;
         }
       }
-    }
-  }
-  if constexpr (sizeof(R) == 4) {
-    // Wave sums into LDS (over the P/y^2 rows), added in wave order into sND.
-    R* red = sB;  // [wave][NI][64][4]
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NI; ++q)
+      for (int u = 0; u < kGU; ++u) {
+        pa[u] = pb[u];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[((wave * NI + q) * 64 + lane) * 4 + r] = acc[q][r];
-    __syncthreads();
-    if (wave == 0)
-#pragma unroll
-      for (int q = 0; q < NI; ++q) {
-        const int blk = 16 * q + (lane >> 2);
-        if (blk >= 2 * NGR * MG) continue;
-        const int ng = blk % NGR, rest = blk / NGR, mg = rest % MG, uz = rest / MG;
-        const int m = 4 * mg + sub;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int n = 4 * ng + r;
-          R v = 0;
-#pragma unroll
-          for (int w = 0; w < kGT / 64; ++w) v += red[((w * NI + q) * 64 + lane) * 4 + r];
-          if (n < N) sND[(n * M + m) * 2 + uz] = v;
-        }
+        for (int n = 0; n < N; ++n) la[u][n] = lb[u][n];
       }
+    }
+    // Lane sums -> this workgroup's partial for bin f (index q * M + m, q < N: numerators).
+    __syncthreads();  // the previous segment's readers of red are done
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      red[(wave * 2 * N + n) * 64 + lane] = num[n];
+      red[(wave * 2 * N + N + n) * 64 + lane] = den[n];
+    }
     __syncthreads();
-    if (tid < N * M) {
-      num = sND[tid * 2];
-      den = sND[tid * 2 + 1];
+    const int first = (f * T) / d.GGR;
+    if (tid < 2 * NM) {
+      const int q = tid / M, mm = tid - q * M;
+      R v = 0;
+#pragma unroll
+      for (int w = 0; w < kGT / 64; ++w)
+#pragma unroll
+        for (int jj = 0; jj < FPW; ++jj) v += red[(w * 2 * N + q) * 64 + jj * M + mm];
+      gpart[((size_t)f * d.GGS + blockIdx.x - first) * 2 * NM + tid] = v;
     }
   }
-  if (tid < N * M) {
-    const R v = gv * sqrt(num / rmax(den, (R)d.eps));
-    if (!isfinite(v)) atomicOr(status, kStNonFinite);
-    g[(size_t)f * N * M + tid] = v;
-  }
+}
+
+// g <- g sqrt(num / max(den, eps)) of eq. (10), one thread per (f, n, m): the bin's partials of
+// k_g_f added in slot order.
+template <typename R, int N, int M>
+__global__ __launch_bounds__(256) void k_gfin_f(Dims d, const R* __restrict__ gpart, R* __restrict__ g,
+                                               int* __restrict__ status) {
+  constexpr int NM = N * M;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= d.F * NM) return;
+  const int f = i / NM, o = i - f * NM;
+  const R v = g_updated<R>(gpart + (size_t)f * d.GGS * 2 * NM + o, g_slots(d, f), NM, g[i], (R)d.eps);
+  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  g[i] = v;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1589,7 +1583,8 @@ struct Set {
       case kFGram:
         if constexpr (kGramD) {
           hipLaunchKernelGGL((k_gramd_f<N, K, ML, L>), dim3(d.GW), dim3(gramd_threads<L>()), 0, s, d, X,
-                             static_cast<const R*>(b.lam), g, static_cast<double*>(b.Vpart));
+                             static_cast<const R*>(b.lam), g, static_cast<const R*>(b.gpart),
+                             static_cast<const R*>(b.gsnap), static_cast<double*>(b.Vpart));
         } else {
           hipLaunchKernelGGL((k_gram_f<double, R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d,
                              X, static_cast<const R*>(b.lam), g, static_cast<double*>(b.Vpart));
@@ -1622,8 +1617,12 @@ struct Set {
                            static_cast<R*>(b.lam), b.status);
         break;
       case kFG:
-        hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.F), dim3(kGT), (GShape<R, N, K, ML, L>::smem()), s, d,
-                           static_cast<const R*>(b.lam), g, P, b.status);
+        hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.GGW), dim3(kGT), 0, s, d, static_cast<const R*>(b.lam), g,
+                           P, static_cast<R*>(b.gpart), static_cast<R*>(b.gsnap));
+        break;
+      case kFGFin:
+        hipLaunchKernelGGL((k_gfin_f<R, N, M>), dim3((d.F * N * M + 255) / 256), dim3(256), 0, s, d,
+                           static_cast<const R*>(b.gpart), g, b.status);
         break;
       default:
         return hipErrorInvalidValue;

@@ -36,6 +36,10 @@ struct Dims {
   int SG;    // partial-sum slots per bin of the covariances (S slices, or balanced ranges, below)
   int GR;    // k_gramd_f: flattened (f, t) frames per workgroup (0: per-slice partials)
   int GW;    // k_gramd_f: workgroups
+  int GGR;   // k_g_f: flattened (f, t) frames per workgroup
+  int GGW;   // k_g_f: workgroups
+  int GGS;   // k_g_f: partial-sum slots per bin
+  int gpend;  // k_gramd_f finishes the previous iteration's g update (set inside dfm_step only)
   int mics[kMaxL];  // M_l
   int moff[kMaxL];  // first mic of subarray l
   int qoff[kMaxL];  // offset of block l in a frequency's packed Q (complex units)
@@ -54,7 +58,8 @@ struct Buffers {
   void* Vpart;   // [F][SG][VF] double: packed covariance sums (FP64 on every path)
   void* Wpart;   // [F][S][N][K][2] real (generic kernels)
   void* Hpart;   // [FS][N][K][T][2] real (generic kernels)
-  void* gpart;   // [F][S][N][M][2] real (generic kernels)
+  void* gpart;   // generic: [F][S][N][M][2] real; specialised: [F][GGS][2][N][M] real
+  void* gsnap;   // [F][N][M] real (specialised): the g that a pending g update multiplies
   double* logdet;   // [F][L]
   double* nllpart;  // [F][S]
   void* Qinv;       // [F][QF] complex double
@@ -70,7 +75,7 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 // lambda = W H).
 enum KernelId {
   kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply,
-  kFGram, kFIp, kFPw, kFWGemm, kFH, kFHGemm, kFG, kFLam, kNumKernels
+  kFGram, kFIp, kFPw, kFWGemm, kFH, kFHGemm, kFG, kFLam, kFGFin, kNumKernels
 };
 
 // Launchers (return hipSuccess or the first launch error).
@@ -78,6 +83,9 @@ hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s);
 hipError_t launch_kernel(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
 const char* kernel_name(int kid);
 int stage_kernels(const Dims& d, int stage, int* kids);  // fills kids, returns count
+// Specialised sets whose covariance kernel is k_gramd_f: the G stage ends with k_g_f's partial
+// sums, and the g update is finished by the next k_gramd_f (Dims::gpend) or by k_gfin_f.
+inline bool g_update_deferred(const Dims& d) { return d.fast >= 0 && d.GR > 0; }
 int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns count
 
 // Shape-specialised kernel sets (dfm_fast.hip).

@@ -74,6 +74,9 @@ STAGE_CASES = [
     (20, 77, (4, 4), 3, 16),
     (20, 77, (4, 4, 4), 8, 16),
     (33, 130, (2, 2), 2, 4),
+    # Fewer frames per bin than a g-update workgroup's range: ranges span up to six bins.
+    (23, 9, (4, 4, 4, 4), 5, 16),
+    (7, 3, (2, 2), 2, 4),
 ]
 
 FAST = ["k_gramd_f", "k_ip_f", "k_pw_f", "k_wgemm_f", "k_h_f", "k_hgemm_f", "k_g_f"]
