@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--workload", default="paper_4x4")
     ap.add_argument("--iters", type=int, default=None, help="iterations per step (default: the workload's)")
     ap.add_argument("--cpu-sample-iters", type=int, default=4)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the oracle's NumPy/BLAS pools (default: as the host sets them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -125,19 +127,23 @@ def load_traffic(kernel):
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
-def cpu_baseline(w, X64, W0, H0, n_iter):
-    """Time the FP64 oracle, unmodified, on n_iter iterations of the same full-size workload."""
+def cpu_baseline(w, X64, W0, H0, n_iter, threads=0):
+    """Time the FP64 oracle, unmodified, on n_iter iterations of the same full-size workload
+    (with its thread pools limited to `threads` if that is positive)."""
+    import contextlib
+
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import dfmnmf as D
 
     Q, g = w["Q"], w["g"]
-    st = D.iterate(X64, Q, g, W0, H0, w["mics"], 1)          # warm-up
-    t0 = time.perf_counter()
-    D.iterate(X64, *st, w["mics"], n_iter)
-    dt = time.perf_counter() - t0
-    threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    with threadpool_limits(limits=threads) if threads > 0 else contextlib.nullcontext():
+        st = D.iterate(X64, Q, g, W0, H0, w["mics"], 1)          # warm-up
+        t0 = time.perf_counter()
+        D.iterate(X64, *st, w["mics"], n_iter)
+        dt = time.perf_counter() - t0
+        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
     return {"value": n_iter / dt, "unit": "iterations/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_iter} of {w['iters']} iterations of {w['name']} at full size "
                       f"(F={w['F']}, T={w['T']}, M={w['M']}, N={w['N']}, K={w['K']}) after 1 warm-up "
@@ -360,7 +366,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(w, X32.astype(np.complex128), W32.astype(np.float64),
-                                           H32.astype(np.float64), args.cpu_sample_iters)
+                                           H32.astype(np.float64), args.cpu_sample_iters, args.cpu_threads)
     print(json.dumps(out), flush=True)
 
 

@@ -21,6 +21,9 @@ Workloads (names are what they are, sizes in the name):
   underdetermined, as in the paper's five-source condition (Sec. IV-A).
 * ``paper_16`` -- the same recording (drawn exactly as ``paper_4x4``) with one
   16-mic block: the conventional, non-distributed method (L = 1).
+* ``table2`` -- the shape of the paper's runtime comparison (Sec. IV, Table II):
+  F=2049 (4096-point STFT), T=157, three subarrays of four mics (M=12), N=3,
+  K=16, 200 iterations; mixing as ``paper_4x4``.
 
 Sources: s_ftn ~ CN(0, (W*_n H*_n)_ft) with W*_n ~ Gamma(1,1)[F,K] and
 H*_n ~ Gamma(1,1)[K,T]; x_ft = sum_n a_fn s_ftn + CN(0, 1e-3 I).
@@ -69,6 +72,8 @@ WORKLOADS = {
     # with one 16-mic block: the conventional FastMNMF the paper compares against.
     "paper_16": Workload("paper_16", F=513, T=625, mics=(16,), N=5, K=16,
                          mixing="delay", seed=1, iters=100, extra={"data_mics": (4, 4, 4, 4)}),
+    "table2": Workload("table2", F=2049, T=157, mics=(4, 4, 4), N=3, K=16,
+                       mixing="delay", seed=5, iters=200),
 }
 
 

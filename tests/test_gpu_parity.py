@@ -73,6 +73,7 @@ STAGE_CASES = [
     (18, 150, (16,), 5, 16),
     (20, 77, (4, 4), 3, 16),
     (20, 77, (4, 4, 4), 8, 16),
+    (21, 50, (4, 4, 4), 3, 16),
     (33, 130, (2, 2), 2, 4),
     # Fewer frames per bin than a g-update workgroup's range: ranges span up to six bins.
     (23, 9, (4, 4, 4, 4), 5, 16),
