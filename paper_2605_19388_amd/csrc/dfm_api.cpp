@@ -83,6 +83,7 @@ static bool choose_fast(Dims& d, int dtype) {
       d.GGW = (int)((total + d.GGR - 1) / d.GGR);
       d.GGS = (d.T + d.GGR - 1) / d.GGR + 1;
     }
+    d.HC = fast_hgemm_windows(d, dtype);
     if (fast_max_smem(d, dtype) <= 64 * 1024) return true;
   }
   d.fast = -1;
@@ -158,7 +159,9 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   n += al(8 * (size_t)d.F * d.SG * d.VF);              // Vpart (FP64 sums)
   const bool fast = d.fast >= 0;
   n += al(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);    // Wpart
-  n += al(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);  // Hpart
+  const size_t kp16 = 16 * 4 * (size_t)((d.K + 3) / 4);
+  n += al(fast ? (d.HC > 1 ? r * d.N * d.TBN * d.HC * 2 * kp16 : 0) : r * (size_t)d.FS * d.N * d.K * d.T * 2);  // Hpart
+  n += al(fast && d.HC > 1 ? r * d.N * d.K * d.T : 0);  // Hsnap
   n += al(fast ? r * d.F * d.GGS * d.N * d.M * 2 : r * d.F * d.S * d.N * d.M * 2);  // gpart
   n += al(fast ? r * d.F * d.N * d.M : 0);              // gsnap
   n += al(8 * d.F * d.L);                              // logdet
@@ -182,7 +185,9 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   b.Vpart = take(8 * (size_t)d.F * d.SG * d.VF);
   const bool fast = d.fast >= 0;
   b.Wpart = take(fast ? 0 : r * d.F * d.S * d.N * d.K * 2);
-  b.Hpart = take(fast ? 0 : r * (size_t)d.FS * d.N * d.K * d.T * 2);
+  const size_t kp16 = 16 * 4 * (size_t)((d.K + 3) / 4);
+  b.Hpart = take(fast ? (d.HC > 1 ? r * d.N * d.TBN * d.HC * 2 * kp16 : 0) : r * (size_t)d.FS * d.N * d.K * d.T * 2);
+  b.Hsnap = fast && d.HC > 1 ? take(r * d.N * d.K * d.T) : nullptr;
   b.gpart = take(fast ? r * d.F * d.GGS * d.N * d.M * 2 : r * d.F * d.S * d.N * d.M * 2);
   b.gsnap = fast ? take(r * d.F * d.N * d.M) : nullptr;
   b.logdet = reinterpret_cast<double*>(take(8 * d.F * d.L));

@@ -1110,6 +1110,25 @@ __global__ __launch_bounds__(kT) void k_h_f(Dims d, const R* __restrict__ lamin,
 // iteration read it).  Step st of chunk c takes bins c * 16 + 4 st + kk, so each 4-byte
 // plane load of a wave is one contiguous 256-byte run.  LDS window: sW[f - f0][k] =
 // W[n][f][k] for f0 <= f < f0 + FW, row stride KP + 4, zero beyond F and K.
+// Window [f0, f0 + nf) of W[n] -> sW, flat over (bin, basis) with row stride GemmLds::WS; every
+// load is issued before the first LDS write.
+template <typename R, int K>
+__device__ __forceinline__ void stage_w(R* sW, const R* wn, int F, int f0, int nf, int tid) {
+  typedef GemmLds<R, K> G;
+  constexpr int KP = G::KP, WS = G::WS;
+  R v[G::WNE];
+#pragma unroll
+  for (int q = 0; q < G::WNE; ++q) {
+    const int e = tid + q * 64 * kGW, fl = e / KP, k = e - fl * KP, f = f0 + fl;
+    v[q] = (fl < nf && f < F && k < K) ? wn[(size_t)f * K + k] : (R)0;
+  }
+#pragma unroll
+  for (int q = 0; q < G::WNE; ++q) {
+    const int e = tid + q * 64 * kGW, fl = e / KP, k = e - fl * KP;
+    if (fl < nf) sW[fl * WS + k] = v[q];
+  }
+}
+
 template <typename R, int N, int K>
 __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restrict__ W, const R* __restrict__ AB,
                                                       R* __restrict__ H, R* __restrict__ lam,
@@ -1239,6 +1258,147 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
           if (f < F) lam[((size_t)f * N + n) * T + t] = acc[r];
         }
     }
+  }
+}
+
+// H update split along the bins, for shapes where W[n] takes more than one LDS window (F above
+// about 600 bins in FP32 with K = 16): window c of k_hgemm_f goes to workgroup (n, tt, c) of
+// k_hsum_f, which writes its partial sums and (c = 0) a copy of the H it updates; k_hlam_f adds
+// a 16-frame block's partials in window order, applies the update (every workgroup the same way,
+// the c = 0 workgroup storing H) and writes lambda = W H for its window of bins.  The copy is
+// what k_hlam_f multiplies, so no workgroup reads H while another writes it.
+template <typename R, int N, int K>
+__global__ __launch_bounds__(64 * kGW) void k_hsum_f(Dims d, const R* __restrict__ W, const R* __restrict__ AB,
+                                                     const R* __restrict__ H, R* __restrict__ Hpart,
+                                                     R* __restrict__ Hsnap) {
+  typedef GemmLds<R, K> G;
+  constexpr int KT = G::KT, KP = G::KP, WS = G::WS;
+  static_assert(KT <= 2, "bases per source");
+  typedef typename Mma<R>::v4 v4;
+  __shared__ R red[kGW * 2 * KT * 256];
+  extern __shared__ __align__(16) unsigned char dyn[];
+  R* sW = reinterpret_cast<R*>(dyn);
+  const int n = blockIdx.x, tt = blockIdx.y, t0 = tt * 16, c = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int T = d.T, F = d.F;
+  const int FP = (F + 15) & ~15, FW = G::fw(d);
+  const int f0 = c * FW, nf = min(FW, FP - f0), cb = f0 / 16, ce = cb + nf / 16;
+  const R* ap = AB + ((size_t)n * d.TBN + tt) * F * 16 + i;
+  const R* bp = AB + ((size_t)(N + n) * d.TBN + tt) * F * 16 + i;
+  const R* wn = W + (size_t)n * F * K;
+  const bool tok = t0 + i < T;
+
+  v4 accN[KT], accD[KT];
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt) {
+    accN[kt] = v4{0, 0, 0, 0};
+    accD[kt] = v4{0, 0, 0, 0};
+  }
+  R av[kGB][4], bv[kGB][4];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int cc = min(c0 + u * kGW, ce - 1);
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int f = min(cc * 16 + 4 * st + kk, F - 1);
+        av[u][st] = ap[(size_t)f * 16];
+        bv[u][st] = bp[(size_t)f * 16];
+      }
+    }
+  };
+  load(cb + wave);  // first batch in flight while the window is staged
+  stage_w<R, K>(sW, wn, F, f0, nf, tid);
+  __syncthreads();
+  for (int c0 = cb + wave; c0 < ce; c0 += kGW * kGB) {
+    if (c0 != cb + wave) {
+      load(c0);
+      sched_fence();
+    }
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int cc = c0 + u * kGW;
+      const int fl = (min(cc, ce - 1) - cb) * 16;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int f = cc * 16 + 4 * st + kk;
+        const bool ok = cc < ce && f < F && tok;
+        const R a = ok ? av[u][st] : (R)0, b = ok ? bv[u][st] : (R)0;
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const int k = kt * 16 + i;
+          const R w = k < K ? sW[(fl + 4 * st + kk) * WS + (k < K ? k : 0)] : (R)0;
+          accN[kt] = Mma<R>::run(w, a, accN[kt]);
+          accD[kt] = Mma<R>::run(w, b, accD[kt]);
+        }
+      }
+    }
+  }
+  spill_tiles<R, KT>(red, wave, lane, accN, accD);
+  __syncthreads();
+  R* part = Hpart + (((size_t)n * d.TBN + tt) * d.HC + c) * 2 * KP * 16;
+  for (int e = tid; e < KP * 16; e += 64 * kGW) {
+    const int k = e >> 4, tl = e & 15, t = t0 + tl;
+    R num, den;
+    sum_tiles<R, KT>(red, k >> 4, k & 15, tl, num, den);
+    part[e] = num;
+    part[KP * 16 + e] = den;
+    if (c == 0 && k < K && t < T) Hsnap[((size_t)n * K + k) * T + t] = H[((size_t)n * K + k) * T + t];
+  }
+}
+
+template <typename R, int N, int K>
+__global__ __launch_bounds__(64 * kGW) void k_hlam_f(Dims d, const R* __restrict__ Hpart, const R* __restrict__ Hsnap,
+                                                     const R* __restrict__ W, R* __restrict__ H, R* __restrict__ lam,
+                                                     int* __restrict__ status) {
+  typedef GemmLds<R, K> G;
+  constexpr int KP = G::KP, KS = KP / 4, WS = G::WS;
+  typedef typename Mma<R>::v4 v4;
+  __shared__ R sHn[KP * 16];  // new H of the 16 frames, [k][t], zero beyond K and T
+  extern __shared__ __align__(16) unsigned char dyn[];
+  R* sW = reinterpret_cast<R*>(dyn);
+  const int n = blockIdx.x, tt = blockIdx.y, t0 = tt * 16, c = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int T = d.T, F = d.F;
+  const int FP = (F + 15) & ~15, FW = G::fw(d);
+  const int f0 = c * FW, nf = min(FW, FP - f0), cb = f0 / 16, ce = cb + nf / 16;
+  stage_w<R, K>(sW, W + (size_t)n * F * K, F, f0, nf, tid);  // loads fly during the update
+  const R* part = Hpart + ((size_t)n * d.TBN + tt) * d.HC * 2 * KP * 16;
+  for (int e = tid; e < KP * 16; e += 64 * kGW) {
+    const int k = e >> 4, tl = e & 15, t = t0 + tl;
+    R h = 0;
+    if (k < K && t < T) {
+      R num = 0, den = 0;
+      for (int cc = 0; cc < d.HC; ++cc) {
+        num += part[(size_t)cc * 2 * KP * 16 + e];
+        den += part[(size_t)cc * 2 * KP * 16 + KP * 16 + e];
+      }
+      const size_t idx = ((size_t)n * K + k) * T + t;
+      h = Hsnap[idx] * sqrt(num / rmax(den, (R)d.eps));
+      if (c == 0) {
+        if (!isfinite(h)) atomicOr(status, kStNonFinite);
+        H[idx] = h;
+      }
+    }
+    sHn[e] = h;
+  }
+  __syncthreads();
+  R hb[KS];
+#pragma unroll
+  for (int st = 0; st < KS; ++st) hb[st] = sHn[(4 * st + kk) * 16 + i];
+  for (int cc = cb + wave; cc < ce; cc += kGW) {
+    v4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < KS; ++st) acc = Mma<R>::run(sW[((cc - cb) * 16 + i) * WS + 4 * st + kk], hb[st], acc);
+    const int t = t0 + i;
+    if (t < T)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int f = cc * 16 + Mma<R>::row(lane, r);
+        if (f < F) lam[((size_t)f * N + n) * T + t] = acc[r];
+      }
   }
 }
 
@@ -1532,6 +1692,11 @@ struct Set {
     return align_up(sizeof(double) * N * M, 16) + sizeof(double) * (size_t)d.SLP * (G::MP + G::OP);
   }
   static size_t max_smem(const Dims& d) { return kGramD ? 0 : smem_gram(d); }
+  // LDS windows of W[n] in the H update (k_hgemm_f, or k_hsum_f / k_hlam_f when above one).
+  static int hgemm_windows(const Dims& d) {
+    const int fp = (d.F + 15) & ~15, fw = GemmLds<R, K>::fw(d);
+    return (fp + fw - 1) / fw;
+  }
   // Workgroups of k_gramd_f resident per CU (registers and LDS), or 0 if unknown.
   static int gramd_blocks_per_cu() {
     if constexpr (kGramD) {
@@ -1612,9 +1777,19 @@ struct Set {
                            static_cast<const R*>(b.lam), g, P, static_cast<R*>(b.AB));
         break;
       case kFHGemm:
-        hipLaunchKernelGGL((k_hgemm_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kGW),
-                           (GemmLds<R, K>::hgemm_smem(d)), s, d, W, static_cast<const R*>(b.AB), H,
-                           static_cast<R*>(b.lam), b.status);
+        if (d.HC > 1)
+          hipLaunchKernelGGL((k_hsum_f<R, N, K>), dim3(N, d.TBN, d.HC), dim3(64 * kGW),
+                             (GemmLds<R, K>::hgemm_smem(d)), s, d, W, static_cast<const R*>(b.AB), H,
+                             static_cast<R*>(b.Hpart), static_cast<R*>(b.Hsnap));
+        else
+          hipLaunchKernelGGL((k_hgemm_f<R, N, K>), dim3(N, (d.T + 15) / 16), dim3(64 * kGW),
+                             (GemmLds<R, K>::hgemm_smem(d)), s, d, W, static_cast<const R*>(b.AB), H,
+                             static_cast<R*>(b.lam), b.status);
+        break;
+      case kFHLam:
+        hipLaunchKernelGGL((k_hlam_f<R, N, K>), dim3(N, d.TBN, d.HC), dim3(64 * kGW),
+                           (GemmLds<R, K>::hgemm_smem(d)), s, d, static_cast<const R*>(b.Hpart),
+                           static_cast<const R*>(b.Hsnap), W, H, static_cast<R*>(b.lam), b.status);
         break;
       case kFG:
         hipLaunchKernelGGL((k_g_f<R, N, K, ML, L>), dim3(d.GGW), dim3(kGT), 0, s, d, static_cast<const R*>(b.lam), g,
@@ -1668,6 +1843,18 @@ int fast_gramd_blocks_per_cu(const Dims& d) {
   return 0;
 }
 
+int fast_hgemm_windows(const Dims& d, int dtype) {
+  switch (d.fast) {
+#define DFM_HW(i, n, k, ml, l)                                                       \
+  case i:                                                                            \
+    return dtype == DFM_C64 ? fast::Set<float, n, k, ml, l>::hgemm_windows(d)        \
+                            : fast::Set<double, n, k, ml, l>::hgemm_windows(d);
+    DFM_FAST_SETS(DFM_HW)
+#undef DFM_HW
+  }
+  return 1;
+}
+
 size_t fast_max_smem(const Dims& d, int dtype) {
   switch (d.fast) {
 #define DFM_SMEM(i, n, k, ml, l)                                                     \
@@ -1683,6 +1870,7 @@ size_t fast_max_smem(const Dims& d, int dtype) {
 const char* fast_kernel_name(const Dims& d, int dtype, int kid) {
   if (kid == kFGram && dtype == DFM_C64 && (d.ML == 2 || d.ML == 4)) return "k_gramd_f";
   if (kid == kFIp && d.ML > 4) return kernel_name(kKIp);
+  if (kid == kFHGemm && d.HC > 1) return "k_hsum_f";
   return kernel_name(kid);
 }
 

@@ -39,6 +39,7 @@ struct Dims {
   int GGR;   // k_g_f: flattened (f, t) frames per workgroup
   int GGW;   // k_g_f: workgroups
   int GGS;   // k_g_f: partial-sum slots per bin
+  int HC;    // LDS windows of W[n] in the H update: above 1, k_hsum_f / k_hlam_f replace k_hgemm_f
   int gpend;  // k_gramd_f finishes the previous iteration's g update (set inside dfm_step only)
   int mics[kMaxL];  // M_l
   int moff[kMaxL];  // first mic of subarray l
@@ -57,7 +58,8 @@ struct Buffers {
   void* P;       // [F][T][M] real: |Q x|^2 of the latest W sub-step
   void* Vpart;   // [F][SG][VF] double: packed covariance sums (FP64 on every path)
   void* Wpart;   // [F][S][N][K][2] real (generic kernels)
-  void* Hpart;   // [FS][N][K][T][2] real (generic kernels)
+  void* Hpart;   // generic: [FS][N][K][T][2] real; specialised with HC > 1: [N][TBN][HC][2][KP][16] real
+  void* Hsnap;   // [N][K][T] real (specialised with HC > 1): the H that the H update multiplies
   void* gpart;   // generic: [F][S][N][M][2] real; specialised: [F][GGS][2][N][M] real
   void* gsnap;   // [F][N][M] real (specialised): the g that a pending g update multiplies
   double* logdet;   // [F][L]
@@ -75,7 +77,7 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b);
 // lambda = W H).
 enum KernelId {
   kKGram = 0, kKIp, kKPw, kKWApply, kKH, kKHApply, kKG, kKGApply,
-  kFGram, kFIp, kFPw, kFWGemm, kFH, kFHGemm, kFG, kFLam, kFGFin, kNumKernels
+  kFGram, kFIp, kFPw, kFWGemm, kFH, kFHGemm, kFG, kFLam, kFGFin, kFHLam, kNumKernels
 };
 
 // Launchers (return hipSuccess or the first launch error).
@@ -91,6 +93,7 @@ int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns 
 // Shape-specialised kernel sets (dfm_fast.hip).
 int fast_set_index(int N, int K, int ML, int L);
 size_t fast_max_smem(const Dims& d, int dtype);
+int fast_hgemm_windows(const Dims& d, int dtype);  // LDS windows of W[n] in the H update
 int fast_gramd_blocks_per_cu(const Dims& d);  // resident k_gramd_f workgroups per CU (0: unknown)
 hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
 const char* fast_kernel_name(const Dims& d, int dtype, int kid);  // symbol family a kernel id runs

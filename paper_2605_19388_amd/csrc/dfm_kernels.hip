@@ -735,7 +735,7 @@ const char* kernel_name(int kid) {
   static const char* names[kNumKernels] = {"k_gram",   "k_ip",    "k_pw",    "k_wapply",  "k_h",
                                            "k_happly", "k_g",     "k_gapply", "k_gram_f", "k_ip_f",
                                            "k_pw_f",   "k_wgemm_f", "k_h_f",  "k_hgemm_f", "k_g_f",
-                                           "k_lam_f",  "k_gfin_f"};
+                                           "k_lam_f",  "k_gfin_f", "k_hlam_f"};
   return kid >= 0 && kid < kNumKernels ? names[kid] : nullptr;
 }
 
@@ -745,7 +745,12 @@ int stage_kernels(const Dims& d, int stage, int* kids) {
     switch (stage) {
       case DFM_STAGE_IP: kids[0] = kFGram; kids[1] = kFIp; return 2;
       case DFM_STAGE_W: kids[0] = kFPw; kids[1] = kFWGemm; return 2;
-      case DFM_STAGE_H: kids[0] = kFH; kids[1] = kFHGemm; return 2;
+      case DFM_STAGE_H:
+        kids[0] = kFH;
+        kids[1] = kFHGemm;
+        if (d.HC <= 1) return 2;
+        kids[2] = kFHLam;
+        return 3;
       case DFM_STAGE_G:
         kids[0] = kFG;
         if (g_update_deferred(d)) return 1;

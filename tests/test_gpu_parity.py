@@ -74,6 +74,10 @@ STAGE_CASES = [
     (20, 77, (4, 4), 3, 16),
     (20, 77, (4, 4, 4), 8, 16),
     (21, 50, (4, 4, 4), 3, 16),
+    # W[n] over more than one LDS window in the H update (FP64 above 176 bins, FP32 above 592):
+    # the bin-split H update.
+    (200, 37, (4, 4, 4), 3, 16),
+    (620, 21, (4, 4, 4), 3, 16),
     (33, 130, (2, 2), 2, 4),
     # Fewer frames per bin than a g-update workgroup's range: ranges span up to six bins.
     (23, 9, (4, 4, 4, 4), 5, 16),
