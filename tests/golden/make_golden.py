@@ -1,13 +1,17 @@
 #!/usr/bin/env python3
-"""Write tests/golden/paper_4x4_oracle.npz: the FP64 oracle's trajectory on the paper-shaped
-workload (F=513, T=625, four 4-mic subarrays, N=5, K=16, 100 iterations), for the GPU
-end-to-end parity test at full size.
+"""Write tests/golden/<workload>_oracle.npz: the FP64 oracle's trajectory on a full-size
+workload, for the GPU end-to-end parity tests:
+
+* ``paper_4x4`` -- F=513, T=625, four 4-mic subarrays, N=5, K=16; 100 iterations
+  (about 4 minutes on 8 cores);
+* ``table2`` -- the shape of the paper's Table II: F=2049, T=157, three 4-mic subarrays,
+  N=3, K=16; 50 iterations (about a minute on 8 cores).
 
 Only ``oracle/`` and the seeded input generator are called; the inputs are rounded to the
-storage precision of the FP32 path first.  Stored: the cost (13) at a
-few iteration counts and 8192 entries of the separated source images (Wiener filter per
-subarray) after the last iteration, at positions drawn from a fixed seed.  Run from the
-repository root:  python tests/golden/make_paper_4x4.py   (about 4 minutes on 8 cores).
+storage precision of the FP32 path first.  Stored: the cost (13) at a few iteration counts
+and 8192 entries of the separated source images (Wiener filter per subarray) after the last
+iteration, at positions drawn from a fixed seed.  Run from the repository root:
+    python tests/golden/make_golden.py paper_4x4
 """
 import os
 import sys
@@ -20,13 +24,13 @@ sys.path.insert(0, ROOT)
 from oracle import dfmnmf as D  # noqa: E402
 from paper_2605_19388_amd import synth  # noqa: E402
 
-CHECKPOINTS = (0, 1, 2, 5, 10, 20, 50, 100)
+CHECKPOINTS = {"paper_4x4": (0, 1, 2, 5, 10, 20, 50, 100), "table2": (0, 1, 2, 5, 10, 20, 50)}
 SAMPLES = 8192
 SAMPLE_SEED = 4242
 
 
-def main():
-    w = synth.make("paper_4x4")
+def main(name):
+    w = synth.make(name)
     # The inputs exactly as the FP32 path receives them (complex64 / float32), held in FP64.
     c64 = lambda a: np.asarray(a).astype(np.complex64).astype(np.complex128)  # noqa: E731
     r32 = lambda a: np.asarray(a).astype(np.float32).astype(np.float64)  # noqa: E731
@@ -35,7 +39,7 @@ def main():
     state = (c64(w["Q"]), r32(w["g"]), r32(w["W"]), r32(w["H"]))
     costs = {}
     done = 0
-    for target in CHECKPOINTS:
+    for target in CHECKPOINTS[name]:
         if target > done:
             state = D.iterate(X, *state, mics, target - done)
             done = target
@@ -46,12 +50,14 @@ def main():
     idx = np.stack([rng.integers(0, N, SAMPLES), rng.integers(0, F, SAMPLES),
                     rng.integers(0, T, SAMPLES), rng.integers(0, M, SAMPLES)]).astype(np.int32)
     vals = S[idx[0], idx[1], idx[2], idx[3]]
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_4x4_oracle.npz")
-    np.savez_compressed(out, checkpoints=np.array(CHECKPOINTS, dtype=np.int32),
-                        costs=np.array([costs[c] for c in CHECKPOINTS]), sample_index=idx, sample_values=vals,
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.npz")
+    np.savez_compressed(out, checkpoints=np.array(CHECKPOINTS[name], dtype=np.int32),
+                        costs=np.array([costs[c] for c in CHECKPOINTS[name]]), sample_index=idx, sample_values=vals,
                         source_norms=np.sqrt((np.abs(S) ** 2).sum(axis=(1, 2, 3))))
     print("wrote", out)
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) != 2 or sys.argv[1] not in CHECKPOINTS:
+        sys.exit(f"usage: make_golden.py {{{'|'.join(CHECKPOINTS)}}}")
+    main(sys.argv[1])

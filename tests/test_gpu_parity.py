@@ -184,12 +184,13 @@ def test_end_to_end_small_2x2(fp32):
 
 # ------------------------------------------------------------------ end to end, paper_4x4 workload
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_4x4_oracle.npz")
+GOLDEN_TABLE2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table2_oracle.npz")
 
 
 def test_end_to_end_paper_4x4_fp32():
     """FP32 path at full size (F=513, T=625, four 4-mic subarrays, N=5, K=16), in the launch
     configuration bench.py times, against the oracle's stored trajectory on the same rounded
-    inputs (tests/golden/make_paper_4x4.py): the cost at every checkpoint up to 100
+    inputs (tests/golden/make_golden.py): the cost at every checkpoint up to 100
     iterations and 8192 sampled entries of the separated images, 1e-4 relative per source."""
     ref = np.load(GOLDEN)
     w = synth.make("paper_4x4")
@@ -198,6 +199,35 @@ def test_end_to_end_paper_4x4_fp32():
     F, T, M = X.shape
     p = plan(X, mics, N, K, Q, g, W, H, True)
     assert p.kernel_names()[0] == "k_gramd_f"  # the specialised kernels bench.py times
+    done = 0
+    for c, cost in zip(ref["checkpoints"], ref["costs"]):
+        p.step(int(c) - done)
+        done = int(c)
+        got = p.nll()
+        assert nll_rel(got, cost, F, T, M) < 1e-4, (int(c), got, cost)
+    p.sync_status()
+    S = p.separate()
+    idx = torch.as_tensor(ref["sample_index"].astype(np.int64), device=S.device)
+    got = S[idx[0], idx[1], idx[2], idx[3]].cpu().numpy()
+    want = ref["sample_values"]
+    for n in range(N):
+        sel = ref["sample_index"][0] == n
+        assert rel(got[sel], want[sel]) < 1e-4, n
+
+
+def test_end_to_end_table2_fp32():
+    """FP32 path at the shape of the paper's Table II (F=2049, T=157, three 4-mic subarrays,
+    N=3, K=16), where the H update runs split over the LDS windows of W, against the oracle's
+    stored trajectory (tests/golden/make_golden.py): the cost at every checkpoint up to 50
+    iterations and 8192 sampled entries of the separated images, 1e-4 relative per source."""
+    ref = np.load(GOLDEN_TABLE2)
+    w = synth.make("table2")
+    mics, N, K = w["mics"], w["N"], w["K"]
+    X, Q, g, W, H = (as_precision(w[k], True) for k in ("X", "Q", "g", "W", "H"))
+    F, T, M = X.shape
+    p = plan(X, mics, N, K, Q, g, W, H, True)
+    names = p.kernel_names()
+    assert names[0] == "k_gramd_f" and "k_hsum_f" in names and "k_hlam_f" in names, names
     done = 0
     for c, cost in zip(ref["checkpoints"], ref["costs"]):
         p.step(int(c) - done)
