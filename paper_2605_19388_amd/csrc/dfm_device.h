@@ -21,6 +21,18 @@ __device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.
 __device__ __forceinline__ cd csub(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
 __device__ __forceinline__ cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cd cconj(cd a) { return {a.re, -a.im}; }
+// c + a b and c - a b with two fused multiply-adds per part (the unfused forms round the
+// product before the sum and take a third instruction).
+__device__ __forceinline__ cd cfma(cd c, cd a, cd b) {
+  return {fma(-a.im, b.im, fma(a.re, b.re, c.re)), fma(a.im, b.re, fma(a.re, b.im, c.im))};
+}
+__device__ __forceinline__ cd cfms(cd c, cd a, cd b) {
+  return {fma(a.im, b.im, fma(-a.re, b.re, c.re)), fma(-a.im, b.re, fma(-a.re, b.im, c.im))};
+}
+// c + conj(a) b.
+__device__ __forceinline__ cd cfmac(cd c, cd a, cd b) {
+  return {fma(a.im, b.im, fma(a.re, b.re, c.re)), fma(-a.im, b.re, fma(a.re, b.im, c.im))};
+}
 __device__ __forceinline__ double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
 __device__ __forceinline__ cd cinv(cd a) {
   const double s = 1.0 / cabs2(a);

@@ -91,6 +91,28 @@ __device__ __forceinline__ void store16(R* dst, const R (&src)[C]) {
 // the pivots of Q plus the sum of ln|b^H c| over the rows.  A zero pivot (V_mu or Q
 // singular) keeps the row and sets the sticky singular flag.
 
+// 1 / x and 1 / sqrt(x) in FP64 for the small solves: the hardware estimate refined by two
+// Newton steps (each squares the relative error, so an estimate good to 2^-14 ends below
+// 2^-53).  Shorter dependency chains than the IEEE division and square-root sequences, for
+// finite nonzero x (zero pivots are caught before).
+__device__ __forceinline__ double nr_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double nr_rsqrt(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) r = fma(r, fma(-h * r, r, 0.5), r);
+  return r;
+}
+__device__ __forceinline__ cd nr_cinv(cd a) {
+  const double s = nr_rcp(cabs2(a));
+  return {a.re * s, -a.im * s};
+}
+
 // LU factorisation without pivoting of a Hermitian positive (semi)definite n x n matrix in
 // registers (L unit lower, U upper; inverse pivots of U in dinv).  Elimination without
 // row exchanges is stable for such matrices; a zero pivot (a singular covariance, e.g. a
@@ -102,13 +124,13 @@ __device__ __forceinline__ bool hpd_factor(cd (&A)[n][n], cd (&dinv)[n]) {
   for (int p = 0; p < n; ++p) {
     const bool zero = cabs2(A[p][p]) == 0.0;
     if (zero) ok = false;
-    dinv[p] = zero ? cd{0.0, 0.0} : cinv(A[p][p]);
+    dinv[p] = zero ? cd{0.0, 0.0} : nr_cinv(A[p][p]);
 #pragma unroll
     for (int r = p + 1; r < n; ++r) {
       const cd fac = cmul(A[r][p], dinv[p]);
       A[r][p] = fac;
 #pragma unroll
-      for (int c = p + 1; c < n; ++c) A[r][c] = csub(A[r][c], cmul(fac, A[p][c]));
+      for (int c = p + 1; c < n; ++c) A[r][c] = cfms(A[r][c], fac, A[p][c]);
     }
   }
   return ok;
@@ -120,11 +142,11 @@ __device__ __forceinline__ void hpd_solve(const cd (&A)[n][n], const cd (&dinv)[
 #pragma unroll
   for (int r = 1; r < n; ++r)
 #pragma unroll
-    for (int c = 0; c < r; ++c) x[r] = csub(x[r], cmul(A[r][c], x[c]));
+    for (int c = 0; c < r; ++c) x[r] = cfms(x[r], A[r][c], x[c]);
 #pragma unroll
   for (int r = n - 1; r >= 0; --r) {
 #pragma unroll
-    for (int c = r + 1; c < n; ++c) x[r] = csub(x[r], cmul(A[r][c], x[c]));
+    for (int c = r + 1; c < n; ++c) x[r] = cfms(x[r], A[r][c], x[c]);
     x[r] = cmul(x[r], dinv[r]);
   }
 }
@@ -162,12 +184,12 @@ __device__ __forceinline__ bool inverse_column(cd (&A)[n][n + 1], int col, cd (&
     }
     if (best == 0.0) ok = false;
     pivprod *= best == 0.0 ? 1.0 : best;
-    pinv[p] = best == 0.0 ? cd{0.0, 0.0} : cinv(A[p][p]);
+    pinv[p] = best == 0.0 ? cd{0.0, 0.0} : nr_cinv(A[p][p]);
 #pragma unroll
     for (int r = p + 1; r < n; ++r) {
       const cd fac = cmul(A[r][p], pinv[p]);
 #pragma unroll
-      for (int c = p + 1; c <= n; ++c) A[r][c] = csub(A[r][c], cmul(fac, A[p][c]));
+      for (int c = p + 1; c <= n; ++c) A[r][c] = cfms(A[r][c], fac, A[p][c]);
     }
   }
   logabs = 0.5 * log(pivprod);
@@ -175,7 +197,7 @@ __device__ __forceinline__ bool inverse_column(cd (&A)[n][n + 1], int col, cd (&
   for (int r = n - 1; r >= 0; --r) {
     cd acc = A[r][n];
 #pragma unroll
-    for (int c = r + 1; c < n; ++c) acc = csub(acc, cmul(A[r][c], x[c]));
+    for (int c = r + 1; c < n; ++c) acc = cfms(acc, A[r][c], x[c]);
     x[r] = cmul(acc, pinv[r]);
   }
   return ok;
@@ -265,8 +287,8 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
       hpd_solve<ML>(V, vdinv, dv);
       cd dc = {0.0, 0.0};  // d^H c = d^H V d
 #pragma unroll
-      for (int k = 0; k < ML; ++k) dc = cadd(dc, cmul(cconj(dv[k]), ci[k]));
-      const double sc = 1.0 / sqrt(dc.re > d.eps ? dc.re : d.eps);
+      for (int k = 0; k < ML; ++k) dc = cfmac(dc, dv[k], ci[k]);
+      const double sc = nr_rsqrt(dc.re > d.eps ? dc.re : d.eps);
 #pragma unroll
       for (int k = 0; k < ML; ++k) {
         const cd b = {dv[k].re * sc, dv[k].im * sc};
@@ -282,11 +304,11 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
     if (sOk[blk]) {
       cd bq = {r == mu ? -1.0 : 0.0, 0.0};  // b^H Q^{-1}[:, r] - delta_{mu r}
 #pragma unroll
-      for (int k = 0; k < ML; ++k) bq = cadd(bq, cmul(cconj(sB[blk][k]), ci[k]));
+      for (int k = 0; k < ML; ++k) bq = cfmac(bq, sB[blk][k], ci[k]);
       const cd w = sW[blk];
-      const cd fac = cmul(bq, cinv(w));
+      const cd fac = cmul(bq, nr_cinv(w));
 #pragma unroll
-      for (int k = 0; k < ML; ++k) ci[k] = csub(ci[k], cmul(sC[blk][k], fac));
+      for (int k = 0; k < ML; ++k) ci[k] = cfms(ci[k], sC[blk][k], fac);
       wprod *= cabs2(w);
     }
     __syncthreads();
