@@ -613,7 +613,7 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
     for (int o = 0; o < NO; ++o) acc[o] = 0.0;
 
     for (int t0 = ts + j; t0 < te; t0 += FB * kGDL) {
-      if (t0 + FB * kGDL < te) fetch(t0 + FB * kGDL, xn, ln);
+      fetch(t0 + FB * kGDL, xn, ln);  // unconditional (clamped to the segment), so the waits count it
       sched_fence();
 #pragma unroll
       for (int u = 0; u < FB; ++u) {
