@@ -78,6 +78,9 @@ STAGE_CASES = [
     # the bin-split H update.
     (200, 37, (4, 4, 4), 3, 16),
     (620, 21, (4, 4, 4), 3, 16),
+    # H[n] over more than one LDS window in the W update (k_wgemm_f walks the windows; FP64 above
+    # 224 frames, FP32 above 736).
+    (5, 800, (4, 4, 4, 4), 5, 16),
     (33, 130, (2, 2), 2, 4),
     # Fewer frames per bin than a g-update workgroup's range: ranges span up to six bins.
     (23, 9, (4, 4, 4, 4), 5, 16),
