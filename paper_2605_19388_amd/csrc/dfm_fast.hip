@@ -494,22 +494,6 @@ __global__ __launch_bounds__(kT) void k_gram_f(Dims d, const cx<RI>* __restrict_
   }
 }
 
-// ------------------------------------------------------------------------------------
-// Weighted covariances (eq. (14)) for subarrays of M_l <= 4 mics, FP32 inputs, FP64 sums.
-// As many workgroups as fit on the chip at once share the flattened (f, t) frames equally,
-// so every SIMD gets the same work; kGDL lanes per subarray: lane j takes frames j, j + kGDL,
-// ... of each bin segment of the workgroup's share.  Per frame it forms 1/y for the
-// subarray's mics (FP32), the packed entries of x^(l) x^(l)H in FP64 (exact: products of
-// FP32 values) and adds (1/y_mu) x x^H into M_l x M_l^2 FP64 registers; the lanes' sums are
-// then added through LDS in a fixed order, one slot per (bin, workgroup).  FP32 sums over
-// frames would leave rounding errors outside the dominant directions of V, which the solve
-// of eq. (15) amplifies by cond(V) -- large at the lowest bins, where the mixing is nearly
-// rank-deficient; FP64 sums keep the solve's input at the precision of the FP64 reference.
-// Output: V[f][slot][packed entries], FP64, /T not applied.
-constexpr int kGDL = 32;  // lanes per subarray
-
-constexpr int kGDH = 1;   // lanes per frame (each sums ML / kGDH of the rows mu)
-
 // g <- g sqrt(num / max(den, eps)) of eq. (10) for one (f, n, m): num and den are the sums of
 // the bin's `need` partials of k_g_f (stride 2 N M, den at offset N M), added in slot order with
 // four slots' loads in flight at a time.  Every kernel that finishes the g update calls this, so
@@ -539,6 +523,21 @@ __device__ __forceinline__ R g_updated(const R* __restrict__ part, int need, int
 __device__ __forceinline__ int g_slots(const Dims& d, int f) {
   return (f * d.T + d.T - 1) / d.GGR - (f * d.T) / d.GGR + 1;
 }
+
+// ------------------------------------------------------------------------------------
+// Weighted covariances (eq. (14)) for subarrays of M_l <= 4 mics, FP32 inputs, FP64 sums.
+// As many workgroups as fit on the chip at once share the flattened (f, t) frames equally,
+// so every SIMD gets the same work; kGDL lanes per subarray: lane j takes frames j, j + kGDL,
+// ... of each bin segment of the workgroup's share.  Per frame it forms 1/y for the
+// subarray's mics (FP32), the packed entries of x^(l) x^(l)H in FP64 (exact: products of
+// FP32 values) and adds (1/y_mu) x x^H into M_l x M_l^2 FP64 registers; the lanes' sums are
+// then added through LDS in a fixed order, one slot per (bin, workgroup).  FP32 sums over
+// frames would leave rounding errors outside the dominant directions of V, which the solve
+// of eq. (15) amplifies by cond(V) -- large at the lowest bins, where the mixing is nearly
+// rank-deficient; FP64 sums keep the solve's input at the precision of the FP64 reference.
+// Output: V[f][slot][packed entries], FP64, /T not applied.
+constexpr int kGDL = 32;  // lanes per subarray
+constexpr int kGDH = 1;   // lanes per frame (each sums ML / kGDH of the rows mu)
 
 template <int L>
 constexpr int gramd_threads() {
@@ -1428,14 +1427,16 @@ __global__ __launch_bounds__(64 * kGW) void k_hlam_f(Dims d, const R* __restrict
 // Diagonal SCM update, eq. (10): num/den[n][m] = sum_t lambda_n (P_m / y_m^2, 1 / y_m) over
 // every frame, then g <- g sqrt(num / max(den, eps)).  The F*T frames are dealt out in equal
 // contiguous ranges of Dims::GGR to Dims::GGW workgroups (a range may run into the next bins).
-// A lane owns one mic of one frame per step (64 / M frames per wave), keeps the 2N sums of its
-// mic in registers, and loads the next batch of P and lambda while it computes the current one.
-// A workgroup adds its lanes' sums in a fixed order through LDS into one partial per bin it
-// touched (slot = its rank among the bin's workgroups).  The g update itself (each bin's partials
-// added in slot order) is finished by k_gfin_f or, inside a run of iterations, by the next
-// iteration's k_gramd_f, which applies it to the copy of g kept here.  (Finishing a bin in the last workgroup to reach it would need a
-// device-scope fence per workgroup, which on this chip writes back and invalidates the L2 of
-// the workgroup's XCD; that made the kernel ten times slower.)
+// A lane owns one mic of one frame per step (64 / M frames per wave) and keeps the 2N sums of
+// its mic in registers; the source asks for the next batch's P and lambda before the current
+// batch's arithmetic (the compiler keeps the P loads a batch ahead and moves the lambda loads to
+// their batch).  A workgroup adds its lanes' sums in a fixed order through LDS into one partial
+// per bin it touched (slot = its rank among the bin's workgroups).  The g update itself (each
+// bin's partials added in slot order) is finished by k_gfin_f or, inside a run of iterations,
+// by the next iteration's k_gramd_f, which applies it to the copy of g kept here.  (Finishing a
+// bin in the last workgroup to reach it would need a device-scope fence per workgroup, which on
+// this chip writes back and invalidates the L2 of the workgroup's XCD; that made the kernel ten
+// times slower.)
 constexpr int kGT = 256;  // threads of a g-update workgroup
 constexpr int kGU = 2;    // steps per batch of loads
 
@@ -1642,6 +1643,7 @@ __global__ __launch_bounds__(kT) void k_sep_f(Dims d, const cx<R>* __restrict__ 
   const int T = d.T, t0 = s * d.SL, nt = min(d.SL, T - t0);
   __shared__ cx<R> sQ[QF], sQi[QF];
   __shared__ R sg[N * M];
+  __shared__ __align__(16) unsigned char sOraw[sizeof(R) * kT * (2 * M + V16<R>::E)];  // output rows
   R xv[2 * M], lam[N];
   const bool live = tid < nt;
   if (live) {
@@ -1657,47 +1659,73 @@ __global__ __launch_bounds__(kT) void k_sep_f(Dims d, const cx<R>* __restrict__ 
   for (int i = tid; i < N * M; i += kT) sg[i] = g[(size_t)f * N * M + i];
   sched_fence();
   __syncthreads();
-  if (!live) return;
-  const int t = t0 + tid;
+  // Q x and 1/y of this frame, every mic.
+  R zr[M], zi[M], iy[M];
+  if (live) {
 #pragma unroll
-  for (int l = 0; l < L; ++l) {
-    R zr[ML], zi[ML], iy[ML];
+    for (int l = 0; l < L; ++l)
 #pragma unroll
-    for (int mu = 0; mu < ML; ++mu) {
-      R ar = 0, ai = 0;
+      for (int mu = 0; mu < ML; ++mu) {
+        R ar = 0, ai = 0;
 #pragma unroll
-      for (int c = 0; c < ML; ++c) {
-        const cx<R> q = sQ[l * ML2 + mu * ML + c];
-        const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
-        ar += q.re * xr - q.im * xi;
-        ai += q.re * xi + q.im * xr;
-      }
-      zr[mu] = ar;
-      zi[mu] = ai;
-      R y = 0;
-#pragma unroll
-      for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + l * ML + mu];
-      iy[mu] = (R)1 / rmax(y, (R)d.eps);
-    }
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-      R out[2 * ML];
-#pragma unroll
-      for (int a = 0; a < ML; ++a) {
-        R vr = 0, vi = 0;
-#pragma unroll
-        for (int mu = 0; mu < ML; ++mu) {
-          const R gain = lam[n] * sg[n * M + l * ML + mu] * iy[mu];
-          const cx<R> q = sQi[l * ML2 + a * ML + mu];
-          const R ur = gain * zr[mu], ui = gain * zi[mu];
-          vr += q.re * ur - q.im * ui;
-          vi += q.re * ui + q.im * ur;
+        for (int c = 0; c < ML; ++c) {
+          const cx<R> q = sQ[l * ML2 + mu * ML + c];
+          const R xr = xv[2 * (l * ML + c)], xi = xv[2 * (l * ML + c) + 1];
+          ar += q.re * xr - q.im * xi;
+          ai += q.re * xi + q.im * xr;
         }
-        out[2 * a] = vr;
-        out[2 * a + 1] = vi;
+        const int m = l * ML + mu;
+        zr[m] = ar;
+        zi[m] = ai;
+        R y = 0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) y += lam[n] * sg[n * M + m];
+        iy[m] = (R)1 / rmax(y, (R)d.eps);
       }
-      store16<R, 2 * ML>(reinterpret_cast<R*>(S + (((size_t)n * d.F + f) * T + t) * M + l * ML), out);
+  }
+  // Per source: the frame's row of M complex outputs goes to LDS, then the workgroup stores
+  // its frames' rows, contiguous in S, as whole 16-byte-per-lane runs (per-frame stores at the
+  // row stride would reach L2 as one partial-line request per lane).
+  typedef typename V16<R>::type vt;
+  constexpr int E = V16<R>::E, RW = 2 * M, OS = RW + E;  // row length and padded LDS stride (reals)
+  R* sO = reinterpret_cast<R*>(sOraw);
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    if (live) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        R out[2 * ML];
+#pragma unroll
+        for (int a = 0; a < ML; ++a) {
+          R vr = 0, vi = 0;
+#pragma unroll
+          for (int mu = 0; mu < ML; ++mu) {
+            const int m = l * ML + mu;
+            const R gain = lam[n] * sg[n * M + m] * iy[m];
+            const cx<R> q = sQi[l * ML2 + a * ML + mu];
+            const R ur = gain * zr[m], ui = gain * zi[m];
+            vr += q.re * ur - q.im * ui;
+            vi += q.re * ui + q.im * ur;
+          }
+          out[2 * a] = vr;
+          out[2 * a + 1] = vi;
+        }
+#pragma unroll
+        for (int i = 0; i < 2 * ML / E; ++i) {
+          vt v;
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e] = out[i * E + e];
+          *reinterpret_cast<vt*>(sO + tid * OS + l * 2 * ML + i * E) = v;
+        }
+      }
     }
+    __syncthreads();
+    R* dst = reinterpret_cast<R*>(S + (((size_t)n * d.F + f) * T + t0) * M);
+    for (int c = tid; c < nt * (RW / E); c += kT) {
+      const int fr = c / (RW / E), part = c - fr * (RW / E);
+      *reinterpret_cast<vt*>(dst + (size_t)c * E) = *reinterpret_cast<const vt*>(sO + fr * OS + part * E);
+    }
+    __syncthreads();
   }
 }
 
