@@ -223,28 +223,36 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
   R qv[2 * ML2], qr[2 * ML];  // interleaved (re, im)
   load16<R, 2 * ML2>(qv, reinterpret_cast<const R*>(qb));
   load16<R, 2 * ML>(qr, reinterpret_cast<const R*>(qb + r * ML));  // r is not a compile-time index
+  // This lane's covariance slots (V_r packed, FP64), in flight while Q^{-1} is formed below.
+  const double* vp = Vpart + (size_t)f * d.SG * d.VF + (size_t)l * ML * ML2 + r * ML2;
+  const int ns = cov_slots(d, f);
+  constexpr int SU = 3;  // slots loaded together (the covariance kernel's grid touches at most 3)
+  double part[SU][ML2];
+#pragma unroll
+  for (int s = 0; s < SU; ++s) load16<double, ML2>(part[s], vp + (size_t)(s < ns ? s : 0) * d.VF);
+  sched_fence();  // every load above in flight before the first use
 
+  // Column r of Q_fl^{-1} and ln|det Q_fl| (every sweep from Q itself, so a run resumed from
+  // the state is bitwise identical to an uninterrupted one).
+  cd A[ML][ML + 1], row[ML], ci[ML];
+#pragma unroll
+  for (int a = 0; a < ML; ++a)
+#pragma unroll
+    for (int c = 0; c < ML; ++c) A[a][c] = {(double)qv[2 * (a * ML + c)], (double)qv[2 * (a * ML + c) + 1]};
+#pragma unroll
+  for (int c = 0; c < ML; ++c) row[c] = {(double)qr[2 * c], (double)qr[2 * c + 1]};
+  double ld;
+  const bool qok = inverse_column<ML>(A, r, ci, ld);
   // V_r = (sum over slices) / T, Hermitian from its packed entries.
   cd V[ML][ML];
   {
     double vs[ML2];
 #pragma unroll
     for (int j = 0; j < ML2; ++j) vs[j] = 0.0;
-    const double* vp = Vpart + (size_t)f * d.SG * d.VF + (size_t)l * ML * ML2 + r * ML2;
-    const int ns = cov_slots(d, f);
-    constexpr int SU = 3;  // slots loaded together (the covariance kernel's grid touches at most 3)
-    double part[SU][ML2];
-#pragma unroll
-    for (int s = 0; s < SU; ++s) {
-      load16<double, ML2>(part[s], vp + (size_t)(s < ns ? s : 0) * d.VF);
-#pragma unroll
-      for (int j = 0; j < ML2; ++j) part[s][j] = s < ns ? part[s][j] : 0.0;
-    }
-    sched_fence();  // every load above in flight before the first use
 #pragma unroll
     for (int s = 0; s < SU; ++s)
 #pragma unroll
-      for (int j = 0; j < ML2; ++j) vs[j] += part[s][j];
+      for (int j = 0; j < ML2; ++j) vs[j] += s < ns ? part[s][j] : 0.0;
     for (int s = SU; s < ns; ++s)
 #pragma unroll
       for (int j = 0; j < ML2; ++j) vs[j] += vp[(size_t)s * d.VF + j];
@@ -264,17 +272,6 @@ __global__ __launch_bounds__(64) void k_ip_f(Dims d, const double* __restrict__ 
   cd vdinv[ML];
   const bool vok = hpd_factor<ML>(V, vdinv);
 
-  // Column r of Q_fl^{-1} and ln|det Q_fl| (every sweep from Q itself, so a run resumed from
-  // the state is bitwise identical to an uninterrupted one).
-  cd A[ML][ML + 1], row[ML], ci[ML];
-#pragma unroll
-  for (int a = 0; a < ML; ++a)
-#pragma unroll
-    for (int c = 0; c < ML; ++c) A[a][c] = {(double)qv[2 * (a * ML + c)], (double)qv[2 * (a * ML + c) + 1]};
-#pragma unroll
-  for (int c = 0; c < ML; ++c) row[c] = {(double)qr[2 * c], (double)qr[2 * c + 1]};
-  double ld;
-  const bool qok = inverse_column<ML>(A, r, ci, ld);
   double wprod = 1.0;
 
 #pragma unroll
