@@ -1169,21 +1169,7 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
   const R* wn = W + (size_t)n * F * K;
   const bool tok = t0 + i < T;
 
-  // Window [f0, f0 + nf) of W[n] -> sW, flat over (bin, basis); every load is issued before
-  // the first LDS write.
-  auto stage = [&](int f0, int nf) {
-    R v[G::WNE];
-#pragma unroll
-    for (int q = 0; q < G::WNE; ++q) {
-      const int e = tid + q * 64 * kGW, fl = e / KP, k = e - fl * KP, f = f0 + fl;
-      v[q] = (fl < nf && f < F && k < K) ? wn[(size_t)f * K + k] : (R)0;
-    }
-#pragma unroll
-    for (int q = 0; q < G::WNE; ++q) {
-      const int e = tid + q * 64 * kGW, fl = e / KP, k = e - fl * KP;
-      if (fl < nf) sW[fl * WS + k] = v[q];
-    }
-  };
+  auto stage = [&](int f0, int nf) { stage_w<R, K>(sW, wn, F, f0, nf, tid); };
 
   v4 accN[KT], accD[KT];
 #pragma unroll
