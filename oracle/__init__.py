@@ -11,8 +11,10 @@ does, and has no CPU fallback.
 * ``oracle.fullcov``      -- brute force from the full covariance of eq. (1) and
   the appendix theorem's commutator test.
 
-Every function is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_pins.py``
+Every function is pinned by ``-m "not gpu"`` tests: ``tests/test_oracle_pins.py``
 (brute force, closed forms, special cases, finite-difference identities,
-monotonicity); none is "parity unpinned".
+monotonicity) and ``tests/test_oracle_floors.py`` (the 1e-6 floors of Sec. IV-A
+with each floor active).  ``tests/test_oracle_mutations.py`` plants mistakes in a
+copy of ``dfmnmf.py`` and checks that each one fails a pin.
 """
 from . import conventional, dfmnmf, fullcov  # noqa: F401
