@@ -41,7 +41,7 @@ extern "C" {
 
 #define DFM_MAX_SUBARRAYS 64   /* L <= 64 */
 #define DFM_MAX_MICS 64        /* M = sum_l M_l <= 64 */
-#define DFM_MAX_SUBARRAY_MICS 16 /* M_l <= 16 */
+#define DFM_MAX_SUBARRAY_MICS 32 /* M_l <= 32 */
 #define DFM_MAX_SOURCES 16     /* N <= 16 */
 #define DFM_MAX_BASES 64       /* K <= 64 */
 
@@ -60,6 +60,17 @@ typedef enum {
   DFM_E_SINGULAR = 6    /* an IP system (Q_fl V_flmu) had a zero pivot */
 } dfm_status;
 
+/* Bits of dfm_problem.flags. */
+#define DFM_F_CHECK_FINITE 1u  /* check every updated W, H, g for NaN/Inf on the device; a
+                                  non-finite value sets DFM_E_NONFINITE in the sticky status */
+#define DFM_F_TRACE_NLL 2u     /* evaluate the cost (13) after every iteration of dfm_step on
+                                  the device into a trace read by dfm_nll_trace (costs one extra
+                                  pass over X per iteration) */
+#define DFM_F_NO_GRAPH 8u      /* dfm_step issues plain kernel launches instead of replaying
+                                  HIP graphs of its iterations (same kernels, same results) */
+#define DFM_TRACE_CAPACITY 4096 /* entries of the cost trace; later iterations are counted
+                                   but not stored */
+
 /* Sub-steps of one iteration, for dfm_substep (in this order). */
 typedef enum {
   DFM_STAGE_IP = 0,  /* V by eq. (14) from the current W,H,g; IP sweep, eqs. (15)-(16) */
@@ -74,12 +85,12 @@ typedef struct {
   int32_t N;                        /* sources, 1..DFM_MAX_SOURCES */
   int32_t K;                        /* NMF bases per source, 1..DFM_MAX_BASES */
   int32_t L;                        /* subarrays, 1..DFM_MAX_SUBARRAYS */
-  int32_t mics[DFM_MAX_SUBARRAYS];  /* M_l in 1..DFM_MAX_SUBARRAY_MICS; subarray l
+  int32_t mics[DFM_MAX_SUBARRAYS];  /* M_l in 1..DFM_MAX_SUBARRAY_MICS (sum <= DFM_MAX_MICS); subarray l
                                        owns X columns o_l .. o_l+M_l-1, o_l = sum_{l'<l} M_l' */
   int32_t dtype;                    /* dfm_dtype */
   double eps;                       /* floor on the model variance, the MM denominators
                                        and the IP normaliser (1e-6 in Sec. IV-A); > 0 */
-  uint32_t flags;                   /* reserved, must be 0 */
+  uint32_t flags;                   /* DFM_F_* bits; unknown bits are DFM_E_ARG */
 } dfm_problem;
 
 typedef struct dfm_plan dfm_plan;   /* opaque host-side handle */
@@ -104,7 +115,12 @@ dfm_status dfm_init(dfm_plan** out, const dfm_problem* p,
                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* Run n_iter >= 0 full iterations (IP sweep, then eqs. (8), (9), (10)),
- * updating Q, g, W, H in place.  Asynchronous. */
+ * updating Q, g, W, H in place.  Asynchronous.  Unless DFM_F_NO_GRAPH is set,
+ * the kernels of one iteration (and of a batch of eight) are captured once per
+ * plan, on a stream the plan owns, into HIP graphs that are then replayed on
+ * `stream`; the plan's buffers are fixed, so a replay runs exactly the kernels
+ * and arguments of a plain launch.  While dfm_profile_kernel is active the
+ * launches are plain. */
 dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream);
 
 /* Run one sub-step of an iteration (dfm_stage).  Asynchronous.  A full
@@ -113,10 +129,17 @@ dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream);
 dfm_status dfm_substep(dfm_plan* plan, int32_t stage, void* stream);
 
 /* Cost (13) of the current state: sum_{f,t,m} (|Q x|^2 / y + ln y)
- * - 2T sum_{f,l} ln|det Q_fl|, terms in the plan's precision and the sum
- * in FP64.  Synchronises `stream`; *out is a host pointer.  Also returns
- * any sticky device error. */
+ * - 2T sum_{f,l} ln|det Q_fl|, terms in the plan's precision, the sums and
+ * the total in FP64 on the device (fixed order); only the 8-byte total is
+ * copied to the host.  Synchronises `stream`; *out is a host pointer.  Also
+ * returns any sticky device error. */
 dfm_status dfm_nll(dfm_plan* plan, double* out, void* stream);
+
+/* With DFM_F_TRACE_NLL: copy the costs (13) recorded after each iteration of
+ * dfm_step since dfm_init (the first min(count, capacity, DFM_TRACE_CAPACITY)
+ * of them) to the host array out[capacity], and the number of iterations
+ * recorded to *count.  Synchronises `stream`.  DFM_E_ARG without the flag. */
+dfm_status dfm_nll_trace(dfm_plan* plan, double* out, int32_t capacity, int32_t* count, void* stream);
 
 /* Source images at every subarray by the multichannel Wiener filter
  * (Sec. III-B, last paragraph): for each subarray l,

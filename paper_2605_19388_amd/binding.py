@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(HERE, "libdfmnmf.so")
 
 MAX_SUBARRAYS = 64
 DFM_C64, DFM_C128 = 0, 1
+# dfm_problem.flags bits
+F_CHECK_FINITE, F_TRACE_NLL, F_NO_GRAPH = 1, 2, 8
+TRACE_CAPACITY = 4096
 STAGES = {"ip": 0, "W": 1, "H": 2, "g": 3}
 STATUS = {0: "DFM_OK", 1: "DFM_E_ARG", 2: "DFM_E_SHAPE", 3: "DFM_E_WORKSPACE", 4: "DFM_E_HIP",
           5: "DFM_E_NONFINITE", 6: "DFM_E_SINGULAR"}
@@ -39,7 +42,7 @@ class Problem(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ("dfm_workspace_size", "dfm_init", "dfm_step", "dfm_substep", "dfm_nll", "dfm_separate",
+EXPORTS = ("dfm_workspace_size", "dfm_init", "dfm_step", "dfm_substep", "dfm_nll", "dfm_nll_trace", "dfm_separate",
            "dfm_covariances", "dfm_sync_status", "dfm_kernel_times", "dfm_profile_kernel", "dfm_profile_read",
            "dfm_kernel_count", "dfm_kernel_name", "dfm_destroy", "dfm_status_string")
 
@@ -59,6 +62,7 @@ def load(path: str = LIB_PATH):
     lib.dfm_step.argtypes = [vp, i32, vp]
     lib.dfm_substep.argtypes = [vp, i32, vp]
     lib.dfm_nll.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.dfm_nll_trace.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32), vp]
     lib.dfm_separate.argtypes = [vp, vp, vp]
     lib.dfm_covariances.argtypes = [vp, vp, vp]
     lib.dfm_sync_status.argtypes = [vp, vp]
@@ -110,6 +114,22 @@ def _check(st, where):
         raise DFMError(st, where)
 
 
+def check_output(out, shape, dtype, device):
+    """A caller-supplied output tensor must be exactly what the kernel writes: the kernels
+    store every element of `shape` from out.data_ptr() on, with no bounds of their own."""
+    import torch
+    if not isinstance(out, torch.Tensor):
+        raise DFMError(1, "out must be a torch tensor")
+    if tuple(out.shape) != tuple(shape):
+        raise DFMError(1, f"out has shape {tuple(out.shape)}, expected {tuple(shape)}")
+    if out.dtype != dtype:
+        raise DFMError(1, f"out has dtype {out.dtype}, expected {dtype}")
+    if out.device != torch.device(device):
+        raise DFMError(1, f"out is on {out.device}, expected {device}")
+    if not out.is_contiguous():
+        raise DFMError(1, "out must be contiguous")
+
+
 class DistributedFastMNMF:
     """Distributed FastMNMF plan on one GPU.
 
@@ -120,7 +140,7 @@ class DistributedFastMNMF:
     tensors owned by this object and is updated in place by ``step``.
     """
 
-    def __init__(self, X, mics, n_src, n_basis, W, H, Q=None, g=None, eps=1e-6, device="cuda"):
+    def __init__(self, X, mics, n_src, n_basis, W, H, Q=None, g=None, eps=1e-6, device="cuda", flags=0):
         import torch
 
         self._torch = torch
@@ -157,13 +177,13 @@ class DistributedFastMNMF:
                              ("W", self.W, (self.N, F, self.K)), ("H", self.H, (self.N, self.K, T))):
             if tuple(t.shape) != shp:
                 raise DFMError(2, f"{name} has shape {tuple(t.shape)}, expected {shp}")
-        self.problem = make_problem(F, T, self.mics, self.N, self.K, self.dtype, eps)
+        self.problem = make_problem(F, T, self.mics, self.N, self.K, self.dtype, eps, flags)
         nbytes = workspace_size(self.problem)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         off = (-self._ws.data_ptr()) % 256
         self._ws_ptr = self._ws.data_ptr() + off
         self._ws_bytes = nbytes
-        self.device = dev
+        self.device = self.X.device  # with its index (cuda:0), for comparisons
         self._plan = ctypes.c_void_p()
         st = lib_.dfm_init(ctypes.byref(self._plan), ctypes.byref(self.problem),
                            self.X.data_ptr(), self.Q.data_ptr(), self.g.data_ptr(), self.W.data_ptr(),
@@ -187,10 +207,21 @@ class DistributedFastMNMF:
         _check(load().dfm_nll(self._plan, ctypes.byref(out), self._stream()), "dfm_nll")
         return float(out.value)
 
+    def nll_trace(self):
+        """Costs (13) recorded after each iteration of step() (plan made with F_TRACE_NLL)."""
+        buf = (ctypes.c_double * TRACE_CAPACITY)()
+        n = ctypes.c_int32(0)
+        _check(load().dfm_nll_trace(self._plan, buf, TRACE_CAPACITY, ctypes.byref(n), self._stream()),
+               "dfm_nll_trace")
+        return np.array(buf[:min(n.value, TRACE_CAPACITY)]), int(n.value)
+
     def separate(self, out=None):
         torch = self._torch
+        shape = (self.N, self.F, self.T, self.M)
         if out is None:
-            out = torch.empty((self.N, self.F, self.T, self.M), dtype=self.X.dtype, device=self.device)
+            out = torch.empty(shape, dtype=self.X.dtype, device=self.device)
+        else:
+            check_output(out, shape, self.X.dtype, self.device)
         _check(load().dfm_separate(self._plan, out.data_ptr(), self._stream()), "dfm_separate")
         return out
 

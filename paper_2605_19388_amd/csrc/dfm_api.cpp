@@ -22,6 +22,11 @@ struct dfm_plan {
   int prof_kid = -1;
   std::vector<hipEvent_t> prof_events;  // pairs (start, stop)
   size_t prof_used = 0;
+  // HIP graphs of dfm_step's iterations, captured on first use on the plan's own stream:
+  // [0] the first iteration of a call, [1] a later one, [2] kGraphBatch later ones.
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  bool graph_off = false;  // DFM_F_NO_GRAPH, or a capture failed (plain launches from then on)
 };
 
 namespace dfm {
@@ -117,7 +122,8 @@ static void choose_tiles(Dims& d, int dtype) {
 static dfm_status make_dims(const dfm_problem* p, Dims& d) {
   if (!p) return DFM_E_ARG;
   if (p->dtype != DFM_C64 && p->dtype != DFM_C128) return DFM_E_ARG;
-  if (!(p->eps > 0.0) || !std::isfinite(p->eps) || p->flags != 0) return DFM_E_ARG;
+  constexpr uint32_t known = DFM_F_CHECK_FINITE | DFM_F_TRACE_NLL | DFM_F_NO_GRAPH;
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps) || (p->flags & ~known) != 0) return DFM_E_ARG;
   if (p->F < 1 || p->T < 1 || p->N < 1 || p->N > kMaxN || p->K < 1 || p->K > kMaxK || p->L < 1 || p->L > kMaxL)
     return DFM_E_SHAPE;
   std::memset(&d, 0, sizeof(d));
@@ -127,6 +133,8 @@ static dfm_status make_dims(const dfm_problem* p, Dims& d) {
   d.K = p->K;
   d.L = p->L;
   d.eps = p->eps;
+  d.flags = (int)p->flags;
+  d.check = (p->flags & DFM_F_CHECK_FINITE) != 0;
   int m = 0, q = 0, v = 0;
   for (int l = 0; l < p->L; ++l) {
     const int ml = p->mics[l];
@@ -168,6 +176,8 @@ size_t workspace_bytes(const Dims& d, int dtype) {
   n += al(8 * d.F * d.S);                              // nllpart
   n += al(16 * d.F * d.QF);                            // Qinv
   n += al(64);                                         // status
+  n += al(8);                                          // cost total
+  n += al(d.flags & DFM_F_TRACE_NLL ? 8 * DFM_TRACE_CAPACITY : 0);  // cost trace
   n += al(fast ? r * d.F * d.T * d.N : 0);             // lambda
   n += al(fast ? r * 2 * d.N * (size_t)d.F * d.TP : 0);  // coefficient planes [2N][TBN][F][16]
   return n;
@@ -194,6 +204,8 @@ void carve(const Dims& d, int dtype, char* ws, Buffers& b) {
   b.nllpart = reinterpret_cast<double*>(take(8 * d.F * d.S));
   b.Qinv = take(16 * d.F * d.QF);
   b.status = reinterpret_cast<int*>(take(64));
+  b.nlltot = reinterpret_cast<double*>(take(8));
+  b.trace = d.flags & DFM_F_TRACE_NLL ? reinterpret_cast<double*>(take(8 * DFM_TRACE_CAPACITY)) : nullptr;
   b.lam = fast ? take(r * d.F * d.T * d.N) : nullptr;
   b.AB = fast ? take(r * 2 * d.N * (size_t)d.F * d.TP) : nullptr;
 }
@@ -220,6 +232,67 @@ static hipError_t run_stage(dfm_plan* plan, int stage, hipStream_t s) {
   return hipSuccess;
 }
 
+// Kernels of one dfm_step iteration on stream s.  `first`: no g update is pending from a
+// previous iteration of the same call.  With the cost trace, every iteration finishes its own g
+// update and records the cost (13) of the new state.
+static hipError_t enqueue_iteration(dfm_plan* plan, bool first, hipStream_t s) {
+  Dims& d = plan->d;
+  const bool trace = (d.flags & DFM_F_TRACE_NLL) != 0;
+  d.gpend = g_update_deferred(d) && !trace && !first;
+  hipError_t e = hipSuccess;
+  for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G && e == hipSuccess; ++stage) e = run_stage(plan, stage, s);
+  d.gpend = 0;
+  if (e == hipSuccess && trace) {
+    if (g_update_deferred(d)) e = run_kernel(plan, kFGFin, s);
+    if (e == hipSuccess) e = launch_nll(d, plan->b, plan->dtype, s);
+    if (e == hipSuccess) e = launch_nll_total(d, plan->b, plan->b.nlltot, true, s);
+  }
+  return e;
+}
+
+constexpr int kGraphBatch = 8;  // iterations in the batch graph
+
+// Capture graph `which` (0: first iteration, 1: a later iteration, 2: kGraphBatch later ones)
+// on the plan's own stream.  Only kernel launches are recorded (no memset or copy nodes).
+static hipError_t capture_graph(dfm_plan* plan, int which) {
+  if (!plan->cap && hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking) != hipSuccess) return hipErrorUnknown;
+  hipError_t e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const int reps = which == 2 ? kGraphBatch : 1;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = enqueue_iteration(plan, which == 0, plan->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(plan->cap, &g);
+  if (e == hipSuccess) e = ee;
+  if (e == hipSuccess && g) e = hipGraphInstantiate(&plan->graph[which], g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) plan->graph[which] = nullptr;
+  return e;
+}
+
+static void free_graphs(dfm_plan* plan) {
+  for (hipGraphExec_t& g : plan->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  if (plan->cap) (void)hipStreamDestroy(plan->cap);
+  plan->cap = nullptr;
+}
+
+// Replay graph `which` on s, capturing it first if needed.  False if graphs are off for this plan
+// (then the caller launches plainly); a capture failure turns them off for good.
+static bool replay(dfm_plan* plan, int which, hipStream_t s, hipError_t& e) {
+  if (plan->graph_off) return false;
+  if (!plan->graph[which] && capture_graph(plan, which) != hipSuccess) {
+    (void)hipGetLastError();
+    free_graphs(plan);
+    plan->graph_off = true;
+    return false;
+  }
+  e = hipGraphLaunch(plan->graph[which], s);
+  return true;
+}
+
 static void free_profile(dfm_plan* plan) {
   for (hipEvent_t e : plan->prof_events) (void)hipEventDestroy(e);
   plan->prof_events.clear();
@@ -231,7 +304,7 @@ static dfm_status read_status(dfm_plan* plan, hipStream_t s, bool clear) {
   int st = 0;
   if (hipMemcpyAsync(&st, plan->b.status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return DFM_E_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return DFM_E_HIP;
-  if (clear && st != 0 && launch_init(plan->d, plan->b, s) != hipSuccess) return DFM_E_HIP;
+  if (clear && st != 0 && launch_clear_status(plan->b, s) != hipSuccess) return DFM_E_HIP;
   if (st & kStSingular) return DFM_E_SINGULAR;
   if (st & kStNonFinite) return DFM_E_NONFINITE;
   return DFM_OK;
@@ -264,6 +337,7 @@ dfm_status dfm_init(dfm_plan** out, const dfm_problem* p, const void* X, void* Q
   if (!plan) return DFM_E_ARG;
   plan->d = d;
   plan->dtype = p->dtype;
+  plan->graph_off = (p->flags & DFM_F_NO_GRAPH) != 0;
   std::memset(&plan->b, 0, sizeof(plan->b));
   plan->b.X = X;
   plan->b.Q = Q;
@@ -281,20 +355,29 @@ dfm_status dfm_init(dfm_plan** out, const dfm_problem* p, const void* X, void* Q
 
 dfm_status dfm_step(dfm_plan* plan, int32_t n_iter, void* stream) {
   if (!plan || n_iter < 0) return DFM_E_ARG;
+  if (n_iter == 0) return DFM_OK;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   // The specialised kernels read lambda = W H, which the W and H updates then keep
   // current; seed it from the caller's state.
-  if (n_iter > 0 && plan->d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess) return DFM_E_HIP;
+  if (plan->d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess) return DFM_E_HIP;
   // Where the g update ends in k_g_f's partial sums (dfm::g_update_deferred), the next
   // iteration's covariance kernel finishes it, and k_gfin_f after the last one.
-  const bool defer = dfm::g_update_deferred(plan->d);
   hipError_t e = hipSuccess;
-  for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
-    plan->d.gpend = defer && it > 0;
-    for (int stage = DFM_STAGE_IP; stage <= DFM_STAGE_G && e == hipSuccess; ++stage) e = dfm::run_stage(plan, stage, s);
+  const bool graphs = plan->prof_kid < 0;  // event-profiled launches stay plain
+  int left = n_iter;
+  if (!(graphs && dfm::replay(plan, 0, s, e))) e = dfm::enqueue_iteration(plan, true, s);
+  --left;
+  while (e == hipSuccess && left > 0) {
+    const int which = left >= dfm::kGraphBatch ? 2 : 1;
+    if (graphs && dfm::replay(plan, which, s, e)) {
+      left -= which == 2 ? dfm::kGraphBatch : 1;
+    } else {
+      e = dfm::enqueue_iteration(plan, false, s);
+      --left;
+    }
   }
-  plan->d.gpend = 0;
-  if (e == hipSuccess && defer && n_iter > 0) e = dfm::run_kernel(plan, dfm::kFGFin, s);
+  const bool defer = dfm::g_update_deferred(plan->d) && !(plan->d.flags & DFM_F_TRACE_NLL);
+  if (e == hipSuccess && defer) e = dfm::run_kernel(plan, dfm::kFGFin, s);
   return e == hipSuccess ? DFM_OK : DFM_E_HIP;
 }
 
@@ -314,18 +397,31 @@ dfm_status dfm_nll(dfm_plan* plan, double* out, void* stream) {
   if (!plan || !out) return DFM_E_ARG;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const Dims& d = plan->d;
-  if (dfm::launch_nll(d, plan->b, plan->dtype, s) != hipSuccess) return DFM_E_HIP;
-  std::vector<double> part((size_t)d.F * d.S), ld((size_t)d.F * d.L);
-  if (hipMemcpyAsync(part.data(), plan->b.nllpart, part.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(ld.data(), plan->b.logdet, ld.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+  if (dfm::launch_nll(d, plan->b, plan->dtype, s) != hipSuccess ||
+      dfm::launch_nll_total(d, plan->b, plan->b.nlltot, false, s) != hipSuccess)
     return DFM_E_HIP;
-  const dfm_status st = dfm::read_status(plan, s, false);
+  double v = 0.0;
+  if (hipMemcpyAsync(&v, plan->b.nlltot, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return DFM_E_HIP;
+  const dfm_status st = dfm::read_status(plan, s, false);  // synchronises s
   if (st == DFM_E_HIP) return st;
-  double data = 0.0, logdet = 0.0;
-  for (double v : part) data += v;
-  for (double v : ld) logdet += v;
-  *out = data - 2.0 * d.T * logdet;
+  *out = v;
   return st;
+}
+
+dfm_status dfm_nll_trace(dfm_plan* plan, double* out, int32_t capacity, int32_t* count, void* stream) {
+  if (!plan || !count || capacity < 0 || (capacity > 0 && !out) || !(plan->d.flags & DFM_F_TRACE_NLL))
+    return DFM_E_ARG;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  int n = 0;
+  if (hipMemcpyAsync(&n, plan->b.status + dfm::kTraceSlot, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DFM_E_HIP;
+  const int k = std::min(std::min(n, (int)capacity), DFM_TRACE_CAPACITY);
+  if (k > 0 && (hipMemcpyAsync(out, plan->b.trace, sizeof(double) * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess))
+    return DFM_E_HIP;
+  *count = n;
+  return DFM_OK;
 }
 
 dfm_status dfm_separate(dfm_plan* plan, void* S, void* stream) {
@@ -428,6 +524,7 @@ dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, v
 void dfm_destroy(dfm_plan* plan) {
   if (!plan) return;
   dfm::free_profile(plan);
+  dfm::free_graphs(plan);
   delete plan;
 }
 

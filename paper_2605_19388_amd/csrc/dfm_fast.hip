@@ -1021,7 +1021,7 @@ __global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restric
       sum_tiles<R, KT>(red, k >> 4, fi, k & 15, num, den);
       const size_t idx = ((size_t)n * F + f) * K + k;
       w = W[idx] * sqrt(num / rmax(den, (R)d.eps));
-      if (!isfinite(w)) atomicOr(status, kStNonFinite);
+      if (d.check && !isfinite(w)) atomicOr(status, kStNonFinite);
       W[idx] = w;
     }
     sWn[e] = w;
@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
       sum_tiles<R, KT>(red, k >> 4, k & 15, tl, num, den);
       const size_t idx = ((size_t)n * K + k) * T + t;
       h = H[idx] * sqrt(num / rmax(den, (R)d.eps));
-      if (!isfinite(h)) atomicOr(status, kStNonFinite);
+      if (d.check && !isfinite(h)) atomicOr(status, kStNonFinite);
       H[idx] = h;
     }
     sHn[e] = h;
@@ -1382,7 +1382,7 @@ __global__ __launch_bounds__(64 * kGW) void k_hlam_f(Dims d, const R* __restrict
       const size_t idx = ((size_t)n * K + k) * T + t;
       h = Hsnap[idx] * sqrt(num / rmax(den, (R)d.eps));
       if (c == 0) {
-        if (!isfinite(h)) atomicOr(status, kStNonFinite);
+        if (d.check && !isfinite(h)) atomicOr(status, kStNonFinite);
         H[idx] = h;
       }
     }
@@ -1526,7 +1526,7 @@ __global__ __launch_bounds__(256) void k_gfin_f(Dims d, const R* __restrict__ gp
   if (i >= d.F * NM) return;
   const int f = i / NM, o = i - f * NM;
   const R v = g_updated<R>(gpart + (size_t)f * d.GGS * 2 * NM + o, g_slots(d, f), NM, g[i], (R)d.eps);
-  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  if (d.check && !isfinite(v)) atomicOr(status, kStNonFinite);
   g[i] = v;
 }
 

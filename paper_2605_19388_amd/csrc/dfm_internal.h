@@ -18,6 +18,7 @@ constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
 // Sticky device status bits (workspace word).
 constexpr int kStSingular = 1;
 constexpr int kStNonFinite = 2;
+constexpr int kTraceSlot = 4;  // int index of the cost-trace counter in the status area
 
 // Problem geometry, passed by value to every kernel.
 struct Dims {
@@ -41,6 +42,8 @@ struct Dims {
   int GGS;   // k_g_f: partial-sum slots per bin
   int HC;    // LDS windows of W[n] in the H update: above 1, k_hsum_f / k_hlam_f replace k_hgemm_f
   int gpend;  // k_gramd_f finishes the previous iteration's g update (set inside dfm_step only)
+  int check;  // DFM_F_CHECK_FINITE: updated W, H, g are checked for NaN / Inf
+  int flags;  // dfm_problem.flags
   int mics[kMaxL];  // M_l
   int moff[kMaxL];  // first mic of subarray l
   int qoff[kMaxL];  // offset of block l in a frequency's packed Q (complex units)
@@ -65,7 +68,9 @@ struct Buffers {
   double* logdet;   // [F][L]
   double* nllpart;  // [F][S]
   void* Qinv;       // [F][QF] complex double
-  int* status;      // sticky status word
+  int* status;      // [0] sticky status word, [kTraceSlot] iterations recorded in the cost trace
+  double* nlltot;   // cost (13) total of the latest dfm_nll
+  double* trace;    // [DFM_TRACE_CAPACITY] costs after each iteration (DFM_F_TRACE_NLL)
   void* lam;           // [F][N][T] real: lambda = W H of the specialised kernels
   void* AB;            // [2N][TBN][F][16] real: per-bin MM coefficients of the specialised kernels
 };
@@ -100,6 +105,10 @@ const char* fast_kernel_name(const Dims& d, int dtype, int kid);  // symbol fami
 // Cost (13) partials or the Wiener filter with the specialised kernels (M_l <= 4).
 hipError_t fast_finish(const Dims& d, const Buffers& b, int dtype, bool separate, void* S, hipStream_t s);
 hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s);
+// Total of the cost (13) from the partials of launch_nll, in a fixed order, to *out; with
+// `trace`, also appended to b.trace at the counter status[kTraceSlot] (then incremented).
+hipError_t launch_nll_total(const Dims& d, const Buffers& b, double* out, bool trace, hipStream_t s);
+hipError_t launch_clear_status(const Buffers& b, hipStream_t s);  // sticky word only
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
 hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);
 

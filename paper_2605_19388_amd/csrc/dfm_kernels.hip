@@ -297,7 +297,7 @@ __global__ void k_wapply(Dims d, R* __restrict__ W, const R* __restrict__ Wpart,
     den += pp[1];
   }
   const R v = W[idx] * sqrt(num / rmax(den, (R)d.eps));
-  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  if (d.check && !isfinite(v)) atomicOr(status, kStNonFinite);
   W[idx] = v;
 }
 
@@ -369,7 +369,7 @@ __global__ void k_happly(Dims d, R* __restrict__ H, const R* __restrict__ Hpart,
     den += pp[1];
   }
   const R v = H[idx] * sqrt(num / rmax(den, (R)d.eps));
-  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  if (d.check && !isfinite(v)) atomicOr(status, kStNonFinite);
   H[idx] = v;
 }
 
@@ -435,7 +435,7 @@ __global__ void k_gapply(Dims d, R* __restrict__ g, const R* __restrict__ gpart,
     den += pp[1];
   }
   const R v = g[idx] * sqrt(num / rmax(den, (R)d.eps));
-  if (!isfinite(v)) atomicOr(status, kStNonFinite);
+  if (d.check && !isfinite(v)) atomicOr(status, kStNonFinite);
   g[idx] = v;
 }
 
@@ -607,6 +607,42 @@ __global__ void k_zero_int(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// Cost (13) = sum of the data-term partials [F][S] - 2T sum of ln|det Q_fl| [F][L], in FP64 by
+// one workgroup in a fixed order (strided lane sums, then a tree over the lanes), so the total
+// is reproducible run to run.  With `trace`, the total is also stored at trace[c], c = *counter
+// (if c is below the trace capacity), and the counter advanced: one launch per recorded
+// iteration, so the index needs no host round trip and the launch can sit in a HIP graph.
+constexpr int kTotThreads = 256;
+__global__ __launch_bounds__(kTotThreads) void k_nll_total(Dims d, const double* __restrict__ nllpart,
+                                                           const double* __restrict__ logdet,
+                                                           double* __restrict__ out, double* __restrict__ trace,
+                                                           int* __restrict__ counter) {
+  __shared__ double sd[kTotThreads], sl[kTotThreads];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int i = tid; i < d.F * d.S; i += kTotThreads) a += nllpart[i];
+  for (int i = tid; i < d.F * d.L; i += kTotThreads) b += logdet[i];
+  sd[tid] = a;
+  sl[tid] = b;
+  __syncthreads();
+  for (int w = kTotThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      sd[tid] += sd[tid + w];
+      sl[tid] += sl[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double tot = sd[0] - 2.0 * d.T * sl[0];
+    *out = tot;
+    if (trace) {
+      const int c = *counter;
+      if (c < DFM_TRACE_CAPACITY) trace[c] = tot;
+      *counter = c + 1;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Host-side launchers.
 template <typename R>
@@ -723,6 +759,17 @@ static hipError_t cov_impl(const Dims& d, const Buffers& b, void* V, hipStream_t
 
 hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.status, 16);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_status(const Buffers& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.status, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_nll_total(const Dims& d, const Buffers& b, double* out, bool trace, hipStream_t s) {
+  hipLaunchKernelGGL(k_nll_total, dim3(1), dim3(kTotThreads), 0, s, d, b.nllpart, b.logdet, out,
+                     trace ? b.trace : nullptr, b.status + kTraceSlot);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 """Helpers for the GPU tests: build plans through the C ABI and compare with the oracle."""
 from __future__ import annotations
 
+import os
 import sys
 
 import numpy as np
@@ -28,13 +29,13 @@ def as_precision(a, fp32: bool):
     return a.astype(np.float32).astype(np.float64)
 
 
-def plan(X, mics, N, K, Q, g, W, H, fp32: bool, eps=1e-6):
+def plan(X, mics, N, K, Q, g, W, H, fp32: bool, eps=1e-6, flags=0):
     from paper_2605_19388_amd import DistributedFastMNMF
     cdt = np.complex64 if fp32 else np.complex128
     rdt = np.float32 if fp32 else np.float64
     return DistributedFastMNMF(np.asarray(X, dtype=cdt), mics, N, K,
                                W=np.asarray(W, dtype=rdt), H=np.asarray(H, dtype=rdt),
-                               Q=np.asarray(Q, dtype=cdt), g=np.asarray(g, dtype=rdt), eps=eps)
+                               Q=np.asarray(Q, dtype=cdt), g=np.asarray(g, dtype=rdt), eps=eps, flags=flags)
 
 
 def rel(a, b):
@@ -48,6 +49,41 @@ def max_rel(a, b, floor=0.0):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor)))
+
+
+def elem_rel(a, b):
+    """Largest elementwise |a-b| / |b| of a positive reference (W, H, g)."""
+    b = np.asarray(b)
+    assert np.all(b > 0)
+    return float(np.max(np.abs(np.asarray(a) - b) / b))
+
+
+def q_block_errors(got, ref, mics):
+    """err[f, l] = max |got - ref| / max |ref| over the entries of block (f, l) of Q [F][sum M_l^2]."""
+    err = np.zeros((got.shape[0], len(mics)))
+    off = 0
+    for l, ml in enumerate(mics):
+        g, r = got[:, off:off + ml * ml], ref[:, off:off + ml * ml]
+        err[:, l] = np.abs(g - r).max(axis=1) / np.abs(r).max(axis=1)
+        off += ml * ml
+    return err
+
+
+def per_bin_errors(got, ref, axes):
+    """max over `axes` of |got - ref| divided by max over `axes` of |ref| (one value per remaining index)."""
+    return np.abs(got - ref).max(axis=axes) / np.abs(ref).max(axis=axes)
+
+
+REPORT_FILE = os.environ.get("DFM_PARITY_REPORT")
+
+
+def report(line: str):
+    """Worst-bin errors and condition numbers of a parity case: to stderr, and appended to the file
+    named by DFM_PARITY_REPORT if set."""
+    print(f"[parity] {line}", file=sys.stderr, flush=True)
+    if REPORT_FILE:
+        with open(REPORT_FILE, "a") as fh:
+            fh.write(line + "\n")
 
 
 def nll_rel(got, ref, F, T, M):

@@ -42,10 +42,10 @@ def test_binding_covers_every_declared_function():
 
 def _problem(**kw):
     from paper_2605_19388_amd import binding
-    args = dict(F=5, T=7, mics=(2, 2), N=2, K=3, dtype=0, eps=1e-6)
+    args = dict(F=5, T=7, mics=(2, 2), N=2, K=3, dtype=0, eps=1e-6, flags=0)
     args.update(kw)
     return binding.make_problem(args["F"], args["T"], args["mics"], args["N"], args["K"],
-                                args["dtype"], args["eps"])
+                                args["dtype"], args["eps"], args["flags"])
 
 
 def _ws(lib, p):
@@ -62,12 +62,43 @@ def test_workspace_size_valid(lib):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(F=0), 2), (dict(T=0), 2), (dict(N=0), 2), (dict(N=17), 2), (dict(K=0), 2), (dict(K=65), 2),
-    (dict(mics=(2, 0)), 2), (dict(mics=(17,)), 2), (dict(mics=(16,) * 5), 2), (dict(mics=()), 2),
-    (dict(dtype=2), 1), (dict(eps=0.0), 1), (dict(eps=-1.0), 1), (dict(eps=float("nan")), 1),
+    (dict(mics=(2, 0)), 2), (dict(mics=(33,)), 2), (dict(mics=(32, 33)), 2), (dict(mics=(16,) * 5), 2),
+    (dict(mics=()), 2), (dict(dtype=2), 1), (dict(eps=0.0), 1), (dict(eps=-1.0), 1), (dict(eps=float("nan")), 1),
+    (dict(flags=4), 1), (dict(flags=16), 1), (dict(flags=1 << 31), 1),
 ])
 def test_workspace_size_rejects(lib, kw, code):
     st, _ = _ws(lib, _problem(**kw))
     assert st == code
+
+
+@pytest.mark.parametrize("kw", [dict(mics=(32,)), dict(mics=(32, 32)), dict(mics=(1,) * 64),
+                                dict(flags=1), dict(flags=2), dict(flags=8), dict(flags=1 | 2 | 8)])
+def test_workspace_size_accepts(lib, kw):
+    st, n = _ws(lib, _problem(**kw))
+    assert st == 0 and n > 0
+
+
+def test_cost_trace_takes_workspace(lib):
+    from paper_2605_19388_amd import binding
+    _, plain = _ws(lib, _problem())
+    _, traced = _ws(lib, _problem(flags=binding.F_TRACE_NLL))
+    assert traced >= plain + 8 * binding.TRACE_CAPACITY
+
+
+def test_separate_output_is_validated_before_any_launch():
+    """A caller's output tensor of the wrong shape, dtype, device or layout is refused on the host
+    (the Wiener-filter kernel writes N*F*T*M entries from its base pointer, unchecked)."""
+    import torch
+    from paper_2605_19388_amd import binding
+    shape, dt, dev = (2, 3, 4, 5), torch.complex64, torch.device("cpu")
+    binding.check_output(torch.empty(shape, dtype=dt), shape, dt, dev)
+    bad = [torch.empty((2, 3, 4, 4), dtype=dt), torch.empty(shape, dtype=torch.complex128),
+           torch.empty((2, 3, 5, 4), dtype=dt).transpose(2, 3), torch.empty(shape, dtype=dt, device="meta"),
+           torch.empty(shape, dtype=dt).numpy()]
+    for out in bad:
+        with pytest.raises(binding.DFMError) as e:
+            binding.check_output(out, shape, dt, dev)
+        assert e.value.status == 1
 
 
 def test_null_arguments_are_rejected(lib):
@@ -91,6 +122,8 @@ def test_null_arguments_are_rejected(lib):
     assert lib.dfm_substep(None, 0, None) == 1
     out = ctypes.c_double()
     assert lib.dfm_nll(None, ctypes.byref(out), None) == 1
+    cnt = ctypes.c_int32()
+    assert lib.dfm_nll_trace(None, ctypes.byref(out), 1, ctypes.byref(cnt), None) == 1
     assert lib.dfm_separate(None, fake, None) == 1
     assert lib.dfm_covariances(None, fake, None) == 1
     assert lib.dfm_sync_status(None, None) == 1
