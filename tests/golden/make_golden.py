@@ -5,12 +5,15 @@ workload, for the GPU end-to-end parity tests:
 * ``paper_4x4`` -- F=513, T=625, four 4-mic subarrays, N=5, K=16; 100 iterations
   (about 4 minutes on 8 cores);
 * ``table2`` -- the shape of the paper's Table II: F=2049, T=157, three 4-mic subarrays,
-  N=3, K=16; 50 iterations (about a minute on 8 cores).
+  N=3, K=16; 50 iterations (about a minute on 8 cores);
+* ``paper_16`` -- the recording of ``paper_4x4`` separated with one 16-mic block (the
+  conventional method, L = 1); 100 iterations.
 
 Only ``oracle/`` and the seeded input generator are called; the inputs are rounded to the
 storage precision of the FP32 path first.  Stored: the cost (13) at a few iteration counts
 and 8192 entries of the separated source images (Wiener filter per subarray) after the last
-iteration, at positions drawn from a fixed seed.  Run from the repository root:
+iteration, at positions drawn from a fixed seed, and the final state (Q, g, W, H) in FP64, from
+which the tests form the oracle's separated images over every bin.  Run from the repository root:
     python tests/golden/make_golden.py paper_4x4
 """
 import os
@@ -24,7 +27,8 @@ sys.path.insert(0, ROOT)
 from oracle import dfmnmf as D  # noqa: E402
 from paper_2605_19388_amd import synth  # noqa: E402
 
-CHECKPOINTS = {"paper_4x4": (0, 1, 2, 5, 10, 20, 50, 100), "table2": (0, 1, 2, 5, 10, 20, 50)}
+CHECKPOINTS = {"paper_4x4": (0, 1, 2, 5, 10, 20, 50, 100), "table2": (0, 1, 2, 5, 10, 20, 50),
+               "paper_16": (0, 1, 2, 5, 10, 20, 50, 100)}
 SAMPLES = 8192
 SAMPLE_SEED = 4242
 
@@ -53,7 +57,8 @@ def main(name):
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.npz")
     np.savez_compressed(out, checkpoints=np.array(CHECKPOINTS[name], dtype=np.int32),
                         costs=np.array([costs[c] for c in CHECKPOINTS[name]]), sample_index=idx, sample_values=vals,
-                        source_norms=np.sqrt((np.abs(S) ** 2).sum(axis=(1, 2, 3))))
+                        source_norms=np.sqrt((np.abs(S) ** 2).sum(axis=(1, 2, 3))),
+                        final_iteration=np.int32(done), Q=state[0], g=state[1], W=state[2], H=state[3])
     print("wrote", out)
 
 
