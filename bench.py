@@ -5,7 +5,8 @@ A step is one whole job on one synthetic mixture already resident in HBM:
 reset the state to its initial values, run the workload's iterations
 (IP sweep + eqs. (8), (9), (10) each), evaluate the cost (13) and separate the
 sources with the per-subarray Wiener filter.  The reported value is
-iterations per second over the timed steps (whole job, one GPU).
+iterations per second over the timed steps (whole job, one GPU); the
+iterations are replayed from HIP graphs (``--no-graph``: plain launches).
 
 Workload (default ``paper_4x4``): F=513 bins, T=625 frames, four subarrays of
 four mics (M=16), N=5 sources, K=16 bases, 100 iterations, complex64 with the
@@ -13,9 +14,12 @@ IP solves in FP64.  Inputs are seeded synthetic mixtures (see
 ``paper_2605_19388_amd/synth.py``).
 
 Extra objects on the line:
-* ``roofline`` -- the kernel with the largest share of an iteration: its
-  algorithmic HBM bytes per launch divided by its average duration, measured
-  with HIP events around each of its launches during the timed steps;
+* ``roofline`` -- the slower of the two kernels with the largest share of an
+  iteration: its algorithmic HBM bytes per launch divided by its average
+  duration, measured with HIP events around each of its launches over a pass
+  of the same steps right after the timed region (``kernels`` lists both);
+  ``iteration`` prices the whole iteration (28 B per F*T*M bin) at the
+  measured time per iteration;
 * ``cpu_baseline`` -- the FP64 NumPy oracle timed on this host on a bounded
   sample of the same workload.
 """
@@ -40,6 +44,7 @@ FP64_PEAK_TFLOPS = 78.6  # dense FP64 (vector and matrix cores) of MI355X
 # same steps (k_gramd_f / k_gram_f: covariances; k_pw_f: powers and the W coefficients;
 # k_h_f: the H coefficients; k_g_f: the g update).
 BYTES_PER_BIN = {"k_gram": 8.0, "k_gramd": 8.0, "k_pw": 12.0, "k_h": 4.0, "k_g": 4.0}
+ITER_BYTES_PER_BIN = 28.0  # the whole iteration: 2 x 8 (X) + 3 x 4 (P written once, read twice)
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_19388_amd", "csrc", "dfm_fast.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_paper_4x4.json")
 
@@ -56,6 +61,12 @@ def parse():
     ap.add_argument("--workload", default="paper_4x4")
     ap.add_argument("--iters", type=int, default=None, help="iterations per step (default: the workload's)")
     ap.add_argument("--cpu-sample-iters", type=int, default=4)
+    ap.add_argument("--cpu-sample-iters-1t", type=int, default=2,
+                    help="iterations of the single-thread oracle leg")
+    ap.add_argument("--gram-bf16", action="store_true",
+                    help="covariances of eq. (14) from BF16 operands on the matrix cores (FP32 sums)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="plain kernel launches instead of HIP graph replays (for comparison)")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the oracle's NumPy/BLAS pools (default: as the host sets them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -238,6 +249,24 @@ def cold_mixtures(args):
     print(json.dumps(out), flush=True)
 
 
+def _live_kernel_times(p, one_step, steps, iters, kernels):
+    """Average duration (ms) of each kernel in `kernels` over `steps` whole steps, measured with
+    a pair of HIP events recorded on the launch stream around each of its launches (one kernel
+    per pass; while a kernel is profiled the launches are plain, since events cannot bracket one
+    kernel inside a graph replay)."""
+    import torch
+    out = {}
+    for k in kernels:
+        p.profile_kernel(k, max_launches=iters * steps + 8)
+        for _ in range(steps):
+            one_step()
+        torch.cuda.synchronize()
+        ms, n = p.profile_read()
+        p.profile_kernel(None)
+        out[k] = (ms, n)
+    return out
+
+
 def main():
     args = parse()
     if args.mixtures > 1:
@@ -262,7 +291,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2605_19388_amd import DistributedFastMNMF, synth
+    from paper_2605_19388_amd import DistributedFastMNMF, binding, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = synth.make(args.workload)
@@ -271,8 +300,9 @@ def main():
     X32 = w["X"].astype(np.complex64)
     W32, H32 = w["W"].astype(np.float32), w["H"].astype(np.float32)
     dev = torch.device("cuda:0")
+    flags = (binding.F_NO_GRAPH if args.no_graph else 0) | (binding.F_GRAM_BF16 if args.gram_bf16 else 0)
     p = DistributedFastMNMF(X32, mics, N, K, W=W32, H=H32, Q=w["Q"].astype(np.complex64),
-                            g=w["g"].astype(np.float32), device=dev)
+                            g=w["g"].astype(np.float32), device=dev, flags=flags)
     init = {k: getattr(p, k).clone() for k in ("Q", "g", "W", "H")}
     S = torch.empty((N, F, T, M), dtype=torch.complex64, device=dev)
 
@@ -287,7 +317,8 @@ def main():
         p.separate(out=S)
         return nll
 
-    log(f"[bench] workload {w['name']} F={F} T={T} mics={mics} N={N} K={K} iters/step={iters}")
+    log(f"[bench] workload {w['name']} F={F} T={T} mics={mics} N={N} K={K} iters/step={iters} "
+        f"launches={'plain' if args.no_graph else 'graph replays'}")
     if args.copy_mb:
         src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -296,20 +327,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log(f"[bench] calibration copy of {args.copy_mb} MiB done")
-    # Per-kernel durations (outside the timed region) to find the dominant kernel.
+    # Per-kernel durations back to back (outside the timed region) to rank the kernels.
     reset()
     p.step(2)
     ktimes = p.kernel_times(reps=args.kernel_reps)
     reset()
-    log("[bench] per-kernel average ms: " + ", ".join(f"{k}={v * 1e3:.1f}us" for k, v in ktimes.items()))
-    dominant = max(ktimes, key=ktimes.get)
+    log("[bench] per-kernel average (back to back): " + ", ".join(f"{k}={v * 1e3:.1f}us" for k, v in ktimes.items()))
+    top = sorted(ktimes, key=ktimes.get, reverse=True)[:2]
 
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-    p.profile_kernel(dominant, max_launches=iters * args.steps + 8)
+    # Timed region: whole steps, nothing else on the stream.
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
     nll = None
@@ -318,38 +348,56 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    dom_ms, dom_n = p.profile_read()
-    p.profile_kernel(None)
-    p.sync_status()
     gpu_ms = ev0.elapsed_time(ev1)
     elapsed = max(wall, gpu_ms / 1e3)
     value = iters * args.steps / elapsed
     bins = F * T * M
-    log(f"[bench] {args.steps} steps in {elapsed:.4f} s (events {gpu_ms:.2f} ms); nll={nll:.6e}; "
-        f"{dominant}: {dom_ms * 1e3:.1f} us avg over {dom_n} launches")
+    log(f"[bench] {args.steps} steps in {elapsed:.4f} s (events {gpu_ms:.2f} ms); nll={nll:.6e}")
+    # The same steps again with each of the two slowest kernels bracketed by HIP events.
+    live = _live_kernel_times(p, one_step, args.steps, iters, top)
+    p.sync_status()
+    for k, (ms, n) in live.items():
+        log(f"[bench] {k}: {ms * 1e3:.2f} us avg over {n} launches (events on the launch stream)")
+    dominant = max(live, key=lambda k: live[k][0])
 
-    base = dominant[:-2] if dominant.endswith("_f") else dominant   # shape-specialised variants
-    traffic = load_traffic(dominant) if w["name"] == "paper_4x4" else None  # counters taken on paper_4x4
-    if base in BYTES_PER_BIN:
-        traffic_alg = BYTES_PER_BIN[base] * bins
-        achieved = traffic_alg / (dom_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
-                "avg_us": round(dom_ms * 1e3, 3), "launches": dom_n,
-                "algorithmic_bytes_per_launch": traffic_alg}
-    else:
-        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
-                "traffic": traffic, "kernel": dominant, "avg_us": round(dom_ms * 1e3, 3), "launches": dom_n}
+    def kernel_roof(k):
+        ms, n = live[k]
+        base = k[:-2] if k.endswith("_f") else k   # shape-specialised variants
+        traffic = load_traffic(k) if w["name"] == "paper_4x4" else None  # counters taken on paper_4x4
+        if base not in BYTES_PER_BIN:
+            return {"kernel": k, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": None, "traffic": traffic, "avg_us": round(ms * 1e3, 3), "launches": n}
+        alg = BYTES_PER_BIN[base] * bins
+        gbs = alg / (ms * 1e-3) / 1e9
+        return {"kernel": k, "bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_us": round(ms * 1e3, 3),
+                "launches": n, "algorithmic_bytes_per_launch": alg}
+
+    roof = kernel_roof(dominant)
+    roof["kernels"] = [kernel_roof(k) for k in top]
+    # Whole iteration: the reference schedule's bytes over the measured time per iteration (the
+    # per-step reset, cost and separation included, so this is a lower bound).
+    it_bytes = ITER_BYTES_PER_BIN * bins
+    it_us = 1e6 * elapsed / (args.steps * iters)
+    roof["iteration"] = {"bytes": it_bytes, "us": round(it_us, 3),
+                         "achieved": round(it_bytes / (it_us * 1e-6) / 1e9, 2), "unit": "GB/s",
+                         "frac": round(it_bytes / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                         "kernel_sum_us": round(sum(ktimes.values()) * 1e3, 2)}
 
     # The contraction of eq. (14) runs on the FP64 matrix cores (16x16x4) when a subarray has
-    # more than four mics: price it against the FP64 MFMA peak at the flops of eq. (14) as
-    # written (a complex multiply-add is 8 flops, sum over subarrays of M_l^3 per frame).
+    # more than four mics.  Priced at the flops the kernel executes (16 x 16 tiles of
+    # (1/y)[mu] times the M_l^2 packed products, K = 4 frames: 2 M_l^3 per frame and subarray)
+    # and, for reference, at eq. (14) as written (a complex multiply-add is 8 flops: 8 M_l^3).
     gram_mfma = None
     if "k_gram_f" in ktimes and max(mics) > 4:
-        flops = 8.0 * sum(ml ** 3 for ml in mics) * F * T
-        tf = flops / (ktimes["k_gram_f"] * 1e-3) / 1e12
-        gram_mfma = {"bound": "mfma", "kernel": "k_gram_f", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4), "flops_per_launch": flops,
+        executed = 2.0 * sum(ml ** 3 for ml in mics) * F * T
+        written = 8.0 * sum(ml ** 3 for ml in mics) * F * T
+        sec = ktimes["k_gram_f"] * 1e-3
+        gram_mfma = {"bound": "mfma", "kernel": "k_gram_f", "achieved": round(executed / sec / 1e12, 2),
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(executed / sec / 1e12 / FP64_PEAK_TFLOPS, 4),
+                     "flops_executed_per_launch": executed, "flops_as_written_per_launch": written,
+                     "as_written_tflops": round(written / sec / 1e12, 2),
                      "avg_us": round(ktimes["k_gram_f"] * 1e3, 2)}
     out = {"metric": METRIC, "value": round(value, 3), "unit": "iterations/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4),
@@ -357,6 +405,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": w["name"], "F": F, "T": T, "mics": list(mics), "N": N, "K": K,
                       "iterations_per_step": iters, "bins_per_iteration": bins,
+                      "launches": "plain" if args.no_graph else "graph replays",
+                      "covariances": "bf16 operands, fp32 sums" if args.gram_bf16 else "fp32 operands, fp64 sums",
                       "step": "reset + iterations + cost (13) + Wiener separation"},
            "bins_per_s": round(value * bins, 1),
            "per_kernel_us": {k: round(v * 1e3, 2) for k, v in ktimes.items()},
@@ -364,9 +414,11 @@ def main():
     if gram_mfma:
         out["roofline_gram"] = gram_mfma
     if not args.no_cpu_baseline:
-        log("[bench] timing the FP64 oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(w, X32.astype(np.complex128), W32.astype(np.float64),
-                                           H32.astype(np.float64), args.cpu_sample_iters, args.cpu_threads)
+        log("[bench] timing the FP64 oracle on the host (all threads, then one) ...")
+        X64, W64, H64 = X32.astype(np.complex128), W32.astype(np.float64), H32.astype(np.float64)
+        cb = cpu_baseline(w, X64, W64, H64, args.cpu_sample_iters, args.cpu_threads)
+        cb["single_thread"] = cpu_baseline(w, X64, W64, H64, args.cpu_sample_iters_1t, 1)
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

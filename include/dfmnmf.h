@@ -66,6 +66,11 @@ typedef enum {
 #define DFM_F_TRACE_NLL 2u     /* evaluate the cost (13) after every iteration of dfm_step on
                                   the device into a trace read by dfm_nll_trace (costs one extra
                                   pass over X per iteration) */
+#define DFM_F_GRAM_BF16 4u     /* weighted covariances of eq. (14) from BF16 operands on the
+                                  matrix cores with FP32 sums (the IP solves, the eq. (16)
+                                  normalisation and ln|det Q| stay FP64); complex64 plans of a
+                                  uniform partition into 2- or 4-mic subarrays with a compiled
+                                  (N, K, M_l, L) set, else DFM_E_ARG */
 #define DFM_F_NO_GRAPH 8u      /* dfm_step issues plain kernel launches instead of replaying
                                   HIP graphs of its iterations (same kernels, same results) */
 #define DFM_TRACE_CAPACITY 4096 /* entries of the cost trace; later iterations are counted

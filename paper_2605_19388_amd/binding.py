@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdfmnmf.so")
 MAX_SUBARRAYS = 64
 DFM_C64, DFM_C128 = 0, 1
 # dfm_problem.flags bits
-F_CHECK_FINITE, F_TRACE_NLL, F_NO_GRAPH = 1, 2, 8
+F_CHECK_FINITE, F_TRACE_NLL, F_GRAM_BF16, F_NO_GRAPH = 1, 2, 4, 8
 TRACE_CAPACITY = 4096
 STAGES = {"ip": 0, "W": 1, "H": 2, "g": 3}
 STATUS = {0: "DFM_OK", 1: "DFM_E_ARG", 2: "DFM_E_SHAPE", 3: "DFM_E_WORKSPACE", 4: "DFM_E_HIP",

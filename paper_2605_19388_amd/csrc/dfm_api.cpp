@@ -122,7 +122,7 @@ static void choose_tiles(Dims& d, int dtype) {
 static dfm_status make_dims(const dfm_problem* p, Dims& d) {
   if (!p) return DFM_E_ARG;
   if (p->dtype != DFM_C64 && p->dtype != DFM_C128) return DFM_E_ARG;
-  constexpr uint32_t known = DFM_F_CHECK_FINITE | DFM_F_TRACE_NLL | DFM_F_NO_GRAPH;
+  constexpr uint32_t known = DFM_F_CHECK_FINITE | DFM_F_TRACE_NLL | DFM_F_GRAM_BF16 | DFM_F_NO_GRAPH;
   if (!(p->eps > 0.0) || !std::isfinite(p->eps) || (p->flags & ~known) != 0) return DFM_E_ARG;
   if (p->F < 1 || p->T < 1 || p->N < 1 || p->N > kMaxN || p->K < 1 || p->K > kMaxK || p->L < 1 || p->L > kMaxL)
     return DFM_E_SHAPE;
@@ -157,6 +157,10 @@ static dfm_status make_dims(const dfm_problem* p, Dims& d) {
   const double big = (double)d.F * d.T * d.M * 2 * (p->N > 1 ? p->N : 1);
   if (big >= 2147483647.0) return DFM_E_SHAPE;
   if (!choose_fast(d, p->dtype)) choose_tiles(d, p->dtype);
+  // BF16 covariances: only where the shape-specialised path has the kernel (k_gramb_f).
+  if ((p->flags & DFM_F_GRAM_BF16) &&
+      (p->dtype != DFM_C64 || d.fast < 0 || d.GR <= 0 || !fast_gram_bf16(d.N, d.K, d.ML, d.L)))
+    return DFM_E_ARG;
   return DFM_OK;
 }
 

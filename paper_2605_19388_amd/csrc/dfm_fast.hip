@@ -670,6 +670,187 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Weighted covariances (eq. (14)) with BF16 operands on the matrix cores and FP32 sums
+// (DFM_F_GRAM_BF16), for subarrays of M_l = 2 or 4 mics.  The IP solves that follow stay FP64.
+//
+// V_flmu = (1/T) sum_t z_t z_t^H with z_t = x^(l)_ft / sqrt(y_{f,t,o_l+mu}): each z is rounded to
+// BF16 once and used on both sides, so the computed V is the exact Gram matrix of the rounded
+// vectors -- Hermitian positive semidefinite like eq. (14) itself.  (Rounding w x_a and x_b
+// separately breaks that: at the lowest bins, where the mixing is nearly rank-1, V then has
+// negative eigenvalues and the IP normaliser of eq. (16) loses its meaning.)  As a real matrix
+// product with the frames and their (re, im) parts along the contraction,
+//   Re V[a][b] = sum_t (Re z_a, Im z_a) . (Re z_b, Im z_b),  Im V[a][b] = sum_t (Im z_a, -Re z_a) . (Re z_b, Im z_b).
+// One v_mfma_f32_16x16x32_bf16 contracts 16 frames for a 16 x 16 tile whose rows and columns
+// are (subarray, mu, mic) triples of 16 / M_l^2 subarrays; the (l, mu) diagonal blocks are the
+// wanted V_flmu.  Lane l supplies row l % 16 of the left operand and column l % 16 of the right
+// one for the four frames of lane group l / 16 -- the same z values for both -- and holds column
+// l % 16, rows 4 (l / 16) .. + 3 of the sum.  The flattened (f, t) frames are shared out as for
+// k_gramd_f (ranges of Dims::GR per workgroup, one partial-sum slot per bin segment) and the
+// slots are written in FP64 in its packed layout, so k_ip_f reads either kernel's output.
+constexpr int kGBW = 4;  // waves per workgroup of k_gramb_f
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int ML, int L>
+struct GramB {
+  static constexpr int ML2 = ML * ML;
+  static constexpr int SPT = 16 / ML2;                 // subarrays per 16 x 16 tile
+  static constexpr int NT = (L + SPT - 1) / SPT;       // tiles
+  static_assert(ML == 2 || ML == 4, "M_l of 2 or 4");
+};
+
+// Per chunk of 16 frames each wave stages the frames' x (16 M complex, contiguous in X) with
+// 16-byte loads and their weights 1 / sqrt(y) (lane (t, mic group) forms y from lambda and g) in
+// its own LDS area, then every lane gathers the x and weights of its rows from there.
+template <int N, int K, int ML, int L>
+__global__ __launch_bounds__(64 * kGBW) void k_gramb_f(Dims d, const cx<float>* __restrict__ X,
+                                                      const float* __restrict__ lamin, float* __restrict__ g,
+                                                      const float* __restrict__ gpart,
+                                                      const float* __restrict__ gsnap, double* __restrict__ V) {
+  typedef GramB<ML, L> G;
+  constexpr int M = ML * L, ML2 = ML * ML, SPT = G::SPT, NT = G::NT, NM = N * M;
+  constexpr int XS = 2 * M + 4;          // LDS row of one frame's x (reals), padded
+  constexpr int XV = 2 * M / 4;          // 16-byte vectors of one frame's x
+  constexpr int MG = 64 / 16;            // mic groups of the weight stage (lane = (frame, group))
+  constexpr int MPG = (M + MG - 1) / MG; // mics per group
+  static_assert(NM <= 64 * kGBW, "one thread per g entry");
+  static_assert((2 * M) % 4 == 0 && 16 * XV <= 64 * 4, "x staging");
+  __shared__ float red[kGBW][L][ML2][ML][2];   // [wave][l][mu * ML + a][b][re, im]
+  __shared__ __align__(16) float sx[kGBW][16][XS];  // per wave: the chunk's x, frame-major
+  __shared__ float sw[kGBW][16][M + 1];        // per wave: 1 / sqrt(y) of the chunk
+  __shared__ float sg[NM];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, kg = lane >> 4;                    // row / column of the tile, lane group
+  const int rl = r / ML2, rmu = (r % ML2) / ML, ra = r % ML;  // (subarray in the tile, mu, mic)
+  const int wt = lane & 15, wg = lane >> 4;                   // weight stage: frame, mic group
+  const int T = d.T;
+  const long long total = (long long)d.F * T;
+  const long long a0 = (long long)blockIdx.x * d.GR, a1 = min(total, a0 + d.GR);
+  for (long long i0 = a0; i0 < a1;) {
+    const int f = (int)(i0 / T);
+    const long long fend = min(a1, (long long)(f + 1) * T);
+    const int ts = (int)(i0 - (long long)f * T), te = (int)(fend - (long long)f * T);
+    const int slot = blockIdx.x - (int)(((long long)f * T) / d.GR);
+    i0 = fend;
+    // g of the bin, finishing a pending g update exactly as k_gramd_f does.
+    const float* gsrc = g + (size_t)f * NM;
+    if (d.gpend) {
+      if (tid < NM) {
+        const float v = g_updated<float>(gpart + (size_t)f * d.GGS * 2 * NM + tid, g_slots(d, f), NM,
+                                         gsnap[(size_t)f * NM + tid], (float)d.eps);
+        sg[tid] = v;
+        if (ts == 0) g[(size_t)f * NM + tid] = v;
+      }
+      __syncthreads();
+      gsrc = sg;
+    }
+    float gm[MPG][N];  // g of this lane's weight-stage mics
+#pragma unroll
+    for (int k = 0; k < MPG; ++k)
+#pragma unroll
+      for (int n = 0; n < N; ++n) gm[k][n] = wg * MPG + k < M ? gsrc[n * M + wg * MPG + k] : 1.0f;
+    const float* xf = reinterpret_cast<const float*>(X + (size_t)f * T * M);
+    const float* lb = lamin + (size_t)f * N * T;
+    f32x4 cre[NT], cim[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      cre[q] = f32x4{0, 0, 0, 0};
+      cim[q] = f32x4{0, 0, 0, 0};
+    }
+    // Global loads of one chunk: lane v < 16 XV takes 16-byte vector v of the chunk's x (frames
+    // past the segment are not read), and lambda at its weight-stage frame (clamped).
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    auto fetch = [&](int c0, f4 (&xv)[(16 * XV + 63) / 64], float (&la)[N]) {
+#pragma unroll
+      for (int u = 0; u < (16 * XV + 63) / 64; ++u) {
+        const int v = lane + 64 * u, fr = v / XV;
+        const bool ok = v < 16 * XV && c0 + fr < te;
+        xv[u] = ok ? *reinterpret_cast<const f4*>(xf + (size_t)c0 * 2 * M + 4 * v) : f4{0, 0, 0, 0};
+      }
+      const int t = min(c0 + wt, te - 1);
+#pragma unroll
+      for (int n = 0; n < N; ++n) la[n] = lb[(size_t)n * T + t];
+    };
+    constexpr int XU = (16 * XV + 63) / 64;
+    f4 xv[XU], xn[XU];
+    float la[N], ln[N];
+    int c0 = ts + wave * 16;
+    fetch(c0, xv, la);
+    for (; c0 < te; c0 += 16 * kGBW) {
+      fetch(c0 + 16 * kGBW, xn, ln);  // the next chunk in flight during this one
+      // Stage: x rows, and the weights of frame wt at this lane's mic group.
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int v = lane + 64 * u;
+        if (v < 16 * XV) *reinterpret_cast<f4*>(&sx[wave][v / XV][4 * (v % XV)]) = xv[u];
+      }
+      const bool tlive = c0 + wt < te;
+#pragma unroll
+      for (int k = 0; k < MPG; ++k) {
+        float y = 0.0f;
+#pragma unroll
+        for (int n = 0; n < N; ++n) y += la[n] * gm[k][n];
+        if (wg * MPG + k < M) sw[wave][wt][wg * MPG + k] = tlive ? __builtin_amdgcn_rsqf(rmax(y, (float)d.eps)) : 0.0f;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int l = min(q * SPT + rl, L - 1);
+        const bool rowv = q * SPT + rl < L;
+        bf16x8 az, ai;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int fr = 4 * kg + j;
+          const float s = rowv ? sw[wave][fr][l * ML + rmu] : 0.0f;
+          const float2 x = *reinterpret_cast<const float2*>(&sx[wave][fr][2 * (l * ML + ra)]);
+          const __bf16 zr = (__bf16)(s * x.x), zi = (__bf16)(s * x.y);
+          az[2 * j] = zr;
+          az[2 * j + 1] = zi;
+          ai[2 * j] = zi;
+          ai[2 * j + 1] = -zr;
+        }
+        cre[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(az, az, cre[q], 0, 0, 0);
+        cim[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, az, cim[q], 0, 0, 0);
+      }
+      // The staging area is rewritten by the next chunk: every lane's gathers come first.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int u = 0; u < XU; ++u) xv[u] = xn[u];
+#pragma unroll
+      for (int n = 0; n < N; ++n) la[n] = ln[n];
+    }
+    // Lane (column r, group kg) holds rows 4 kg + e of each tile; the (l, mu) diagonal blocks are
+    // V_lmu.  Every (l, mu, a, b) sits in exactly one lane of each wave.
+    __syncthreads();  // the previous segment's readers of red are done
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = 4 * kg + e;
+        const int l = q * SPT + row / ML2, mu = (row % ML2) / ML, a = row % ML;
+        if (l < L && row / ML2 == rl && mu == rmu) {
+          red[wave][l][mu * ML + a][ra][0] = cre[q][e];
+          red[wave][l][mu * ML + a][ra][1] = cim[q][e];
+        }
+      }
+    __syncthreads();
+    for (int o = tid; o < L * ML * ML2; o += 64 * kGBW) {
+      const int l = o / (ML * ML2), rem = o - l * ML * ML2, mu = rem / ML2, jj = rem - mu * ML2;
+      int a, b, part;
+      packed_pair(ML, jj, a, b, part);
+      float sum = 0.0f;
+      for (int w = 0; w < kGBW; ++w) sum += red[w][l][mu * ML + a][b][part];
+      V[((size_t)f * d.SG + slot) * d.VF + o] = (double)sum;
+    }
+  }
+}
+
 // lambda[f][n][t] = sum_k W[n][f][k] H[n][k][t] (eq. (2)) on the matrix cores: one 16 x 16
 // tile (rows f, columns t) per wave, contraction over the bases four at a time.
 // Hn: the activations of source n for the tile's 16 frames, [4 * ceil(K/4)][16] in LDS,
@@ -1730,14 +1911,22 @@ struct Set {
     const int fp = (d.F + 15) & ~15, fw = GemmLds<R, K>::fw(d);
     return (fp + fw - 1) / fw;
   }
-  // Workgroups of k_gramd_f resident per CU (registers and LDS), or 0 if unknown.
-  static int gramd_blocks_per_cu() {
+  // BF16 covariances on the matrix cores (DFM_F_GRAM_BF16) exist for the FP32 sets with M_l <= 4.
+  static constexpr bool kGramB = kGramD;
+  // Workgroups of k_gramd_f (or k_gramb_f) resident per CU (registers and LDS), or 0 if unknown.
+  static int gramd_blocks_per_cu(bool bf16) {
     if constexpr (kGramD) {
       int n = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gramd_f<N, K, ML, L>, gramd_threads<L>(), 0) !=
-          hipSuccess)
-        return 0;
-      return n;
+      hipError_t e;
+      if constexpr (kGramB) {
+        if (bf16)
+          e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gramb_f<N, K, ML, L>, 64 * kGBW, 0);
+        else
+          e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gramd_f<N, K, ML, L>, gramd_threads<L>(), 0);
+      } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gramd_f<N, K, ML, L>, gramd_threads<L>(), 0);
+      }
+      return e == hipSuccess ? n : 0;
     } else {
       return 0;
     }
@@ -1779,6 +1968,14 @@ struct Set {
                            static_cast<R*>(b.lam));
         break;
       case kFGram:
+        if constexpr (kGramB) {
+          if (d.flags & DFM_F_GRAM_BF16) {
+            hipLaunchKernelGGL((k_gramb_f<N, K, ML, L>), dim3(d.GW), dim3(64 * kGBW), 0, s, d, X,
+                               static_cast<const R*>(b.lam), g, static_cast<const R*>(b.gpart),
+                               static_cast<const R*>(b.gsnap), static_cast<double*>(b.Vpart));
+            break;
+          }
+        }
         if constexpr (kGramD) {
           hipLaunchKernelGGL((k_gramd_f<N, K, ML, L>), dim3(d.GW), dim3(gramd_threads<L>()), 0, s, d, X,
                              static_cast<const R*>(b.lam), g, static_cast<const R*>(b.gpart),
@@ -1866,10 +2063,11 @@ int fast_set_index(int N, int K, int ML, int L) {
 }
 
 int fast_gramd_blocks_per_cu(const Dims& d) {
+  const bool bf16 = (d.flags & DFM_F_GRAM_BF16) != 0;
   switch (d.fast) {
 #define DFM_OCC(i, n, k, ml, l) \
   case i:                      \
-    return fast::Set<float, n, k, ml, l>::gramd_blocks_per_cu();
+    return fast::Set<float, n, k, ml, l>::gramd_blocks_per_cu(bf16);
     DFM_FAST_SETS(DFM_OCC)
 #undef DFM_OCC
   }
@@ -1900,7 +2098,16 @@ size_t fast_max_smem(const Dims& d, int dtype) {
   return 0;
 }
 
+bool fast_gram_bf16(int N, int K, int ML, int L) {
+#define DFM_GB(i, n, k, ml, l) \
+  if (N == n && K == k && ML == ml && L == l) return fast::Set<float, n, k, ml, l>::kGramB;
+  DFM_FAST_SETS(DFM_GB)
+#undef DFM_GB
+  return false;
+}
+
 const char* fast_kernel_name(const Dims& d, int dtype, int kid) {
+  if (kid == kFGram && dtype == DFM_C64 && (d.flags & DFM_F_GRAM_BF16)) return "k_gramb_f";
   if (kid == kFGram && dtype == DFM_C64 && (d.ML == 2 || d.ML == 4)) return "k_gramd_f";
   if (kid == kFIp && d.ML > 4) return kernel_name(kKIp);
   if (kid == kFHGemm && d.HC > 1) return "k_hsum_f";

@@ -99,7 +99,8 @@ int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns 
 int fast_set_index(int N, int K, int ML, int L);
 size_t fast_max_smem(const Dims& d, int dtype);
 int fast_hgemm_windows(const Dims& d, int dtype);  // LDS windows of W[n] in the H update
-int fast_gramd_blocks_per_cu(const Dims& d);  // resident k_gramd_f workgroups per CU (0: unknown)
+int fast_gramd_blocks_per_cu(const Dims& d);  // resident k_gramd_f / k_gramb_f workgroups per CU (0: unknown)
+bool fast_gram_bf16(int N, int K, int ML, int L);  // the set has the BF16 covariance kernel
 hipError_t fast_launch(const Dims& d, const Buffers& b, int dtype, int kid, hipStream_t s);
 const char* fast_kernel_name(const Dims& d, int dtype, int kid);  // symbol family a kernel id runs
 // Cost (13) partials or the Wiener filter with the specialised kernels (M_l <= 4).

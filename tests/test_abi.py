@@ -64,7 +64,10 @@ def test_workspace_size_valid(lib):
     (dict(F=0), 2), (dict(T=0), 2), (dict(N=0), 2), (dict(N=17), 2), (dict(K=0), 2), (dict(K=65), 2),
     (dict(mics=(2, 0)), 2), (dict(mics=(33,)), 2), (dict(mics=(32, 33)), 2), (dict(mics=(16,) * 5), 2),
     (dict(mics=()), 2), (dict(dtype=2), 1), (dict(eps=0.0), 1), (dict(eps=-1.0), 1), (dict(eps=float("nan")), 1),
-    (dict(flags=4), 1), (dict(flags=16), 1), (dict(flags=1 << 31), 1),
+    (dict(flags=16), 1), (dict(flags=1 << 31), 1),
+    (dict(flags=4, mics=(2, 3)), 1),                      # BF16 covariances: generic partition
+    (dict(flags=4, mics=(16,), N=5, K=16), 1),            # 16-mic blocks
+    (dict(flags=4, mics=(4, 4, 4, 4), N=5, K=16, dtype=1), 1),  # complex128
 ])
 def test_workspace_size_rejects(lib, kw, code):
     st, _ = _ws(lib, _problem(**kw))
@@ -72,7 +75,9 @@ def test_workspace_size_rejects(lib, kw, code):
 
 
 @pytest.mark.parametrize("kw", [dict(mics=(32,)), dict(mics=(32, 32)), dict(mics=(1,) * 64),
-                                dict(flags=1), dict(flags=2), dict(flags=8), dict(flags=1 | 2 | 8)])
+                                dict(flags=1), dict(flags=2), dict(flags=8), dict(flags=1 | 2 | 8),
+                                dict(flags=4, mics=(4, 4, 4, 4), N=5, K=16), dict(flags=4, mics=(2, 2), N=2, K=4),
+                                dict(flags=4, mics=(4, 4, 4), N=3, K=16)])
 def test_workspace_size_accepts(lib, kw):
     st, n = _ws(lib, _problem(**kw))
     assert st == 0 and n > 0
