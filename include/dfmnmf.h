@@ -185,6 +185,31 @@ dfm_status dfm_profile_kernel(dfm_plan* plan, int32_t kernel, int32_t max_launch
  * the number of profiled launches since the last read, and reset the count. */
 dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, void* stream);
 
+/* ---- Entry point that allocates nothing.
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  One call does what
+ * dfm_init, dfm_step(n_iter) and (if cost != NULL) the cost of dfm_nll do, with the
+ * same kernels and the same results, but its workspace is a static device array
+ * of DFM_NOALLOC_SCRATCH_BYTES owned by the library (one per GPU, held until the
+ * process ends) instead of a caller's buffer, its launches are plain (no graphs),
+ * and it calls no hipMalloc, hipFree or other allocating routine and makes no host
+ * copy.  Asynchronous on `stream`.
+ *   p, X, Q, g, W, H: as for dfm_init (Q, g, W, H updated in place).
+ *   cost: device pointer to one double receiving the cost (13) after the last
+ *     iteration, or NULL.
+ *   status: device pointer to one int32 receiving the sticky device status bits
+ *     after the run (1: singular IP system, 2: non-finite parameter with
+ *     DFM_F_CHECK_FINITE), or NULL.
+ * Returns DFM_E_WORKSPACE if the problem needs more than DFM_NOALLOC_SCRATCH_BYTES
+ * (dfm_workspace_size), DFM_E_ARG for DFM_F_TRACE_NLL (its trace is read through a
+ * plan), and the errors of dfm_init / dfm_step otherwise.  Every call on a GPU
+ * uses that GPU's one array: calls that overlap on one GPU (on different streams,
+ * or from different host threads) race and give wrong results; the array keeps
+ * the last call's contents (each call clears what it reads before writing). */
+#define DFM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dfm_status dfm_run_noalloc(const dfm_problem* p, const void* X, void* Q, void* g, void* W, void* H,
+                           int32_t n_iter, double* cost, int32_t* status, void* stream);
+
 /* Free the host-side plan.  Does not touch the caller's device buffers. */
 void dfm_destroy(dfm_plan* plan);
 

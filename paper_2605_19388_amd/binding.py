@@ -20,6 +20,7 @@ DFM_C64, DFM_C128 = 0, 1
 # dfm_problem.flags bits
 F_CHECK_FINITE, F_TRACE_NLL, F_GRAM_BF16, F_NO_GRAPH = 1, 2, 4, 8
 TRACE_CAPACITY = 4096
+NOALLOC_SCRATCH_BYTES = 64 << 20
 STAGES = {"ip": 0, "W": 1, "H": 2, "g": 3}
 STATUS = {0: "DFM_OK", 1: "DFM_E_ARG", 2: "DFM_E_SHAPE", 3: "DFM_E_WORKSPACE", 4: "DFM_E_HIP",
           5: "DFM_E_NONFINITE", 6: "DFM_E_SINGULAR"}
@@ -44,7 +45,7 @@ class Problem(ctypes.Structure):
 _lib = None
 EXPORTS = ("dfm_workspace_size", "dfm_init", "dfm_step", "dfm_substep", "dfm_nll", "dfm_nll_trace", "dfm_separate",
            "dfm_covariances", "dfm_sync_status", "dfm_kernel_times", "dfm_profile_kernel", "dfm_profile_read",
-           "dfm_kernel_count", "dfm_kernel_name", "dfm_destroy", "dfm_status_string")
+           "dfm_kernel_count", "dfm_kernel_name", "dfm_run_noalloc", "dfm_destroy", "dfm_status_string")
 
 
 def load(path: str = LIB_PATH):
@@ -69,6 +70,7 @@ def load(path: str = LIB_PATH):
     lib.dfm_kernel_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.dfm_profile_kernel.argtypes = [vp, i32, i32]
     lib.dfm_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), vp]
+    lib.dfm_run_noalloc.argtypes = [P, vp, vp, vp, vp, vp, i32, vp, vp, vp]
     lib.dfm_kernel_count.argtypes = [vp]
     lib.dfm_kernel_count.restype = i32
     lib.dfm_kernel_name.argtypes = [vp, i32]

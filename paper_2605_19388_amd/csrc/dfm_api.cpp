@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -522,6 +523,70 @@ dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, v
   *launches = (int64_t)n;
   *avg_ms = n ? total / n : 0.0;
   plan->prof_used = 0;
+  return DFM_OK;
+}
+
+}  // extern "C"
+
+// ---- The workspace of dfm_run_noalloc: a static device array, one per GPU.  In host code
+// `scratch` names a host-side stand-in, not the array: its device address on the current GPU
+// comes from hipGetSymbolAddress, taken once per device and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[DFM_NOALLOC_SCRATCH_BYTES];
+
+namespace dfm {
+
+constexpr int kMaxDevices = 64;
+static void* scratch_ptr[kMaxDevices];
+static std::mutex scratch_mu;
+
+// Device address of `scratch` on the current GPU (looked up on the first call per device), or
+// nullptr on a HIP error.
+static void* scratch_address() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    scratch_ptr[dev] = ptr;
+  }
+  return scratch_ptr[dev];
+}
+
+}  // namespace dfm
+
+extern "C" {
+
+dfm_status dfm_run_noalloc(const dfm_problem* p, const void* X, void* Q, void* g, void* W, void* H,
+                           int32_t n_iter, double* cost, int32_t* status, void* stream) {
+  Dims d;
+  const dfm_status st = dfm::make_dims(p, d);
+  if (st != DFM_OK) return st;
+  if (!X || !Q || !g || !W || !H || n_iter < 0 || (p->flags & DFM_F_TRACE_NLL)) return DFM_E_ARG;
+  if (dfm::workspace_bytes(d, p->dtype) > DFM_NOALLOC_SCRATCH_BYTES) return DFM_E_WORKSPACE;
+  void* ws = dfm::scratch_address();
+  if (!ws) return DFM_E_HIP;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // A plan on the stack (its vector of profiling events stays empty: nothing is allocated),
+  // plain launches only.
+  dfm_plan plan;
+  plan.d = d;
+  plan.dtype = p->dtype;
+  plan.graph_off = true;
+  std::memset(&plan.b, 0, sizeof(plan.b));
+  plan.b.X = X;
+  plan.b.Q = Q;
+  plan.b.g = g;
+  plan.b.W = W;
+  plan.b.H = H;
+  dfm::carve(d, p->dtype, static_cast<char*>(ws), plan.b);
+  if (dfm::launch_init(d, plan.b, s) != hipSuccess) return DFM_E_HIP;  // status and trace counter
+  const dfm_status r = dfm_step(&plan, n_iter, stream);
+  if (r != DFM_OK) return r;
+  if (cost && (dfm::launch_nll(d, plan.b, plan.dtype, s) != hipSuccess ||
+               dfm::launch_nll_total(d, plan.b, cost, false, s) != hipSuccess))
+    return DFM_E_HIP;
+  if (status && dfm::launch_copy_status(plan.b, status, s) != hipSuccess) return DFM_E_HIP;
   return DFM_OK;
 }
 

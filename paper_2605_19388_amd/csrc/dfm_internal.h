@@ -110,6 +110,7 @@ hipError_t launch_nll(const Dims& d, const Buffers& b, int dtype, hipStream_t s)
 // `trace`, also appended to b.trace at the counter status[kTraceSlot] (then incremented).
 hipError_t launch_nll_total(const Dims& d, const Buffers& b, double* out, bool trace, hipStream_t s);
 hipError_t launch_clear_status(const Buffers& b, hipStream_t s);  // sticky word only
+hipError_t launch_copy_status(const Buffers& b, int* out, hipStream_t s);  // sticky word -> out
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
 hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);
 

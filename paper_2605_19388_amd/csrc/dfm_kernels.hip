@@ -762,6 +762,15 @@ hipError_t launch_init(const Dims& d, const Buffers& b, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_copy_int(const int* src, int* dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+hipError_t launch_copy_status(const Buffers& b, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(64), 0, s, b.status, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_clear_status(const Buffers& b, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.status, 1);
   return hipGetLastError();
