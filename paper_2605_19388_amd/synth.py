@@ -36,7 +36,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "mixture", "initial_state", "make", "qblock_offsets"]
+__all__ = ["Workload", "WORKLOADS", "mixture", "source_images", "initial_state", "make", "qblock_offsets"]
 
 
 @dataclass(frozen=True)
@@ -93,8 +93,11 @@ def qblock_offsets(mics) -> list:
 
 
 def mixture(F: int, T: int, mics, N: int, K: int, seed: int, mixing: str = "iid",
-            noise: float = 1e-3, max_delay: float = 20.0, gain_range=(0.5, 2.0)) -> np.ndarray:
-    """Return X[F, T, M] complex128 drawn from the generative model of eqs. (1)-(2)."""
+            noise: float = 1e-3, max_delay: float = 20.0, gain_range=(0.5, 2.0), _masks: bool = False):
+    """Return X[F, T, M] complex128 drawn from the generative model of eqs. (1)-(2).
+
+    With ``_masks`` also return the sources' share of the power at each (f, t),
+    psd_n / sum_n' psd_n' [N, F, T], from the same draws (see ``source_images``)."""
     mics = tuple(int(m) for m in mics)
     M = sum(mics)
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -116,7 +119,20 @@ def mixture(F: int, T: int, mics, N: int, K: int, seed: int, mixing: str = "iid"
     else:
         raise ValueError(f"unknown mixing {mixing!r}")
     X = np.einsum("fnm,ftn->ftm", A, s) + _cn(rng, (F, T, M), noise)
+    if _masks:
+        return np.ascontiguousarray(X), np.transpose(psd / psd.sum(axis=2, keepdims=True), (2, 0, 1))
     return np.ascontiguousarray(X)
+
+
+def source_images(F: int, T: int, mics, N: int, K: int, seed: int, mixing: str = "iid", **kw):
+    """Estimates of the N source images c_ftn [N, F, T, M] complex128 of the recording that
+    ``mixture`` draws with the same arguments, made the way the paper's initialisation makes
+    them (Sec. IV-A, step 2: soft time-frequency masks applied to the mixture): c_ftn = m_ftn x_ft
+    with the mask m_ftn = psd_ftn / sum_n psd_ftn taken from the sources' true power
+    spectrograms.  (The paper estimates the masks by clustering; that step is a separate
+    method and stands outside this library.)  Returns (X, C)."""
+    X, m = mixture(F, T, mics, N, K, seed, mixing=mixing, _masks=True, **kw)
+    return X, np.ascontiguousarray(m[:, :, :, None] * X[None])
 
 
 def initial_state(F: int, T: int, mics, N: int, K: int, seed: int):
