@@ -185,6 +185,30 @@ dfm_status dfm_profile_kernel(dfm_plan* plan, int32_t kernel, int32_t max_launch
  * the number of profiled launches since the last read, and reset the count. */
 dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, void* stream);
 
+/* ---- Initial parameters from estimates of the source images (Sec. IV-A, steps 3, 5, 6).
+ * The paper initialises from source images estimated by time-frequency masking
+ * (its steps 1-2) and factorises the initial spectrograms by IS-NMF (step 4);
+ * those are separate methods and the caller's.  From the image estimates
+ *   C [N][F][T][M] complex (c_ftn, the dtype of *p), read-only,
+ * dfm_initialise computes, all in FP64:
+ *   R_fn = (1/T) sum_t c_ftn c_ftn^H (M x M, across subarrays) and
+ *   h [N][F][T] real = c_ftn^H R_fn^{-1} c_ftn / M (step 3; h may be NULL);
+ *   Q [F][sum_l M_l^2] complex: per (f, l) the columns w_mu of W solve the generalized
+ *     eigenproblem R_f,N-1^(l) w = lambda R_f,N^(l) w on the l-th diagonal blocks of
+ *     the last two sources (step 5), with W^H R_f,N^(l) W = I, lambda ascending and
+ *     each w's largest entry (the first on a tie) real positive; row mu of Q_fl is
+ *     w_mu^H;
+ *   g [F][N][M] real: g[f][n][o_l + mu] = w_mu^H R_fn^(l) w_mu (step 6, the diagonal
+ *     of W^H R_fn^(l) W).
+ * Q, g and h are written, caller-owned.  N >= 2 (step 5 needs two sources), else
+ * DFM_E_SHAPE.  The workspace (>= dfm_initialise_workspace_size bytes, 256-byte
+ * aligned) holds the R_fn.  Synchronises `stream`; returns DFM_E_SINGULAR if an
+ * image covariance is not positive definite (that block's outputs are then
+ * unspecified). */
+dfm_status dfm_initialise_workspace_size(const dfm_problem* p, size_t* bytes);
+dfm_status dfm_initialise(const dfm_problem* p, const void* C, void* Q, void* g, void* h,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- Entry point that allocates nothing.
  * For callers that cannot allocate device memory: code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc.  One call does what

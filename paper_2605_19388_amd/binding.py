@@ -45,7 +45,8 @@ class Problem(ctypes.Structure):
 _lib = None
 EXPORTS = ("dfm_workspace_size", "dfm_init", "dfm_step", "dfm_substep", "dfm_nll", "dfm_nll_trace", "dfm_separate",
            "dfm_covariances", "dfm_sync_status", "dfm_kernel_times", "dfm_profile_kernel", "dfm_profile_read",
-           "dfm_kernel_count", "dfm_kernel_name", "dfm_run_noalloc", "dfm_destroy", "dfm_status_string")
+           "dfm_kernel_count", "dfm_kernel_name", "dfm_run_noalloc", "dfm_initialise_workspace_size",
+           "dfm_initialise", "dfm_destroy", "dfm_status_string")
 
 
 def load(path: str = LIB_PATH):
@@ -71,6 +72,8 @@ def load(path: str = LIB_PATH):
     lib.dfm_profile_kernel.argtypes = [vp, i32, i32]
     lib.dfm_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), vp]
     lib.dfm_run_noalloc.argtypes = [P, vp, vp, vp, vp, vp, i32, vp, vp, vp]
+    lib.dfm_initialise_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.dfm_initialise.argtypes = [P, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.dfm_kernel_count.argtypes = [vp]
     lib.dfm_kernel_count.restype = i32
     lib.dfm_kernel_name.argtypes = [vp, i32]
@@ -130,6 +133,40 @@ def check_output(out, shape, dtype, device):
         raise DFMError(1, f"out is on {out.device}, expected {device}")
     if not out.is_contiguous():
         raise DFMError(1, "out must be contiguous")
+
+
+def initialise(C, mics, with_h=True, device="cuda"):
+    """Initial Q, g (and h) from source-image estimates C [N, F, T, M] (complex64 or complex128;
+    numpy array or torch tensor), by dfm_initialise (Sec. IV-A, steps 3, 5, 6).  Returns torch
+    tensors on `device`: Q [F, sum M_l^2], g [F, N, M], h [N, F, T] (None unless with_h)."""
+    import torch
+    lib_ = load()
+    if not torch.cuda.is_available():
+        raise DFMError(4, "no GPU visible to HIP")
+    dev = torch.device(device)
+    Ct = torch.as_tensor(C)
+    if Ct.dtype not in (torch.complex64, torch.complex128):
+        raise DFMError(1, "C must be complex64 or complex128")
+    Ct = Ct.to(dev).contiguous()
+    N, F, T, M = Ct.shape
+    mics = tuple(int(m) for m in mics)
+    if sum(mics) != M:
+        raise DFMError(2, "sum(mics) != C.shape[3]")
+    dtype = DFM_C64 if Ct.dtype == torch.complex64 else DFM_C128
+    rdt = torch.float32 if dtype == DFM_C64 else torch.float64
+    prob = make_problem(F, T, mics, N, 1, dtype)
+    n = ctypes.c_size_t(0)
+    _check(lib_.dfm_initialise_workspace_size(ctypes.byref(prob), ctypes.byref(n)), "dfm_initialise_workspace_size")
+    ws = torch.empty(n.value + 256, dtype=torch.uint8, device=dev)
+    ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    Q = torch.empty((F, sum(m * m for m in mics)), dtype=Ct.dtype, device=dev)
+    g = torch.empty((F, N, M), dtype=rdt, device=dev)
+    h = torch.empty((N, F, T), dtype=rdt, device=dev) if with_h else None
+    st = lib_.dfm_initialise(ctypes.byref(prob), Ct.data_ptr(), Q.data_ptr(), g.data_ptr(),
+                             h.data_ptr() if with_h else None, ptr, n.value,
+                             torch.cuda.current_stream(dev).cuda_stream)
+    _check(st, "dfm_initialise")
+    return Q, g, h
 
 
 class DistributedFastMNMF:

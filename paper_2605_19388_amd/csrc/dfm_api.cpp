@@ -150,6 +150,8 @@ static dfm_status make_dims(const dfm_problem* p, Dims& d) {
     v += ml * ml * ml;
   }
   d.M = m;
+  d.MLX = 0;
+  for (int l = 0; l < p->L; ++l) d.MLX = std::max(d.MLX, (int)p->mics[l]);
   d.QF = q;
   d.VF = v;
   d.VC = v;
@@ -524,6 +526,35 @@ dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, v
   *avg_ms = n ? total / n : 0.0;
   plan->prof_used = 0;
   return DFM_OK;
+}
+
+dfm_status dfm_initialise_workspace_size(const dfm_problem* p, size_t* bytes) {
+  if (!bytes) return DFM_E_ARG;
+  Dims d;
+  const dfm_status st = dfm::make_dims(p, d);
+  if (st != DFM_OK) return st;
+  if (d.N < 2) return DFM_E_SHAPE;
+  *bytes = dfm::initialise_workspace_bytes(d);
+  return DFM_OK;
+}
+
+dfm_status dfm_initialise(const dfm_problem* p, const void* C, void* Q, void* g, void* h, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  Dims d;
+  const dfm_status st = dfm::make_dims(p, d);
+  if (st != DFM_OK) return st;
+  if (d.N < 2) return DFM_E_SHAPE;
+  if (!C || !Q || !g || !workspace) return DFM_E_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0 || workspace_bytes < dfm::initialise_workspace_bytes(d))
+    return DFM_E_WORKSPACE;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dfm::launch_initialise(d, p->dtype, C, Q, g, h, workspace, s) != hipSuccess) return DFM_E_HIP;
+  int status = 0;
+  if (hipMemcpyAsync(&status, dfm::initialise_status(d, workspace), sizeof(int), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DFM_E_HIP;
+  return status & dfm::kStSingular ? DFM_E_SINGULAR : DFM_OK;
 }
 
 }  // extern "C"

@@ -32,6 +32,7 @@ struct Dims {
   double eps;
   int fast;  // index of the shape-specialised kernel set, or -1 for the generic kernels
   int ML;    // common subarray size when the partition is uniform, else 0
+  int MLX;   // largest subarray size
   int SLP;   // LDS row stride (elements) of per-frame arrays in the specialised kernels
   int TP;    // frames rounded up to 16: row length of the coefficient planes (specialised kernels)
   int SG;    // partial-sum slots per bin of the covariances (S slices, or balanced ranges, below)
@@ -113,5 +114,11 @@ hipError_t launch_clear_status(const Buffers& b, hipStream_t s);  // sticky word
 hipError_t launch_copy_status(const Buffers& b, int* out, hipStream_t s);  // sticky word -> out
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
 hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);
+
+// Initial parameters from source-image estimates (dfm_init.hip).
+size_t initialise_workspace_bytes(const Dims& d);
+hipError_t launch_initialise(const Dims& d, int dtype, const void* C, void* Q, void* g, void* h, void* ws,
+                             hipStream_t s);
+int* initialise_status(const Dims& d, void* ws);  // sticky word inside the workspace
 
 }  // namespace dfm

@@ -88,10 +88,16 @@ __global__ __launch_bounds__(kBlock) void k_ip(Dims d, const double* __restrict_
                                                double* __restrict__ logdet, int* __restrict__ status) {
   const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, bd = blockDim.x;
   const int Ml = d.mics[l], l2 = 2 * Ml, lv = Ml + 1;
-  __shared__ cd sQ[kMaxMl * kMaxMl];      // Q, rows replaced as the sweep goes
-  __shared__ cd sI[kMaxMl * 2 * kMaxMl];  // [Q | I] -> columns Ml .. 2 Ml - 1: Q^{-1}
-  __shared__ cd sV[kMaxMl * (kMaxMl + 1)];  // [V_mu | c]
-  __shared__ cd sc[kMaxMl], sb[kMaxMl], su[kMaxMl];
+  // LDS sized for the partition's largest subarray (ip_smem), so that small blocks keep many
+  // workgroups per CU.
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int mx = d.MLX;
+  cd* sQ = reinterpret_cast<cd*>(smem);  // Q, rows replaced as the sweep goes [mx * mx]
+  cd* sI = sQ + mx * mx;                  // [Q | I] -> columns Ml .. 2 Ml - 1: Q^{-1} [mx * 2 mx]
+  cd* sV = sI + 2 * mx * mx;              // [V_mu | c] [mx * (mx + 1)]
+  cd* sc = sV + mx * (mx + 1);            // [mx] each
+  cd* sb = sc + mx;
+  cd* su = sb + mx;
   __shared__ double s_logabs, s_w2;
   __shared__ int s_sing, s_ok;
 
@@ -486,7 +492,8 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_logdet(Dims d, const cx<R>* __restrict__ Q, double* __restrict__ logdet) {
   const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
   const int Ml = d.mics[l];
-  __shared__ cd sA[kMaxMl * kMaxMl];
+  extern __shared__ __align__(16) unsigned char smem[];
+  cd* sA = reinterpret_cast<cd*>(smem);  // [MLX * MLX]
   __shared__ double s_logabs;
   __shared__ int s_sing;
   const cx<R>* qb = Q + (size_t)f * d.QF + d.qoff[l];
@@ -502,7 +509,8 @@ __global__ __launch_bounds__(kBlock) void k_qinv(Dims d, const cx<R>* __restrict
                                                  int* __restrict__ status) {
   const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, bd = blockDim.x;
   const int Ml = d.mics[l], ld = 2 * Ml;
-  __shared__ cd sA[kMaxMl * 2 * kMaxMl];
+  extern __shared__ __align__(16) unsigned char smem[];
+  cd* sA = reinterpret_cast<cd*>(smem);  // [MLX * 2 MLX]
   __shared__ double s_logabs;
   __shared__ int s_sing;
   const cx<R>* qb = Q + (size_t)f * d.QF + d.qoff[l];
@@ -662,6 +670,14 @@ static size_t smem_h(const Dims& d) {
   return sizeof(R) * d.FB * d.TB * d.N * 2;
 }
 
+// Dynamic LDS of the generic IP sweep, ln|det Q| and Q^{-1} kernels: sized for the largest subarray.
+static size_t ip_smem(const Dims& d) {
+  const size_t m = d.MLX;
+  return sizeof(cd) * (m * m + 2 * m * m + m * (m + 1) + 3 * m);
+}
+static size_t logdet_smem(const Dims& d) { return sizeof(cd) * d.MLX * d.MLX; }
+static size_t qinv_smem(const Dims& d) { return sizeof(cd) * 2 * d.MLX * d.MLX; }
+
 static int ip_threads(const Dims& d) {
   int mx = 1;
   for (int l = 0; l < d.L; ++l) mx = d.mics[l] > mx ? d.mics[l] : mx;
@@ -685,7 +701,7 @@ static hipError_t kernel_impl(const Dims& d, const Buffers& b, int kid, hipStrea
                          static_cast<double*>(b.Vpart));
       break;
     case kKIp:
-      hipLaunchKernelGGL(k_ip<R>, dim3(d.F, d.L), dim3(ip_threads(d)), 0, s, d,
+      hipLaunchKernelGGL(k_ip<R>, dim3(d.F, d.L), dim3(ip_threads(d)), ip_smem(d), s, d,
                          static_cast<const double*>(b.Vpart), Q, b.logdet, b.status);
       break;
     case kKPw:
@@ -723,7 +739,7 @@ static hipError_t nll_impl(const Dims& d, const Buffers& b, hipStream_t s) {
   const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
   hipLaunchKernelGGL(k_nll<R>, dim3(d.F, d.S), dim3(kBlock), 0, s, d, X, Q, static_cast<const R*>(b.W),
                      static_cast<const R*>(b.H), static_cast<const R*>(b.g), b.nllpart);
-  hipLaunchKernelGGL(k_logdet<R>, dim3(d.F, d.L), dim3(ip_threads(d)), 0, s, d, Q, b.logdet);
+  hipLaunchKernelGGL(k_logdet<R>, dim3(d.F, d.L), dim3(ip_threads(d)), logdet_smem(d), s, d, Q, b.logdet);
   return hipGetLastError();
 }
 
@@ -731,7 +747,7 @@ template <typename R>
 static hipError_t sep_impl(const Dims& d, const Buffers& b, void* S, hipStream_t s) {
   const cx<R>* X = static_cast<const cx<R>*>(b.X);
   const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
-  hipLaunchKernelGGL(k_qinv<R>, dim3(d.F, d.L), dim3(ip_threads(d)), 0, s, d, Q, static_cast<cd*>(b.Qinv),
+  hipLaunchKernelGGL(k_qinv<R>, dim3(d.F, d.L), dim3(ip_threads(d)), qinv_smem(d), s, d, Q, static_cast<cd*>(b.Qinv),
                      b.status);
   hipLaunchKernelGGL(k_sep<R>, dim3(d.F, d.S), dim3(kBlock), 0, s, d, X, Q, static_cast<const cd*>(b.Qinv),
                      static_cast<const R*>(b.W), static_cast<const R*>(b.H), static_cast<const R*>(b.g),
