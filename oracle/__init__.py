@@ -12,6 +12,8 @@ does, and has no CPU fallback.
   the appendix theorem's commutator test.
 * ``oracle.init``         -- the initial parameters from source-image estimates
   (Sec. IV-A, steps 3, 5 and 6), pinned by ``tests/test_oracle_init.py``.
+* ``oracle.grad``         -- the cost after unrolled MM iterations written in PyTorch
+  float64 and its gradient by torch.autograd, pinned by ``tests/test_oracle_grad.py``.
 
 Every function is pinned by ``-m "not gpu"`` tests: ``tests/test_oracle_pins.py``
 (brute force, closed forms, special cases, finite-difference identities,
@@ -19,4 +21,4 @@ monotonicity) and ``tests/test_oracle_floors.py`` (the 1e-6 floors of Sec. IV-A
 with each floor active).  ``tests/test_oracle_mutations.py`` plants mistakes in a
 copy of ``dfmnmf.py`` and checks that each one fails a pin.
 """
-from . import conventional, dfmnmf, fullcov, init  # noqa: F401
+from . import conventional, dfmnmf, fullcov, grad, init  # noqa: F401

@@ -1,0 +1,115 @@
+"""Pins of the oracle's gradient of the cost after unrolled MM iterations (oracle/grad.py) --
+CPU only.
+
+* its forward equals the NumPy oracle's MM updates and cost (two independent writings);
+* its gradient equals FP64 central finite differences (step 1e-6) of the NumPy oracle, for every
+  parameter block and the real and imaginary parts of Q, with and without floors active;
+* at an MM fixed point (a recording with |Q x|^2 = y exactly) the gradient with respect to g, W
+  and H is zero, for the cost itself and after any number of unrolled iterations (the MM updates
+  are the identity there and their outputs' adjoints vanish);
+* with no iteration, dL/dW = den_W - num_W of eq. (8) (the MM terms are the cost's gradient).
+"""
+import numpy as np
+import pytest
+
+from oracle import dfmnmf as D
+from oracle import grad as G
+from tests.common import random_state
+from paper_2605_19388_amd import synth
+
+
+def _case(F=2, T=6, mics=(2, 1), N=2, K=2, seed=3, scale=1.0):
+    X = scale * synth.mixture(F, T, mics, N, K, seed)
+    Q, g, W, H = random_state(F, T, mics, N, K, seed + 1)
+    return X, Q, g, W, H
+
+
+def _numpy_unrolled_cost(X, Q, g, W, H, mics, n_iter):
+    P = D.powers(X, Q, mics)
+    for _ in range(n_iter):
+        W = D.update_W(W, H, g, P)
+        H = D.update_H(W, H, g, P)
+        g = D.update_g(W, H, g, P)
+    return D.nll(X, Q, g, W, H, mics)
+
+
+def test_forward_equals_numpy_oracle():
+    X, Q, g, W, H = _case(F=4, T=20, mics=(2, 2), N=3, K=3)
+    mics = (2, 2)
+    gn, Wn, Hn = G.mm_unrolled_state(X, Q, g, W, H, mics, 3)
+    P = D.powers(X, Q, mics)
+    for _ in range(3):
+        W = D.update_W(W, H, g, P)
+        H = D.update_H(W, H, g, P)
+        g = D.update_g(W, H, g, P)
+    np.testing.assert_allclose(gn, g, rtol=1e-12)
+    np.testing.assert_allclose(Wn, W, rtol=1e-12)
+    np.testing.assert_allclose(Hn, H, rtol=1e-12)
+    L, *_ = G.mm_unrolled_grad(X, Q, *(a for a in (g, W, H)), mics, 0)
+    assert abs(L - D.nll(X, Q, g, W, H, mics)) <= 1e-12 * abs(L)
+
+
+def _fd_check(X, Q, g, W, H, mics, n_iter, samples=6, seed=0, rtol=1e-5):
+    L, dQ, dg, dW, dH = G.mm_unrolled_grad(X, Q, g, W, H, mics, n_iter)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = {"Q": Q, "g": g, "W": W, "H": H}
+    grads = {"Q": dQ, "g": dg, "W": dW, "H": dH}
+    scale = max(abs(L), 1.0)
+    for name, p in params.items():
+        for _ in range(samples):
+            idx = tuple(int(rng.integers(0, s)) for s in p.shape)
+            parts = [(1.0, "re"), (1j, "im")] if np.iscomplexobj(p) else [(1.0, "re")]
+            for unit, part in parts:
+                h = 1e-6 * (abs(p[idx]) if p[idx] != 0 else 1.0)  # step 1e-6 relative to the entry
+                args = {k: v.copy() for k, v in params.items()}
+                args[name][idx] += unit * h
+                lp = _numpy_unrolled_cost(X, args["Q"], args["g"], args["W"], args["H"], mics, n_iter)
+                args[name][idx] -= 2 * unit * h
+                lm = _numpy_unrolled_cost(X, args["Q"], args["g"], args["W"], args["H"], mics, n_iter)
+                fd = (lp - lm) / (2 * h)
+                got = grads[name][idx].real if part == "re" else grads[name][idx].imag
+                assert abs(got - fd) <= rtol * max(abs(fd), 1e-3 * scale / p.size), (name, idx, part, got, fd)
+
+
+@pytest.mark.parametrize("n_iter", [0, 1, 3])
+def test_gradient_equals_central_finite_differences(n_iter):
+    X, Q, g, W, H = _case()
+    _fd_check(X, Q, g, W, H, (2, 1), n_iter)
+
+
+def test_gradient_equals_finite_differences_with_floors_active():
+    """A faint recording with a small model: y floored at some bins, the g denominators floored."""
+    X, Q, g, W, H = _case(scale=1e-3)
+    W, H = 3e-4 * W, 3e-4 * H
+    y = D.model_variance(D.source_psd(W, H), g)
+    assert np.any(y == D.EPS) and np.any(y > D.EPS)
+    _fd_check(X, Q, g, W, H, (2, 1), 2, seed=1)
+
+
+def _fixed_point_case(F=3, T=8, mics=(2, 2), N=2, K=2, seed=9):
+    """Q = I and x_ftm = sqrt(y_ftm) e^{i phi}: P = y, so every MM update is the identity."""
+    _, g, W, H = random_state(F, T, mics, N, K, seed)
+    Q = synth.initial_state(F, T, mics, N, K, seed)[0]
+    y = D.model_variance(D.source_psd(W, H), g)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = np.sqrt(y) * np.exp(2j * np.pi * rng.random(y.shape))
+    return X, Q, g, W, H, mics
+
+
+@pytest.mark.parametrize("n_iter", [0, 2])
+def test_gradient_vanishes_at_an_mm_fixed_point(n_iter):
+    X, Q, g, W, H, mics = _fixed_point_case()
+    np.testing.assert_allclose(D.update_W(W, H, g, D.powers(X, Q, mics)), W, rtol=1e-12)
+    L, dQ, dg, dW, dH = G.mm_unrolled_grad(X, Q, g, W, H, mics, n_iter)
+    for name, d, p in (("g", dg, g), ("W", dW, W), ("H", dH, H)):
+        assert np.abs(d * p).max() <= 1e-10 * abs(L), name   # relative to the cost's scale
+
+
+def test_direct_gradient_is_den_minus_num():
+    X, Q, g, W, H = _case(F=3, T=10, mics=(2, 2), N=2, K=3)
+    mics = (2, 2)
+    _, _, dg, dW, dH = G.mm_unrolled_grad(X, Q, g, W, H, mics, 0)
+    P = D.powers(X, Q, mics)
+    for d, terms in ((dW, D.mm_terms_W), (dH, D.mm_terms_H), (dg, D.mm_terms_g)):
+        num, den = terms(W, H, g, P)
+        np.testing.assert_allclose(d, den - num, rtol=1e-10, atol=1e-12)
