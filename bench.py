@@ -65,6 +65,9 @@ def parse():
                     help="iterations of the single-thread oracle leg")
     ap.add_argument("--gram-bf16", action="store_true",
                     help="covariances of eq. (14) from BF16 operands on the matrix cores (FP32 sums)")
+    ap.add_argument("--grad", type=int, default=0, metavar="N",
+                    help="time the gradient of the cost after N unrolled MM iterations (forward with "
+                         "checkpoints + hand-written reverse pass) and print its own JSON line")
     ap.add_argument("--no-graph", action="store_true",
                     help="plain kernel launches instead of HIP graph replays (for comparison)")
     ap.add_argument("--cpu-threads", type=int, default=0,
@@ -267,10 +270,48 @@ def _live_kernel_times(p, one_step, steps, iters, kernels):
     return out
 
 
+def grad_timing(args):
+    """Whole-job time of the unrolled-MM gradient on the workload: reset, N MM iterations with
+    per-iteration checkpoints, the cost, the reverse pass (FP64 internally)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_19388_amd import DistributedFastMNMF, synth
+
+    w = synth.make(args.workload)
+    F, T, M, N, K, mics = w["F"], w["T"], w["M"], w["N"], w["K"], w["mics"]
+    dev = torch.device("cuda:0")
+    p = DistributedFastMNMF(w["X"].astype(np.complex64), mics, N, K, W=w["W"].astype(np.float32),
+                            H=w["H"].astype(np.float32), Q=w["Q"].astype(np.complex64), g=w["g"].astype(np.float32),
+                            device=dev)
+    init = {k: getattr(p, k).clone() for k in ("Q", "g", "W", "H")}
+
+    def one():
+        for k, v in init.items():
+            getattr(p, k).copy_(v)
+        tape = p.mm_forward(args.grad)
+        cost = p.nll()
+        return cost, p.mm_backward(tape)
+
+    for _ in range(max(args.warmup, 1)):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"mode": "grad", "workload": w["name"], "mm_iterations": args.grad, "ms_per_gradient": round(1e3 * dt, 3),
+                      "gradients_per_s": round(1.0 / dt, 2), "dtype": "f32 state, f64 reverse pass"}), flush=True)
+
+
 def main():
     args = parse()
     if args.mixtures > 1:
         cold_mixtures(args)
+        return
+    if args.grad > 0:
+        grad_timing(args)
         return
     if args.pmc_summary:
         copy_mb = args.copy_mb or 256

@@ -185,6 +185,27 @@ dfm_status dfm_profile_kernel(dfm_plan* plan, int32_t kernel, int32_t max_launch
  * the number of profiled launches since the last read, and reset the count. */
 dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, void* stream);
 
+/* ---- Gradient of the cost after unrolled MM iterations.
+ * The map: from the plan's state (Q, g, W, H), n_iter iterations of the MM updates
+ * (8), (9), (10) in that order with Q held fixed (P = |Q x|^2 fixed, y refreshed
+ * after each update, every Sec. IV-A floor in place), then the cost (13).
+ * dfm_mm_forward runs those iterations on the plan's kernels (updating g, W, H in
+ * place) and stores the state (g, W, H) before each iteration in `tape` (per-
+ * iteration checkpoints).  dfm_mm_backward, called after it with the same n_iter
+ * and tape and with the state it left, computes by hand-written reverse-mode
+ * kernels (FP64 internally) the gradient of that cost with respect to the state
+ * before the forward: dQ [F][sum_l M_l^2] complex = dL/dRe Q + i dL/dIm Q, dg
+ * [F][N][M], dW [N][F][K], dH [N][K][T] real (plan precision, caller-owned,
+ * written entirely).  A floored quantity has zero derivative where its floor is
+ * active.  n_iter = 0 gives the gradient of the cost at the current state (at a
+ * fixed point of (8)-(10), dg = dW = dH = 0).  The tape (caller-owned, 256-byte
+ * aligned, >= dfm_mm_tape_size bytes) also holds the reverse pass's FP64 work
+ * arrays.  Asynchronous; the IP sweep (14)-(16) is not part of the map. */
+dfm_status dfm_mm_tape_size(const dfm_plan* plan, int32_t n_iter, size_t* bytes);
+dfm_status dfm_mm_forward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* stream);
+dfm_status dfm_mm_backward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* dQ, void* dg,
+                           void* dW, void* dH, void* stream);
+
 /* ---- Initial parameters from estimates of the source images (Sec. IV-A, steps 3, 5, 6).
  * The paper initialises from source images estimated by time-frequency masking
  * (its steps 1-2) and factorises the initial spectrograms by IS-NMF (step 4);

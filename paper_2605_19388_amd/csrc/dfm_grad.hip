@@ -1,0 +1,521 @@
+// Gradient of the cost (13) after n unrolled MM iterations (eqs. (8), (9), (10) in that order,
+// Q held fixed, the Sec. IV-A floors in place) with respect to the state the iterations started
+// from: reverse-mode, hand-written, in FP64 whatever the plan's precision.
+//
+// The forward iterations run on the plan's own kernels and store the state (g, W, H) before each
+// iteration in the caller's tape (per-iteration checkpoints).  The reverse pass then starts from
+// the cost's gradient at the final state and walks the iterations backwards; for each it
+// recomputes, from that iteration's checkpoint, the intermediate sums of (8)-(10) and goes back
+// through the g, H and W updates in turn.  With theta' = theta sqrt(a / max(b, eps)) (a, b the
+// numerator and denominator sums of the update) and theta'bar the adjoint of the updated value:
+//   abar = theta'bar theta' / (2 a),  bbar = -theta'bar theta' / (2 max(b, eps)) [b > eps],
+//   thetabar (direct) = theta'bar sqrt(a / max(b, eps)),
+// and the sums carry abar, bbar back to the per-frame quantities: y (through P / y^2 and 1 / y;
+// y = max(u, eps), u = sum_n lambda g, has zero derivative where floored), P, lambda = W H and g.
+// The adjoint of P accumulates over all iterations (Q is fixed, so P is one quantity), and the
+// gradient with respect to Q comes last:
+//   dL/dRe Q + i dL/dIm Q = 2 sum_t Pbar z conj(x) - 2T Q^-H  (per block, z = Q x).
+//
+// Kernels (one workgroup per bin where a bin's frames are reduced, so every sum has a fixed
+// order and the result is reproducible):
+//   kb_powers  P = |Q x|^2 in FP64;
+//   kb_coef    c = sum_m g P / y^2, d = sum_m g / y per (f, t, n) (the W and H sums' planes);
+//   kb_sum_t   out[n][f][k] (+)= sum_t A1[n][k][t] C1[f][t][n] + A2 C2;
+//   kb_sum_f   out[n][k][t] (+)= sum_f A1[n][f][k] C1[f][t][n] + A2 C2;
+//   kb_cbar    out[f][t][n] = sum_k A1[n][f][k] B1[n][k][t] (and a second pair);
+//   kb_apply / kb_mmback  the update theta' and its adjoint split (elementwise);
+//   kb_frame   per bin, frames in chunks: the per-frame adjoints of one update (or of the cost),
+//              Pbar += ..., lambdabar, and the sums over frames into g's adjoint;
+//   kb_qgrad   the gradient with respect to Q.
+#include <hip/hip_runtime.h>
+
+#include "dfm_device.h"
+
+namespace dfm {
+namespace grad {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ double dsqrt_ratio(double a, double b, double eps) { return sqrt(a / (b > eps ? b : eps)); }
+
+template <typename R>
+__global__ __launch_bounds__(kB) void kb_powers(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+                                                double* __restrict__ P) {
+  const int f = blockIdx.x, t = blockIdx.y * kB + threadIdx.x;
+  if (t >= d.T) return;
+  const cx<R>* x = X + ((size_t)f * d.T + t) * d.M;
+  const cx<R>* qf = Q + (size_t)f * d.QF;
+  double* p = P + ((size_t)f * d.T + t) * d.M;
+  for (int l = 0; l < d.L; ++l) {
+    const int ml = d.mics[l], o = d.moff[l], q0 = d.qoff[l];
+    for (int mu = 0; mu < ml; ++mu) {
+      double zr = 0.0, zi = 0.0;
+      for (int c = 0; c < ml; ++c) {
+        const double qr = qf[q0 + mu * ml + c].re, qi = qf[q0 + mu * ml + c].im;
+        const double xr = x[o + c].re, xi = x[o + c].im;
+        zr += qr * xr - qi * xi;
+        zi += qr * xi + qi * xr;
+      }
+      p[o + mu] = zr * zr + zi * zi;
+    }
+  }
+}
+
+// lambda_n at (f, t) from W (row of bin f staged in sW [N][K]) and H [N][K][T].
+template <typename RH>
+__device__ __forceinline__ double lam_at(const Dims& d, const double* sW, const RH* __restrict__ H, int n, int t) {
+  double acc = 0.0;
+  const RH* hn = H + (size_t)n * d.K * d.T + t;
+  for (int k = 0; k < d.K; ++k) acc += sW[n * d.K + k] * (double)hn[(size_t)k * d.T];
+  return acc;
+}
+
+template <typename RW, typename RG>
+__device__ __forceinline__ void stage_bin(const Dims& d, const RW* __restrict__ W, const RG* __restrict__ g, int f,
+                                          double* sW, double* sg) {
+  for (int i = threadIdx.x; i < d.N * d.K; i += blockDim.x) {
+    const int n = i / d.K, k = i - n * d.K;
+    sW[i] = (double)W[((size_t)n * d.F + f) * d.K + k];
+  }
+  for (int i = threadIdx.x; i < d.N * d.M; i += blockDim.x) sg[i] = (double)g[(size_t)f * d.N * d.M + i];
+}
+
+// c[f][t][n] = sum_m g P / y^2, d[f][t][n] = sum_m g / y for the state (W, H, g); grid (F, T / kB).
+template <typename RW, typename RH, typename RG>
+__global__ __launch_bounds__(kB) void kb_coef(Dims d, const RW* __restrict__ W, const RH* __restrict__ H,
+                                              const RG* __restrict__ g, const double* __restrict__ P,
+                                              double* __restrict__ c, double* __restrict__ dd) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sW = reinterpret_cast<double*>(smem);
+  double* sg = sW + d.N * d.K;
+  const int f = blockIdx.x, t = blockIdx.y * kB + threadIdx.x;
+  stage_bin(d, W, g, f, sW, sg);
+  __syncthreads();
+  if (t >= d.T) return;
+  double lam[kMaxN];
+  for (int n = 0; n < d.N; ++n) lam[n] = lam_at(d, sW, H, n, t);
+  double cn[kMaxN], dn[kMaxN];
+  for (int n = 0; n < d.N; ++n) cn[n] = dn[n] = 0.0;
+  const double* p = P + ((size_t)f * d.T + t) * d.M;
+  for (int m = 0; m < d.M; ++m) {
+    double u = 0.0;
+    for (int n = 0; n < d.N; ++n) u += lam[n] * sg[n * d.M + m];
+    const double y = u > d.eps ? u : d.eps, iy = 1.0 / y, w = p[m] * iy * iy;
+    for (int n = 0; n < d.N; ++n) {
+      cn[n] += sg[n * d.M + m] * w;
+      dn[n] += sg[n * d.M + m] * iy;
+    }
+  }
+  for (int n = 0; n < d.N; ++n) {
+    c[((size_t)f * d.T + t) * d.N + n] = cn[n];
+    dd[((size_t)f * d.T + t) * d.N + n] = dn[n];
+  }
+}
+
+// out[n][f][k] (+)= sum_t A1[n][k][t] C1[f][t][n] + A2[n][k][t] C2[f][t][n]; A of type RA.
+template <typename RA>
+__global__ __launch_bounds__(kB) void kb_sum_t(Dims d, const RA* __restrict__ A1, const double* __restrict__ C1,
+                                               const RA* __restrict__ A2, const double* __restrict__ C2,
+                                               double* __restrict__ out, int accumulate) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= d.N * d.F * d.K) return;
+  const int n = i / (d.F * d.K), r = i - n * d.F * d.K, f = r / d.K, k = r - f * d.K;
+  const RA* a1 = A1 + ((size_t)n * d.K + k) * d.T;
+  const RA* a2 = A2 ? A2 + ((size_t)n * d.K + k) * d.T : nullptr;
+  double acc = 0.0;
+  for (int t = 0; t < d.T; ++t) {
+    const size_t ci = ((size_t)f * d.T + t) * d.N + n;
+    acc += (double)a1[t] * C1[ci];
+    if (a2) acc += (double)a2[t] * C2[ci];
+  }
+  out[i] = accumulate ? out[i] + acc : acc;
+}
+
+// out[n][k][t] (+)= sum_f A1[n][f][k] C1[f][t][n] + A2[n][f][k] C2[f][t][n].
+template <typename RA>
+__global__ __launch_bounds__(kB) void kb_sum_f(Dims d, const RA* __restrict__ A1, const double* __restrict__ C1,
+                                               const RA* __restrict__ A2, const double* __restrict__ C2,
+                                               double* __restrict__ out, int accumulate) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= d.N * d.K * d.T) return;
+  const int n = i / (d.K * d.T), r = i - n * d.K * d.T, k = r / d.T, t = r - k * d.T;
+  double acc = 0.0;
+  for (int f = 0; f < d.F; ++f) {
+    const size_t ai = ((size_t)n * d.F + f) * d.K + k, ci = ((size_t)f * d.T + t) * d.N + n;
+    acc += (double)A1[ai] * C1[ci];
+    if (A2) acc += (double)A2[ai] * C2[ci];
+  }
+  out[i] = accumulate ? out[i] + acc : acc;
+}
+
+// out[f][t][n] = sum_k A[n][f][k] B[n][k][t] for (A1, B1) -> out1 and (A2, B2) -> out2.
+template <typename RA, typename RB>
+__global__ __launch_bounds__(kB) void kb_cbar(Dims d, const RA* __restrict__ A1, const RB* __restrict__ B1,
+                                              const RA* __restrict__ A2, const RB* __restrict__ B2,
+                                              double* __restrict__ out1, double* __restrict__ out2) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= d.F * d.T * d.N) return;
+  const int f = i / (d.T * d.N), r = i - f * d.T * d.N, t = r / d.N, n = r - t * d.N;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = 0; k < d.K; ++k) {
+    const size_t ai = ((size_t)n * d.F + f) * d.K + k, bi = ((size_t)n * d.K + k) * d.T + t;
+    s1 += (double)A1[ai] * (double)B1[bi];
+    s2 += (double)A2[ai] * (double)B2[bi];
+  }
+  out1[i] = s1;
+  out2[i] = s2;
+}
+
+// theta1 = theta sqrt(a / max(b, eps)).
+template <typename R>
+__global__ __launch_bounds__(kB) void kb_apply(int n, const R* __restrict__ th, const double* __restrict__ a,
+                                               const double* __restrict__ b, double eps, double* __restrict__ th1) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i < n) th1[i] = (double)th[i] * dsqrt_ratio(a[i], b[i], eps);
+}
+
+// Adjoint of theta1 = theta sqrt(a / max(b, eps)) with theta1bar in acc: abar, bbar, and
+// acc <- the direct part of thetabar.
+template <typename R>
+__global__ __launch_bounds__(kB) void kb_mmback(int n, const R* __restrict__ th, const double* __restrict__ a,
+                                                const double* __restrict__ b, double eps, double* __restrict__ acc,
+                                                double* __restrict__ abar, double* __restrict__ bbar) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const double bb = b[i] > eps ? b[i] : eps, r = sqrt(a[i] / bb), t1 = (double)th[i] * r, tb = acc[i];
+  abar[i] = a[i] > 0.0 ? tb * t1 / (2.0 * a[i]) : 0.0;
+  bbar[i] = b[i] > eps ? -tb * t1 / (2.0 * bb) : 0.0;
+  acc[i] = tb * r;
+}
+
+// Modes of kb_frame.
+enum { kCost = 0, kFwdG = 1, kBackG = 2, kBackWH = 3 };
+
+// One workgroup per bin, frames in chunks of CH: phase 1 one thread per frame (per-frame
+// adjoints, Pbar, lambdabar; the terms that sum over frames go to LDS), phase 2 one thread per
+// (n, m) adding the chunk's terms in frame order.
+//   kCost:   L's own gradient: ybar = 1/y - P/y^2, Pbar = 1/y (written), lambdabar, gout = g's.
+//   kFwdG:   the sums of eq. (10): gout = sum_t lambda P / y^2, gout2 = sum_t lambda / y.
+//   kBackG:  coefficients abar, bbar [F][N][M] of eq. (10): ybar, Pbar +=, lambdabar, gout +=.
+//   kBackWH: coefficients cbar, dbar [F][T][N] of eq. (8) or (9): ybar, Pbar +=, lambdabar, gout +=.
+template <typename RW, typename RH, typename RG, int MODE>
+__global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W, const RH* __restrict__ H,
+                                               const RG* __restrict__ g, const double* __restrict__ P,
+                                               const double* __restrict__ c1, const double* __restrict__ c2,
+                                               double* __restrict__ Pbar, double* __restrict__ lbar,
+                                               double* __restrict__ gout, double* __restrict__ gout2, int CH) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = d.N, M = d.M, f = blockIdx.x, tid = threadIdx.x;
+  double* sW = reinterpret_cast<double*>(smem);  // [N][K]
+  double* sg = sW + N * d.K;                      // [N][M]
+  double* sa = sg + N * M;                        // kBackG: abar [N][M]
+  double* sb = sa + N * M;                        // kBackG: bbar [N][M]
+  double* sl = sb + N * M;                        // [CH][N]: lambda
+  double* su = sl + CH * N;                       // [CH][M]: ubar (floored y: 0)
+  double* sy = su + CH * M;                       // [CH][M]: 1 / y
+  double* sp = sy + CH * M;                       // [CH][M]: P / y^2
+  double* sc = sp + CH * M;                       // [CH][N]: cbar (kBackWH)
+  double* sd = sc + CH * N;                       // [CH][N]: dbar (kBackWH)
+  for (int i = tid; i < N * d.K; i += kB) {
+    const int n = i / d.K, k = i - n * d.K;
+    sW[i] = (double)W[((size_t)n * d.F + f) * d.K + k];
+  }
+  for (int i = tid; i < N * M; i += kB) {
+    sg[i] = (double)g[(size_t)f * N * M + i];
+    if (MODE == kBackG) {
+      sa[i] = c1[(size_t)f * N * M + i];
+      sb[i] = c2[(size_t)f * N * M + i];
+    }
+  }
+  double acc1[4] = {0, 0, 0, 0}, acc2[4] = {0, 0, 0, 0};  // phase 2: this thread's (n, m) entries
+  __syncthreads();
+  for (int t0 = 0; t0 < d.T; t0 += CH) {
+    const int nt = min(CH, d.T - t0);
+    if (tid < nt) {
+      const int t = t0 + tid;
+      const size_t ft = (size_t)f * d.T + t;
+      double lam[kMaxN], lb[kMaxN], cb[kMaxN], db[kMaxN];
+      for (int n = 0; n < N; ++n) {
+        lam[n] = lam_at(d, sW, H, n, t);
+        lb[n] = 0.0;
+        if (MODE == kBackWH) {
+          cb[n] = c1[ft * N + n];
+          db[n] = c2[ft * N + n];
+        }
+      }
+      for (int m = 0; m < M; ++m) {
+        double u = 0.0;
+        for (int n = 0; n < N; ++n) u += lam[n] * sg[n * M + m];
+        const bool live = u > d.eps;
+        const double y = live ? u : d.eps, iy = 1.0 / y, pm = P[ft * M + m], py2 = pm * iy * iy;
+        double ybar = 0.0, pbar = 0.0;
+        if (MODE == kCost) {
+          ybar = iy - py2;
+          pbar = iy;
+        } else if (MODE == kBackG) {
+          for (int n = 0; n < N; ++n) {
+            const double a = sa[n * M + m], b = sb[n * M + m];
+            ybar += lam[n] * (a * (-2.0 * py2 * iy) - b * iy * iy);
+            pbar += a * lam[n] * iy * iy;
+            lb[n] += a * py2 + b * iy;
+          }
+        } else if (MODE == kBackWH) {
+          for (int n = 0; n < N; ++n) {
+            const double gg = sg[n * M + m];
+            ybar += gg * (cb[n] * (-2.0 * py2 * iy) - db[n] * iy * iy);
+            pbar += cb[n] * gg * iy * iy;
+          }
+        }
+        const double ubar = live ? ybar : 0.0;
+        if (MODE != kFwdG) {
+          for (int n = 0; n < N; ++n) lb[n] += ubar * sg[n * M + m];
+          if (MODE == kCost)
+            Pbar[ft * M + m] = pbar;
+          else
+            Pbar[ft * M + m] += pbar;
+        }
+        su[tid * M + m] = ubar;
+        sy[tid * M + m] = iy;
+        sp[tid * M + m] = py2;
+      }
+      for (int n = 0; n < N; ++n) {
+        sl[tid * N + n] = lam[n];
+        if (MODE == kBackWH) {
+          sc[tid * N + n] = cb[n];
+          sd[tid * N + n] = db[n];
+        }
+        if (MODE != kFwdG) lbar[ft * N + n] = lb[n];
+      }
+    }
+    __syncthreads();
+    for (int e = 0; e < 4; ++e) {  // (n, m) entries tid, tid + kB, ... (N M <= 4 kB)
+      const int i = tid + e * kB;
+      if (i >= N * M) break;
+      const int n = i / M, m = i - n * M;
+      double s1 = 0.0, s2 = 0.0;
+      for (int j = 0; j < nt; ++j) {
+        const double lam = sl[j * N + n];
+        if (MODE == kFwdG) {
+          s1 += lam * sp[j * M + m];
+          s2 += lam * sy[j * M + m];
+        } else if (MODE == kBackWH) {
+          s1 += sc[j * N + n] * sp[j * M + m] + sd[j * N + n] * sy[j * M + m] + su[j * M + m] * lam;
+        } else {
+          s1 += su[j * M + m] * lam;
+        }
+      }
+      acc1[e] += s1;
+      acc2[e] += s2;
+    }
+    __syncthreads();
+  }
+  for (int e = 0; e < 4; ++e) {
+    const int i = tid + e * kB;
+    if (i >= N * M) break;
+    const size_t o = (size_t)f * N * M + i;
+    if (MODE == kFwdG) {
+      gout[o] = acc1[e];
+      gout2[o] = acc2[e];
+    } else if (MODE == kCost) {
+      gout[o] = acc1[e];
+    } else {
+      gout[o] += acc1[e];
+    }
+  }
+}
+
+// dL/dRe Q + i dL/dIm Q per (f, l) block: 2 sum_t Pbar z conj(x) - 2T Q^-H; Qinv from k_qinv.
+template <typename R>
+__global__ __launch_bounds__(kB) void kb_qgrad(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+                                               const cd* __restrict__ Qinv, const double* __restrict__ Pbar,
+                                               cx<R>* __restrict__ dQ) {
+  const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
+  const int ml = d.mics[l], o = d.moff[l], q0 = d.qoff[l];
+  const cx<R>* qf = Q + (size_t)f * d.QF + q0;
+  for (int i = tid; i < ml * ml; i += kB) {  // entry (mu, c)
+    const int mu = i / ml, c = i - mu * ml;
+    double ar = 0.0, ai = 0.0;
+    for (int t = 0; t < d.T; ++t) {
+      const cx<R>* x = X + ((size_t)f * d.T + t) * d.M + o;
+      double zr = 0.0, zi = 0.0;
+      for (int b = 0; b < ml; ++b) {
+        const double qr = qf[mu * ml + b].re, qi = qf[mu * ml + b].im, xr = x[b].re, xi = x[b].im;
+        zr += qr * xr - qi * xi;
+        zi += qr * xi + qi * xr;
+      }
+      const double pb = Pbar[((size_t)f * d.T + t) * d.M + o + mu], xr = x[c].re, xi = x[c].im;
+      ar += pb * (zr * xr + zi * xi);  // Re(z conj(x_c))
+      ai += pb * (zi * xr - zr * xi);  // Im(z conj(x_c))
+    }
+    const cd qi = Qinv[(size_t)f * d.QF + q0 + c * ml + mu];  // (Q^-1)_{c mu}; (Q^-H)_{mu c} = conj
+    dQ[(size_t)f * d.QF + q0 + i] = {(R)(2.0 * ar - 2.0 * d.T * qi.re), (R)(2.0 * ai + 2.0 * d.T * qi.im)};
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kB) void kb_store(int n, const double* __restrict__ src, R* __restrict__ dst) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i < n) dst[i] = (R)src[i];
+}
+
+}  // namespace grad
+
+// ---- Tape layout: checkpoints (plan precision), then FP64 work arrays.
+struct GradTape {
+  void* ckg;  // [n_iter][F N M]
+  void* ckW;  // [n_iter][N F K]
+  void* ckH;  // [n_iter][N K T]
+  double *P, *Pbar, *lbar, *c0, *d0, *c1, *d1, *cb, *db;           // [F][T][M] / [F][T][N]
+  double *aW, *bW, *aWb, *bWb, *W1, *Wacc;                        // [N][F][K]
+  double *aH, *bH, *aHb, *bHb, *H1, *Hacc;                        // [N][K][T]
+  double *ag, *bg, *agb, *bgb, *gacc;                             // [F][N][M]
+};
+
+static size_t alg(size_t x) { return (x + 255) / 256 * 256; }
+
+static size_t carve_tape(const Dims& d, int dtype, int n_iter, char* base, GradTape* t) {
+  const size_t r = dtype == DFM_C64 ? 4 : 8;
+  const size_t NG = (size_t)d.F * d.N * d.M, NW = (size_t)d.N * d.F * d.K, NH = (size_t)d.N * d.K * d.T;
+  const size_t FTM = (size_t)d.F * d.T * d.M, FTN = (size_t)d.F * d.T * d.N;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += alg(bytes);
+    return p;
+  };
+  GradTape tt;
+  tt.ckg = take(r * NG * n_iter);
+  tt.ckW = take(r * NW * n_iter);
+  tt.ckH = take(r * NH * n_iter);
+  double** ftm[] = {&tt.P, &tt.Pbar};
+  for (double** p : ftm) *p = reinterpret_cast<double*>(take(8 * FTM));
+  double** ftn[] = {&tt.lbar, &tt.c0, &tt.d0, &tt.c1, &tt.d1, &tt.cb, &tt.db};
+  for (double** p : ftn) *p = reinterpret_cast<double*>(take(8 * FTN));
+  double** nw[] = {&tt.aW, &tt.bW, &tt.aWb, &tt.bWb, &tt.W1, &tt.Wacc};
+  for (double** p : nw) *p = reinterpret_cast<double*>(take(8 * NW));
+  double** nh[] = {&tt.aH, &tt.bH, &tt.aHb, &tt.bHb, &tt.H1, &tt.Hacc};
+  for (double** p : nh) *p = reinterpret_cast<double*>(take(8 * NH));
+  double** ng[] = {&tt.ag, &tt.bg, &tt.agb, &tt.bgb, &tt.gacc};
+  for (double** p : ng) *p = reinterpret_cast<double*>(take(8 * NG));
+  if (t) *t = tt;
+  return off;
+}
+
+size_t grad_tape_bytes(const Dims& d, int dtype, int n_iter) { return carve_tape(d, dtype, n_iter, nullptr, nullptr); }
+
+void grad_checkpoints(const Dims& d, int dtype, int n_iter, void* tape, int it, void** g, void** W, void** H) {
+  GradTape t;
+  carve_tape(d, dtype, n_iter, static_cast<char*>(tape), &t);
+  const size_t r = dtype == DFM_C64 ? 4 : 8;
+  *g = static_cast<char*>(t.ckg) + r * (size_t)d.F * d.N * d.M * it;
+  *W = static_cast<char*>(t.ckW) + r * (size_t)d.N * d.F * d.K * it;
+  *H = static_cast<char*>(t.ckH) + r * (size_t)d.N * d.K * d.T * it;
+}
+
+static unsigned nblk(size_t n) { return (unsigned)((n + grad::kB - 1) / grad::kB); }
+
+// Chunk of frames of kb_frame: as many as fit 48 KB of LDS next to the bin's W, g, abar, bbar.
+static int frame_chunk(const Dims& d) {
+  const size_t fixed = 8 * ((size_t)d.N * d.K + 3 * (size_t)d.N * d.M);
+  const size_t per = 8 * (3 * (size_t)d.N + 3 * (size_t)d.M);
+  size_t ch = fixed < 48 * 1024 ? (48 * 1024 - fixed) / per : 1;
+  if (ch > (size_t)grad::kB) ch = grad::kB;
+  return ch < 1 ? 1 : (int)ch;
+}
+static size_t frame_smem(const Dims& d, int ch) {
+  return 8 * ((size_t)d.N * d.K + 3 * (size_t)d.N * d.M + (size_t)ch * (3 * d.N + 3 * d.M));
+}
+
+template <typename R>
+static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, void* tape, void* dQ, void* dg,
+                                void* dW, void* dH, hipStream_t s) {
+  using namespace grad;
+  const int dtype = sizeof(R) == 4 ? DFM_C64 : DFM_C128;
+  GradTape t;
+  carve_tape(d, dtype, n_iter, static_cast<char*>(tape), &t);
+  const cx<R>* X = static_cast<const cx<R>*>(b.X);
+  const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
+  const int NG = d.F * d.N * d.M, NW = d.N * d.F * d.K, NH = d.N * d.K * d.T, FTN = d.F * d.T * d.N;
+  const int CH = frame_chunk(d);
+  const size_t fsm = frame_smem(d, CH), csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
+  const dim3 ft(d.F, (d.T + kB - 1) / kB), blk(kB);
+  const dim3 gW(nblk(NW)), gH(nblk(NH)), gG(nblk(NG)), gFTN(nblk(FTN));
+  const double* nul = nullptr;
+  hipLaunchKernelGGL(kb_powers<R>, ft, blk, 0, s, d, X, Q, t.P);
+  // The cost's own gradient at the final state (the plan's current g, W, H).
+  const R* gK = static_cast<const R*>(b.g);
+  const R* WK = static_cast<const R*>(b.W);
+  const R* HK = static_cast<const R*>(b.H);
+  hipLaunchKernelGGL((kb_frame<R, R, R, kCost>), dim3(d.F), blk, fsm, s, d, WK, HK, gK, t.P, nul, nul, t.Pbar,
+                     t.lbar, t.gacc, (double*)nullptr, CH);
+  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, HK, t.lbar, (const R*)nullptr, nul, t.Wacc, 0);
+  hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, WK, t.lbar, (const R*)nullptr, nul, t.Hacc, 0);
+  for (int it = n_iter - 1; it >= 0; --it) {
+    void *pg, *pW, *pH;
+    grad_checkpoints(d, dtype, n_iter, tape, it, &pg, &pW, &pH);
+    const R* g0 = static_cast<const R*>(pg);
+    const R* W0 = static_cast<const R*>(pW);
+    const R* H0 = static_cast<const R*>(pH);
+    // This iteration's forward from its checkpoint, in FP64: W1 (eq. (8)), H1 (eq. (9)), the sums
+    // of eq. (10).  (gacc, Wacc, Hacc) hold the adjoints of the iteration's output (g1, W1, H1).
+    hipLaunchKernelGGL((kb_coef<R, R, R>), ft, blk, csm, s, d, W0, H0, g0, t.P, t.c0, t.d0);
+    hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.c0, (const R*)nullptr, nul, t.aW, 0);
+    hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.d0, (const R*)nullptr, nul, t.bW, 0);
+    hipLaunchKernelGGL(kb_apply<R>, gW, blk, 0, s, NW, W0, t.aW, t.bW, d.eps, t.W1);
+    hipLaunchKernelGGL((kb_coef<double, R, R>), ft, blk, csm, s, d, (const double*)t.W1, H0, g0, t.P, t.c1, t.d1);
+    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.c1, (const double*)nullptr, nul,
+                       t.aH, 0);
+    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.d1, (const double*)nullptr, nul,
+                       t.bH, 0);
+    hipLaunchKernelGGL(kb_apply<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.H1);
+    hipLaunchKernelGGL((kb_frame<double, double, R, kFwdG>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1,
+                       (const double*)t.H1, g0, t.P, nul, nul, (double*)nullptr, (double*)nullptr, t.ag, t.bg, CH);
+    // Back through eq. (10): g1 = g0 sqrt(ag / max(bg, eps)) with lambda2 = W1 H1.
+    hipLaunchKernelGGL(kb_mmback<R>, gG, blk, 0, s, NG, g0, t.ag, t.bg, d.eps, t.gacc, t.agb, t.bgb);
+    hipLaunchKernelGGL((kb_frame<double, double, R, kBackG>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1,
+                       (const double*)t.H1, g0, t.P, (const double*)t.agb, (const double*)t.bgb, t.Pbar, t.lbar,
+                       t.gacc, (double*)nullptr, CH);
+    hipLaunchKernelGGL(kb_sum_t<double>, gW, blk, 0, s, d, (const double*)t.H1, t.lbar, (const double*)nullptr, nul,
+                       t.Wacc, 1);
+    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
+                       t.Hacc, 1);
+    // Back through eq. (9): H1 = H0 sqrt(aH / max(bH, eps)), aH = sum_f W1 c1, bH = sum_f W1 d1.
+    hipLaunchKernelGGL(kb_mmback<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.Hacc, t.aHb, t.bHb);
+    hipLaunchKernelGGL(kb_sum_t<double>, gW, blk, 0, s, d, (const double*)t.aHb, t.c1, (const double*)t.bHb, t.d1,
+                       t.Wacc, 1);
+    hipLaunchKernelGGL((kb_cbar<double, double>), gFTN, blk, 0, s, d, (const double*)t.W1, (const double*)t.aHb,
+                       (const double*)t.W1, (const double*)t.bHb, t.cb, t.db);
+    hipLaunchKernelGGL((kb_frame<double, R, R, kBackWH>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1, H0, g0,
+                       t.P, (const double*)t.cb, (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
+    hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
+    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
+                       t.Hacc, 1);
+    // Back through eq. (8): W1 = W0 sqrt(aW / max(bW, eps)), aW = sum_t H0 c0, bW = sum_t H0 d0.
+    hipLaunchKernelGGL(kb_mmback<R>, gW, blk, 0, s, NW, W0, t.aW, t.bW, d.eps, t.Wacc, t.aWb, t.bWb);
+    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.aWb, t.c0, (const double*)t.bWb, t.d0,
+                       t.Hacc, 1);
+    hipLaunchKernelGGL((kb_cbar<double, R>), gFTN, blk, 0, s, d, (const double*)t.aWb, H0, (const double*)t.bWb, H0,
+                       t.cb, t.db);
+    hipLaunchKernelGGL((kb_frame<R, R, R, kBackWH>), dim3(d.F), blk, fsm, s, d, W0, H0, g0, t.P,
+                       (const double*)t.cb, (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
+    hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
+    hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
+  }
+  // The gradient with respect to Q: Q^-1 by the generic elimination kernel, then the sums over frames.
+  hipError_t e = launch_qinv(d, b, dtype, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_qgrad<R>, dim3(d.F, d.L), blk, 0, s, d, X, Q, static_cast<const cd*>(b.Qinv), t.Pbar,
+                     static_cast<cx<R>*>(dQ));
+  hipLaunchKernelGGL(kb_store<R>, gG, blk, 0, s, NG, (const double*)t.gacc, static_cast<R*>(dg));
+  hipLaunchKernelGGL(kb_store<R>, gW, blk, 0, s, NW, (const double*)t.Wacc, static_cast<R*>(dW));
+  hipLaunchKernelGGL(kb_store<R>, gH, blk, 0, s, NH, (const double*)t.Hacc, static_cast<R*>(dH));
+  return hipGetLastError();
+}
+
+hipError_t launch_mm_backward(const Dims& d, const Buffers& b, int dtype, int n_iter, void* tape, void* dQ,
+                              void* dg, void* dW, void* dH, hipStream_t s) {
+  return dtype == DFM_C64 ? backward_impl<float>(d, b, n_iter, tape, dQ, dg, dW, dH, s)
+                          : backward_impl<double>(d, b, n_iter, tape, dQ, dg, dW, dH, s);
+}
+
+}  // namespace dfm

@@ -115,6 +115,14 @@ hipError_t launch_copy_status(const Buffers& b, int* out, hipStream_t s);  // st
 hipError_t launch_separate(const Dims& d, const Buffers& b, int dtype, void* S, hipStream_t s);
 hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* V, hipStream_t s);
 
+hipError_t launch_qinv(const Dims& d, const Buffers& b, int dtype, hipStream_t s);  // Q^-1 -> b.Qinv (generic)
+
+// Gradient of the cost after unrolled MM iterations (dfm_grad.hip).
+size_t grad_tape_bytes(const Dims& d, int dtype, int n_iter);
+void grad_checkpoints(const Dims& d, int dtype, int n_iter, void* tape, int it, void** g, void** W, void** H);
+hipError_t launch_mm_backward(const Dims& d, const Buffers& b, int dtype, int n_iter, void* tape, void* dQ,
+                              void* dg, void* dW, void* dH, hipStream_t s);
+
 // Initial parameters from source-image estimates (dfm_init.hip).
 size_t initialise_workspace_bytes(const Dims& d);
 hipError_t launch_initialise(const Dims& d, int dtype, const void* C, void* Q, void* g, void* h, void* ws,

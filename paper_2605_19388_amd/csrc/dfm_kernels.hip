@@ -787,6 +787,16 @@ hipError_t launch_copy_status(const Buffers& b, int* out, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_qinv(const Dims& d, const Buffers& b, int dtype, hipStream_t s) {
+  if (dtype == DFM_C64)
+    hipLaunchKernelGGL(k_qinv<float>, dim3(d.F, d.L), dim3(ip_threads(d)), qinv_smem(d), s, d,
+                       static_cast<const cx<float>*>(b.Q), static_cast<cd*>(b.Qinv), b.status);
+  else
+    hipLaunchKernelGGL(k_qinv<double>, dim3(d.F, d.L), dim3(ip_threads(d)), qinv_smem(d), s, d,
+                       static_cast<const cx<double>*>(b.Q), static_cast<cd*>(b.Qinv), b.status);
+  return hipGetLastError();
+}
+
 hipError_t launch_clear_status(const Buffers& b, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.status, 1);
   return hipGetLastError();

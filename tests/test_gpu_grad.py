@@ -1,0 +1,175 @@
+"""Gradient of the cost after unrolled MM iterations (Q fixed) on the GPU -- the library's
+hand-written reverse pass -- against the oracle's (oracle/grad.py, PyTorch float64 autograd of a
+plain forward, itself pinned by finite differences), through the C ABI (GPU only).
+
+Each block of the gradient is compared entry by entry relative to the block's largest entry.
+FP64 plans: <= 1e-12 (rounding of the forward trajectory and of the reverse sums; measured
+3e-15).  FP32 plans: the checkpoints come from the FP32 forward (inputs and state rounded to FP32)
+and the reverse pass recomputes in FP64 from them; <= 2e-6 (measured 3.5e-7), each case's error
+reported.  At the full C4 shape (F=513, T=625, 4 x 4 mics, N=5, K=16, 10 iterations) the oracle's
+dense einsums do not fit in memory, so there the FP64 plan's gradient is checked by central
+differences of its own forward and the FP32 plan's against it."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dfmnmf as D
+from oracle import grad as G
+from paper_2605_19388_amd import synth
+from tests.common import random_state
+from tests.gpu_common import announce, as_precision, plan, report, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu(request):
+    require_gpu()
+    announce(request.node.nodeid)
+    yield
+    torch.cuda.synchronize()
+
+
+def _problem(F, T, mics, N, K, seed, fp32, mixing="delay"):
+    X = synth.mixture(F, T, mics, N, K, seed, mixing=mixing)
+    Q, g, W, H = random_state(F, T, mics, N, K, seed + 1)
+    return tuple(as_precision(a, fp32) for a in (X, Q, g, W, H))
+
+
+def _block_err(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def _gpu_grad(X, Q, g, W, H, mics, N, K, fp32, n_iter):
+    p = plan(X, mics, N, K, Q, g, W, H, fp32)
+    tape = p.mm_forward(n_iter)
+    cost = p.nll()
+    grads = p.mm_backward(tape)
+    torch.cuda.synchronize()
+    return cost, [t.cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64) for t in grads]
+
+
+CASES = [(7, 40, (2, 3), 3, 4), (9, 50, (4, 4, 4, 4), 5, 16), (5, 33, (2, 2), 2, 4), (4, 30, (16,), 3, 4)]
+
+
+@pytest.mark.parametrize("n_iter", [0, 1, 3])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[2])))
+def test_gradient_matches_oracle(case, fp32, n_iter):
+    F, T, mics, N, K = case
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=17, fp32=fp32)
+    cost, (dQ, dg, dW, dH) = _gpu_grad(X, Q, g, W, H, mics, N, K, fp32, n_iter)
+    L, rQ, rg, rW, rH = G.mm_unrolled_grad(X, Q, g, W, H, mics, n_iter)
+    errs = {k: _block_err(a, b) for k, a, b in (("Q", dQ, rQ), ("g", dg, rg), ("W", dW, rW), ("H", dH, rH))}
+    ec = abs(cost - L) / max(abs(L), F * T * sum(mics))
+    report(f"mm gradient {case} {'fp32' if fp32 else 'fp64'} n={n_iter}: cost {ec:.1e}; " +
+           ", ".join(f"d{k} {v:.1e}" for k, v in errs.items()))
+    tol = 2e-6 if fp32 else 1e-12
+    assert ec < (1e-5 if fp32 else 1e-12)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+
+
+def test_gradient_vanishes_at_an_mm_fixed_point():
+    """|Q x|^2 = y: every MM update is the identity, and dL/dg = dL/dW = dL/dH = 0 for the cost
+    and after unrolled iterations (the stationarity of the MM fixed point)."""
+    F, T, mics, N, K = 6, 40, (4, 4, 4, 4), 5, 16
+    _, g, W, H = random_state(F, T, mics, N, K, 9)
+    Q = synth.initial_state(F, T, mics, N, K, 9)[0]
+    y = D.model_variance(D.source_psd(W, H), g)
+    rng = np.random.Generator(np.random.PCG64(9))
+    X = np.sqrt(y) * np.exp(2j * np.pi * rng.random(y.shape))
+    for n_iter in (0, 2):
+        cost, (dQ, dg, dW, dH) = _gpu_grad(X, Q, g, W, H, mics, N, K, False, n_iter)
+        worst = max(np.abs(d * p).max() for d, p in ((dg, g), (dW, W), (dH, H))) / abs(cost)
+        report(f"mm fixed point n={n_iter}: max |theta dL/dtheta| / |L| = {worst:.1e}")
+        assert worst <= 1e-11
+
+
+def test_autograd_function_and_finite_differences():
+    """unrolled_mm_cost(...).backward() gives the library's gradient, and it matches FP64 central
+    differences (step 1e-6 relative) of the library's own forward for a few entries of each block."""
+    from paper_2605_19388_amd.autograd import unrolled_mm_cost
+    F, T, mics, N, K = 5, 30, (2, 3), 2, 3
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=23, fp32=False, mixing="iid")
+    dev = torch.device("cuda:0")
+    ts = {k: torch.tensor(v, device=dev, requires_grad=True) for k, v in (("Q", Q), ("g", g), ("W", W), ("H", H))}
+    Xt = torch.tensor(X, device=dev)
+    n_iter = 2
+    L = unrolled_mm_cost(Xt, ts["Q"], ts["g"], ts["W"], ts["H"], mics, n_iter)
+    L.backward()
+    _, ref = _gpu_grad(X, Q, g, W, H, mics, N, K, False, n_iter)
+    for (k, t), r in zip(ts.items(), ref):
+        np.testing.assert_array_equal(t.grad.cpu().numpy(), r)
+
+    def cost_at(**kw):
+        st = dict(Q=Q, g=g, W=W, H=H)
+        st.update(kw)
+        p = plan(X, mics, N, K, st["Q"], st["g"], st["W"], st["H"], False)
+        p.mm_forward(n_iter)
+        return p.nll()
+    rng = np.random.Generator(np.random.PCG64(5))
+    for k, v in (("Q", Q), ("g", g), ("W", W), ("H", H)):
+        grad = ts[k].grad.cpu().numpy()
+        for _ in range(3):
+            idx = tuple(int(rng.integers(0, s)) for s in v.shape)
+            for unit in ((1.0, 1j) if np.iscomplexobj(v) else (1.0,)):
+                h = 1e-6 * abs(v[idx])
+                vp, vm = v.copy(), v.copy()
+                vp[idx] += unit * h
+                vm[idx] -= unit * h
+                fd = (cost_at(**{k: vp}) - cost_at(**{k: vm})) / (2 * h)
+                got = grad[idx].real if unit == 1.0 else grad[idx].imag
+                assert abs(got - fd) <= 1e-5 * max(abs(fd), 1e-3 * abs(float(L)) / v.size), (k, idx, unit, got, fd)
+
+
+def test_backward_is_deterministic():
+    F, T, mics, N, K = 9, 50, (4, 4, 4, 4), 5, 16
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=31, fp32=True)
+    _, a = _gpu_grad(X, Q, g, W, H, mics, N, K, True, 3)
+    _, b = _gpu_grad(X, Q, g, W, H, mics, N, K, True, 3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_full_size_gradient_c4():
+    """C4: paper_4x4 (F=513, T=625, four 4-mic subarrays, N=5, K=16), 10 unrolled MM iterations.
+    The FP64 plan's gradient against FP64 central differences of the FP64 plan's forward at
+    sampled entries of every block; the FP32 plan's gradient against the FP64 plan's, per block."""
+    w = synth.make("paper_4x4")
+    mics, N, K, n_iter = w["mics"], w["N"], w["K"], 10
+    X, Q, g, W, H = (as_precision(w[k], True) for k in ("X", "Q", "g", "W", "H"))
+    Q = as_precision(random_state(w["F"], w["T"], mics, N, K, 77)[0], True)  # a general, non-identity Q
+    c64, (d64Q, d64g, d64W, d64H) = _gpu_grad(X, Q, g, W, H, mics, N, K, False, n_iter)
+    c32, g32 = _gpu_grad(X, Q, g, W, H, mics, N, K, True, n_iter)
+    errs = {k: _block_err(a, b) for k, a, b in zip("QgWH", g32, (d64Q, d64g, d64W, d64H))}
+    report("C4 full size, FP32 plan vs FP64 plan gradient: " + ", ".join(f"d{k} {v:.1e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= 1e-4, (k, v)
+
+    def cost_at(**kw):
+        st = dict(Q=Q, g=g, W=W, H=H)
+        st.update(kw)
+        p = plan(X, mics, N, K, st["Q"], st["g"], st["W"], st["H"], False)
+        p.mm_forward(n_iter)
+        return p.nll()
+    rng = np.random.Generator(np.random.PCG64(8))
+    worst = 0.0
+    # Step 1e-3 relative here: the cost is about 2.5e7 while a derivative can be of order 1, so the
+    # FP64 rounding of the cost (about 1e-8 absolute after 5.1 M terms) over a 1e-6 step would
+    # swamp it (2e-4 relative was measured with a 1e-5 step); the central difference's truncation
+    # error at 1e-3 is about 1e-6 relative.  The 1e-6 step is used at the small sizes above.
+    for k, v, grad in (("Q", Q, d64Q), ("g", g, d64g), ("W", W, d64W), ("H", H, d64H)):
+        for _ in range(2):
+            idx = tuple(int(rng.integers(0, s)) for s in v.shape)
+            for unit in ((1.0, 1j) if np.iscomplexobj(v) else (1.0,)):
+                h = 1e-3 * abs(v[idx])
+                vp, vm = v.copy(), v.copy()
+                vp[idx] += unit * h
+                vm[idx] -= unit * h
+                fd = (cost_at(**{k: vp}) - cost_at(**{k: vm})) / (2 * h)
+                got = grad[idx].real if unit == 1.0 else grad[idx].imag
+                e = abs(got - fd) / max(abs(fd), 1e-3 * np.abs(grad).max())
+                worst = max(worst, e)
+                assert e <= 1e-4, (k, idx, unit, got, fd)
+    report(f"C4 full size, FP64 plan gradient vs central differences: worst {worst:.1e}")
