@@ -65,6 +65,10 @@ def parse():
                     help="iterations of the single-thread oracle leg")
     ap.add_argument("--gram-bf16", action="store_true",
                     help="covariances of eq. (14) from BF16 operands on the matrix cores (FP32 sums)")
+    ap.add_argument("--batch", type=int, default=0, metavar="B",
+                    help="B uneven mixtures (2-8 subarrays of 4 mics, N in {3, 5, 8}, T in [200, 2000], F=513, "
+                         "K=16, complex64), tiles from the autotuner, stepped as one batch of graph replays and "
+                         "one after another; prints its own JSON line")
     ap.add_argument("--grad", type=int, default=0, metavar="N",
                     help="time the gradient of the cost after N unrolled MM iterations (forward with "
                          "checkpoints + hand-written reverse pass) and print its own JSON line")
@@ -305,8 +309,86 @@ def grad_timing(args):
                       "gradients_per_s": round(1.0 / dt, 2), "dtype": "f32 state, f64 reverse pass"}), flush=True)
 
 
+def batch_timing(args):
+    """Batched against one-after-another stepping of B uneven mixtures (the same plans, tiles from
+    the autotuner), `--iters` iterations (default 100) per step."""
+    import numpy as np
+    import torch
+
+    from paper_2605_19388_amd import autotune, binding, synth
+
+    B, iters = args.batch, args.iters or 100
+    rng = np.random.Generator(np.random.PCG64(1000))
+    shapes = [(513, int(rng.integers(200, 2001)), (4,) * int(rng.integers(2, 9)), int(rng.choice([3, 5, 8])), 16)
+              for _ in range(B)]
+    # Tiles per shape class, tuned on a 65-bin excerpt of each class (the tile sets the frames per
+    # workgroup of the per-frame kernels, which depends on T, N and M, not on F).
+    t0 = time.perf_counter()
+    tiles = {}
+    for F, T, mics, N, K in shapes:
+        key = autotune.shape_key(F, T, mics, N, K)
+        if key not in tiles:
+            tiles[key], _ = autotune.tune(65, T, mics, N, K, iters=2, reps=1)
+            if len(tiles) % 8 == 0:
+                log(f"[bench] {len(tiles)} shape classes tuned")
+    log(f"[bench] {len(tiles)} shape classes tuned in {time.perf_counter() - t0:.1f} s")
+    plans = []
+    for b, (F, T, mics, N, K) in enumerate(shapes):
+        if b % 8 == 0:
+            log(f"[bench] drawing mixture {b} of {B}")
+        X = synth.mixture(F, T, mics, N, K, 1000 + b, mixing="delay").astype(np.complex64)
+        Q, g, W, H = synth.initial_state(F, T, mics, N, K, 2000 + b)
+        plans.append(binding.DistributedFastMNMF(X, mics, N, K, W=W.astype(np.float32), H=H.astype(np.float32),
+                                                 Q=Q.astype(np.complex64), g=g.astype(np.float32),
+                                                 tile=tiles[autotune.shape_key(F, T, mics, N, K)]))
+        del X
+    fast = sum(1 for p in plans if p.kernel_names()[0].endswith("_f"))
+    log(f"[bench] {B} mixtures ({fast} on the specialised kernels), {iters} iterations per step")
+    init = [{k: getattr(p, k).clone() for k in ("Q", "g", "W", "H")} for p in plans]
+
+    def reset():
+        for p, st in zip(plans, init):
+            for k, v in st.items():
+                getattr(p, k).copy_(v)
+
+    batch = binding.Batch(plans)
+    reset()
+    batch.step(2)
+    for p in plans:
+        p.step(2)
+    torch.cuda.synchronize()
+    res = {}
+    for mode in ("batched", "one_after_another"):
+        ts = []
+        for _ in range(max(args.steps, 1)):
+            reset()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if mode == "batched":
+                batch.step(iters)
+            else:
+                for p in plans:
+                    p.step(iters)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        res[mode] = min(ts)
+    bins = sum(F * T * sum(m) for F, T, m, _, _ in shapes)
+    for p in plans:
+        p.sync_status()
+    out = {"mode": "batch", "mixtures": B, "specialised": fast, "iterations": iters,
+           "shape_classes": len(tiles),
+           "batched_s": round(res["batched"], 4), "one_after_another_s": round(res["one_after_another"], 4),
+           "speedup": round(res["one_after_another"] / res["batched"], 3),
+           "mixture_iterations_per_s": round(B * iters / res["batched"], 1),
+           "bins_per_s": round(bins * iters / res["batched"], 1)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.batch > 0:
+        batch_timing(args)
+        return
     if args.mixtures > 1:
         cold_mixtures(args)
         return

@@ -96,6 +96,9 @@ typedef struct {
   double eps;                       /* floor on the model variance, the MM denominators
                                        and the IP normaliser (1e-6 in Sec. IV-A); > 0 */
   uint32_t flags;                   /* DFM_F_* bits; unknown bits are DFM_E_ARG */
+  int32_t tile;                     /* largest frames per slice of the streaming kernels:
+                                       0 (= 128), 16, 32, 64 or 128, else DFM_E_ARG (a
+                                       performance choice; results stay within rounding) */
 } dfm_problem;
 
 typedef struct dfm_plan dfm_plan;   /* opaque host-side handle */
@@ -254,6 +257,22 @@ dfm_status dfm_initialise(const dfm_problem* p, const void* C, void* Q, void* g,
 #define DFM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 dfm_status dfm_run_noalloc(const dfm_problem* p, const void* X, void* Q, void* g, void* W, void* H,
                            int32_t n_iter, double* cost, int32_t* status, void* stream);
+
+/* ---- Many mixtures at once.
+ * A batch steps several independent plans (any shapes, precisions and tiles; one
+ * device) together: dfm_batch_step captures, once per batch, the kernels of all
+ * plans' iterations into HIP graphs in which each plan is its own branch (so the
+ * mixtures' kernels may run concurrently and fill the chip), and replays them on
+ * `stream`: the first iteration (with each plan's lambda seed), later iterations
+ * singly and in groups of eight, and the plans' final g updates.  Each plan's
+ * result is bit for bit what dfm_step(plan, n_iter) gives.  The batch borrows the
+ * plans (they must outlive it, each in at most one batch at a time, and not be
+ * stepped otherwise while the batch runs).  dfm_batch_create copies the plan
+ * pointers; count in 1..4096. */
+typedef struct dfm_batch dfm_batch;
+dfm_status dfm_batch_create(dfm_batch** out, dfm_plan* const* plans, int32_t count);
+dfm_status dfm_batch_step(dfm_batch* batch, int32_t n_iter, void* stream);
+void dfm_batch_destroy(dfm_batch* batch);
 
 /* Free the host-side plan.  Does not touch the caller's device buffers. */
 void dfm_destroy(dfm_plan* plan);

@@ -39,15 +39,15 @@ class Problem(ctypes.Structure):
     _fields_ = [("F", ctypes.c_int32), ("T", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("mics", ctypes.c_int32 * MAX_SUBARRAYS), ("dtype", ctypes.c_int32),
-                ("eps", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("eps", ctypes.c_double), ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32)]
 
 
 _lib = None
 EXPORTS = ("dfm_workspace_size", "dfm_init", "dfm_step", "dfm_substep", "dfm_nll", "dfm_nll_trace", "dfm_separate",
            "dfm_covariances", "dfm_sync_status", "dfm_kernel_times", "dfm_profile_kernel", "dfm_profile_read",
            "dfm_kernel_count", "dfm_kernel_name", "dfm_run_noalloc", "dfm_initialise_workspace_size",
-           "dfm_initialise", "dfm_mm_tape_size", "dfm_mm_forward", "dfm_mm_backward", "dfm_destroy",
-           "dfm_status_string")
+           "dfm_initialise", "dfm_mm_tape_size", "dfm_mm_forward", "dfm_mm_backward", "dfm_batch_create",
+           "dfm_batch_step", "dfm_batch_destroy", "dfm_destroy", "dfm_status_string")
 
 
 def load(path: str = LIB_PATH):
@@ -76,6 +76,10 @@ def load(path: str = LIB_PATH):
     lib.dfm_initialise_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.dfm_initialise.argtypes = [P, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.dfm_mm_tape_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.dfm_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32]
+    lib.dfm_batch_step.argtypes = [vp, i32, vp]
+    lib.dfm_batch_destroy.argtypes = [vp]
+    lib.dfm_batch_destroy.restype = None
     lib.dfm_mm_forward.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
     lib.dfm_mm_backward.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp, vp, vp, vp]
     lib.dfm_kernel_count.argtypes = [vp]
@@ -87,7 +91,7 @@ def load(path: str = LIB_PATH):
     lib.dfm_status_string.argtypes = [st]
     lib.dfm_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("dfm_kernel_count", "dfm_kernel_name", "dfm_destroy", "dfm_status_string"):
+        if name not in ("dfm_kernel_count", "dfm_kernel_name", "dfm_destroy", "dfm_batch_destroy", "dfm_status_string"):
             getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -97,7 +101,7 @@ def lib():
     return load()
 
 
-def make_problem(F, T, mics, N, K, dtype=DFM_C64, eps=1e-6, flags=0) -> Problem:
+def make_problem(F, T, mics, N, K, dtype=DFM_C64, eps=1e-6, flags=0, tile=0) -> Problem:
     p = Problem()
     p.F, p.T, p.N, p.K, p.L = int(F), int(T), int(N), int(K), len(mics)
     if len(mics) > MAX_SUBARRAYS:
@@ -107,6 +111,7 @@ def make_problem(F, T, mics, N, K, dtype=DFM_C64, eps=1e-6, flags=0) -> Problem:
     p.dtype = int(dtype)
     p.eps = float(eps)
     p.flags = int(flags)
+    p.tile = int(tile)
     return p
 
 
@@ -137,6 +142,33 @@ def check_output(out, shape, dtype, device):
         raise DFMError(1, f"out is on {out.device}, expected {device}")
     if not out.is_contiguous():
         raise DFMError(1, "out must be contiguous")
+
+
+class Batch:
+    """Steps several DistributedFastMNMF plans together (dfm_batch_*): one graph launch per phase
+    runs every plan's kernels, each plan a branch of the graph.  Each plan's result equals its own
+    step(n) bit for bit.  Keeps references to the plans."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._plan.value for p in self.plans])
+        self._b = ctypes.c_void_p()
+        _check(load().dfm_batch_create(ctypes.byref(self._b), arr, len(self.plans)), "dfm_batch_create")
+
+    def step(self, n_iter: int = 1):
+        _check(load().dfm_batch_step(self._b, int(n_iter), self.plans[0]._stream()), "dfm_batch_step")
+        return self
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            load().dfm_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def initialise(C, mics, with_h=True, device="cuda"):
@@ -183,7 +215,7 @@ class DistributedFastMNMF:
     tensors owned by this object and is updated in place by ``step``.
     """
 
-    def __init__(self, X, mics, n_src, n_basis, W, H, Q=None, g=None, eps=1e-6, device="cuda", flags=0):
+    def __init__(self, X, mics, n_src, n_basis, W, H, Q=None, g=None, eps=1e-6, device="cuda", flags=0, tile=0):
         import torch
 
         self._torch = torch
@@ -220,7 +252,7 @@ class DistributedFastMNMF:
                              ("W", self.W, (self.N, F, self.K)), ("H", self.H, (self.N, self.K, T))):
             if tuple(t.shape) != shp:
                 raise DFMError(2, f"{name} has shape {tuple(t.shape)}, expected {shp}")
-        self.problem = make_problem(F, T, self.mics, self.N, self.K, self.dtype, eps, flags)
+        self.problem = make_problem(F, T, self.mics, self.N, self.K, self.dtype, eps, flags, tile)
         nbytes = workspace_size(self.problem)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         off = (-self._ws.data_ptr()) % 256

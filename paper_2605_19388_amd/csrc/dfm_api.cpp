@@ -35,13 +35,6 @@ namespace dfm {
 static size_t real_size(int dtype) { return dtype == DFM_C64 ? 4 : 8; }
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
-// Largest frames per slice to try (tile-size tuning): DFM_SLICE in the environment, else 128.
-static int max_slice() {
-  const char* e = std::getenv("DFM_SLICE");
-  const int v = e ? std::atoi(e) : 128;
-  return v == 16 || v == 32 || v == 64 ? v : 128;
-}
-
 // Specialised path: uniform partition with a compiled (N, K, M_l) set.  Frames per slice:
 // the largest of max_slice(), ..., 16 whose LDS needs fit 64 KB in every kernel.
 // Compute units of the current device (the balanced covariance kernel sizes its grid to it).
@@ -61,7 +54,7 @@ static bool choose_fast(Dims& d, int dtype) {
   if (set < 0) return false;
   d.fast = set;
   d.ML = ml;
-  for (int sl = max_slice(); sl >= 16; sl /= 2) {
+  for (int sl = d.tile; sl >= 16; sl /= 2) {
     d.S = (d.T + sl - 1) / sl;
     d.SL = (d.T + d.S - 1) / d.S;
     d.SLP = ((d.SL + 3) & ~3) + 4;
@@ -101,7 +94,7 @@ static bool choose_fast(Dims& d, int dtype) {
 static void choose_tiles(Dims& d, int dtype) {
   const size_t r = real_size(dtype), c = 2 * r;
   const size_t budget = 48 * 1024;
-  int sl = 128;
+  int sl = d.tile;
   for (; sl > 8; sl /= 2) {
     const size_t gram = r * (d.N * d.K + d.N * d.M + sl * d.M) + 16 + c * sl * d.M;
     const size_t pw = c * d.QF + 16 + r * (d.N * d.K + d.N * d.M + sl * d.N * 2);
@@ -135,6 +128,8 @@ static dfm_status make_dims(const dfm_problem* p, Dims& d) {
   d.L = p->L;
   d.eps = p->eps;
   d.flags = (int)p->flags;
+  if (p->tile != 0 && p->tile != 16 && p->tile != 32 && p->tile != 64 && p->tile != 128) return DFM_E_ARG;
+  d.tile = p->tile ? p->tile : 128;
   d.check = (p->flags & DFM_F_CHECK_FINITE) != 0;
   int m = 0, q = 0, v = 0;
   for (int l = 0; l < p->L; ++l) {
@@ -658,6 +653,126 @@ dfm_status dfm_run_noalloc(const dfm_problem* p, const void* X, void* Q, void* g
     return DFM_E_HIP;
   if (status && dfm::launch_copy_status(plan.b, status, s) != hipSuccess) return DFM_E_HIP;
   return DFM_OK;
+}
+
+}  // extern "C"
+
+// ---- Batches: all plans' iterations captured into one graph per phase, each plan a branch
+// forked from and joined into the capture's origin stream.
+struct dfm_batch {
+  std::vector<dfm_plan*> plans;
+  std::vector<hipStream_t> streams;  // one capture branch per plan
+  hipStream_t origin = nullptr;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  // [0] lambda seeds + first iteration, [1] one later iteration, [2] kGraphBatch later ones,
+  // [3] the final g updates (plans whose g update is finished by the next covariance kernel).
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace dfm {
+
+static void free_batch(dfm_batch* b) {
+  for (hipGraphExec_t& g : b->graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->origin) (void)hipStreamDestroy(b->origin);
+  delete b;
+}
+
+// What plan p enqueues in phase `which` on stream s.
+static hipError_t batch_phase(dfm_plan* p, int which, hipStream_t s) {
+  const bool trace = (p->d.flags & DFM_F_TRACE_NLL) != 0;
+  hipError_t e = hipSuccess;
+  switch (which) {
+    case 0:
+      if (p->d.fast >= 0) e = run_kernel(p, kFLam, s);
+      if (e == hipSuccess) e = enqueue_iteration(p, true, s);
+      return e;
+    case 1: return enqueue_iteration(p, false, s);
+    case 2:
+      for (int r = 0; r < kGraphBatch && e == hipSuccess; ++r) e = enqueue_iteration(p, false, s);
+      return e;
+    default:
+      if (g_update_deferred(p->d) && !trace) e = run_kernel(p, kFGFin, s);
+      return e;
+  }
+}
+
+static hipError_t capture_batch(dfm_batch* b, int which) {
+  hipError_t e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b->fork, b->origin);
+  for (size_t i = 0; i < b->plans.size() && e == hipSuccess; ++i) {
+    e = hipStreamWaitEvent(b->streams[i], b->fork, 0);
+    if (e == hipSuccess) e = batch_phase(b->plans[i], which, b->streams[i]);
+    if (e == hipSuccess) e = hipEventRecord(b->joins[i], b->streams[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->origin, b->joins[i], 0);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(b->origin, &g);
+  if (e == hipSuccess) e = ee;
+  if (e == hipSuccess && g) e = hipGraphInstantiate(&b->graph[which], g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) b->graph[which] = nullptr;
+  return e;
+}
+
+}  // namespace dfm
+
+extern "C" {
+
+dfm_status dfm_batch_create(dfm_batch** out, dfm_plan* const* plans, int32_t count) {
+  if (!out || !plans || count < 1 || count > 4096) return DFM_E_ARG;
+  *out = nullptr;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!plans[i]) return DFM_E_ARG;
+    for (int32_t j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return DFM_E_ARG;
+  }
+  dfm_batch* b = new (std::nothrow) dfm_batch;
+  if (!b) return DFM_E_ARG;
+  b->plans.assign(plans, plans + count);
+  bool ok = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int32_t i = 0; i < count && ok; ++i) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    if (ok) b->streams.push_back(s);
+    ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (ok) b->joins.push_back(e);
+  }
+  if (!ok) {
+    dfm::free_batch(b);
+    return DFM_E_HIP;
+  }
+  *out = b;
+  return DFM_OK;
+}
+
+dfm_status dfm_batch_step(dfm_batch* batch, int32_t n_iter, void* stream) {
+  if (!batch || n_iter < 0) return DFM_E_ARG;
+  if (n_iter == 0) return DFM_OK;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  auto launch = [&](int which) -> bool {
+    if (!batch->graph[which] && dfm::capture_batch(batch, which) != hipSuccess) return false;
+    return hipGraphLaunch(batch->graph[which], s) == hipSuccess;
+  };
+  if (!launch(0)) return DFM_E_HIP;
+  int left = n_iter - 1;
+  while (left > 0) {
+    const int which = left >= dfm::kGraphBatch ? 2 : 1;
+    if (!launch(which)) return DFM_E_HIP;
+    left -= which == 2 ? dfm::kGraphBatch : 1;
+  }
+  return launch(3) ? DFM_OK : DFM_E_HIP;
+}
+
+void dfm_batch_destroy(dfm_batch* batch) {
+  if (batch) dfm::free_batch(batch);
 }
 
 void dfm_destroy(dfm_plan* plan) {

@@ -2039,8 +2039,9 @@ struct Set {
 }  // namespace fast
 
 // Compiled sets (index, N, K, M_l, L); index = Dims::fast.
-#define DFM_FAST_SETS(X) \
-  X(0, 2, 4, 2, 2) X(1, 5, 16, 4, 4) X(2, 5, 16, 16, 1) X(3, 3, 16, 4, 2) X(4, 8, 16, 4, 3) X(5, 3, 16, 4, 3)
+#define DFM_FAST_SETS(X)                                                                            \
+  X(0, 2, 4, 2, 2) X(1, 5, 16, 4, 4) X(2, 5, 16, 16, 1) X(3, 3, 16, 4, 2) X(4, 8, 16, 4, 3) X(5, 3, 16, 4, 3) \
+  X(6, 5, 16, 4, 2) X(7, 8, 16, 4, 2) X(8, 5, 16, 4, 3) X(9, 3, 16, 4, 4) X(10, 8, 16, 4, 4)
 
 hipError_t fast_finish(const Dims& d, const Buffers& b, int dtype, bool separate, void* S, hipStream_t s) {
   switch (d.fast) {

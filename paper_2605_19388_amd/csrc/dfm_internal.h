@@ -45,6 +45,7 @@ struct Dims {
   int gpend;  // k_gramd_f finishes the previous iteration's g update (set inside dfm_step only)
   int check;  // DFM_F_CHECK_FINITE: updated W, H, g are checked for NaN / Inf
   int flags;  // dfm_problem.flags
+  int tile;   // largest frames per slice (16, 32, 64 or 128)
   int mics[kMaxL];  // M_l
   int moff[kMaxL];  // first mic of subarray l
   int qoff[kMaxL];  // offset of block l in a frequency's packed Q (complex units)
