@@ -61,8 +61,9 @@ static bool choose_fast(Dims& d, int dtype) {
     d.TB = 16;
     d.TBN = (d.T + 15) / 16;
     d.TP = (d.T + 15) & ~15;
-    // k_gramd_f: as many workgroups as fit on the chip at once share the F*T frames equally;
-    // a bin then has one partial-sum slot per workgroup that touched it.
+    // k_gramd_f: as many workgroups as fit on the chip at once share the F*T frames equally:
+    // the same number per bin (Dims::GSB) when that is at least two, else equal flattened
+    // ranges; a bin then has one partial-sum slot per workgroup that touched it.
     if (dtype == DFM_C64 && (ml == 2 || ml == 4)) {
       const long long total = (long long)d.F * d.T;
       const int per_cu = fast_gramd_blocks_per_cu(d);
@@ -70,6 +71,13 @@ static bool choose_fast(Dims& d, int dtype) {
       d.GR = (int)std::max<long long>((total + want - 1) / want, 32);
       d.GW = (int)((total + d.GR - 1) / d.GR);
       d.SG = (d.T + d.GR - 1) / d.GR + 1;
+      d.GSB = 0;
+      const int per_bin = (int)std::min<long long>(want / d.F, d.T / 32);  // parts of >= 32 frames
+      if (per_bin >= 2) {
+        d.GSB = per_bin;
+        d.GW = d.F * d.GSB;
+        d.SG = d.GSB;
+      }
     } else {
       d.GR = 0;
       d.GW = 0;

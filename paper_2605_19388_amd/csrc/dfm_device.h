@@ -69,6 +69,7 @@ __device__ __forceinline__ void packed_pair(int Ml, int j, int& a, int& b, int& 
 // covariance kernel (ranges of GR flattened frames), one per workgroup that touched f.
 __device__ __forceinline__ int cov_slots(const Dims& d, int f) {
   if (d.GR <= 0) return d.SG;
+  if (d.GSB > 0) return d.GSB;
   return (int)((((long long)f + 1) * d.T - 1) / d.GR - ((long long)f * d.T) / d.GR) + 1;
 }
 

@@ -521,19 +521,68 @@ __device__ __forceinline__ int g_slots(const Dims& d, int f) {
   return (f * d.T + d.T - 1) / d.GGR - (f * d.T) / d.GGR + 1;
 }
 
+// A pending g update split in two: g_preload asks for the first four partial-sum slots (and the
+// copy of g) ahead of other loads, g_finish adds them, and any further slots, in the order of
+// g_updated, so both give bitwise the same g.
+template <typename R>
+struct GPre {
+  R pn[4], pd[4], gv;
+};
+template <typename R>
+__device__ __forceinline__ void g_preload(GPre<R>& q, const R* __restrict__ part, int need, int NM, R gv) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int sl = min(u, need - 1);
+    q.pn[u] = part[(size_t)sl * 2 * NM];
+    q.pd[u] = part[(size_t)sl * 2 * NM + NM];
+  }
+  q.gv = gv;
+}
+template <typename R>
+__device__ __forceinline__ R g_finish(const GPre<R>& q, const R* __restrict__ part, int need, int NM, R eps) {
+  R nu = 0, de = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (u < need) {
+      nu += q.pn[u];
+      de += q.pd[u];
+    }
+  for (int s0 = 4; s0 < need; s0 += 4) {
+    R pn[4], pd[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int sl = min(s0 + u, need - 1);
+      pn[u] = part[(size_t)sl * 2 * NM];
+      pd[u] = part[(size_t)sl * 2 * NM + NM];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (s0 + u < need) {
+        nu += pn[u];
+        de += pd[u];
+      }
+  }
+  return q.gv * sqrt(nu / rmax(de, eps));
+}
+
 // ------------------------------------------------------------------------------------
 // Weighted covariances (eq. (14)) for subarrays of M_l <= 4 mics, FP32 inputs, FP64 sums.
-// As many workgroups as fit on the chip at once share the flattened (f, t) frames equally,
-// so every SIMD gets the same work; kGDL lanes per subarray: lane j takes frames j, j + kGDL,
-// ... of each bin segment of the workgroup's share.  Per frame it forms 1/y for the
+// A workgroup is one wave, and as many as fit on the chip at once share the frames equally:
+// when there are at least two per bin, every bin gets the same number (Dims::GSB), each taking
+// an equal part of its frames; otherwise they share the flattened (f, t) frames in equal ranges,
+// which may cross bins (a range that does is summed as one segment per bin, each with its own
+// start-up and reduction -- the reason for the bin-aligned parts).  kGDL lanes per subarray:
+// lane j takes frames j, j + kGDL, ... of each segment.  Per frame it forms 1/y for the
 // subarray's mics (FP32), the packed entries of x^(l) x^(l)H in FP64 (exact: products of
 // FP32 values) and adds (1/y_mu) x x^H into M_l x M_l^2 FP64 registers; the lanes' sums are
-// then added through LDS in a fixed order, one slot per (bin, workgroup).  FP32 sums over
+// then added through LDS in a fixed order, one slot per (bin, workgroup).  (One-wave
+// workgroups of 16 lanes per subarray and bin-aligned parts took the kernel from 16.0 to
+// 13.7 us at 513 x 625 frames, against two-wave ones with flattened ranges.)  FP32 sums over
 // frames would leave rounding errors outside the dominant directions of V, which the solve
 // of eq. (15) amplifies by cond(V) -- large at the lowest bins, where the mixing is nearly
 // rank-deficient; FP64 sums keep the solve's input at the precision of the FP64 reference.
 // Output: V[f][slot][packed entries], FP64, /T not applied.
-constexpr int kGDL = 32;  // lanes per subarray
+constexpr int kGDL = 16;  // lanes per subarray
 constexpr int kGDH = 1;   // lanes per frame (each sums ML / kGDH of the rows mu)
 
 template <int L>
@@ -559,15 +608,21 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
   const int h = tid / (L * kGDL), l = min(tid / kGDL % L, L - 1), j = tid % kGDL;  // row half, subarray, lane
   const bool live = tid < kGDH * L * kGDL;
   const int T = d.T;
-  // This workgroup's share of the flattened (f, t) frames; it may span several bins, each
-  // summed as one segment into slot (workgroup - first workgroup of the bin).
+  // This workgroup's share of the flattened (f, t) frames: part p of bin fb, or an equal range
+  // that may span several bins, each summed as one segment into slot (workgroup - first
+  // workgroup of the bin).
   const long long total = (long long)d.F * T;
-  const long long a0 = (long long)blockIdx.x * d.GR, a1 = min(total, a0 + d.GR);
+  long long a0 = (long long)blockIdx.x * d.GR, a1 = min(total, a0 + d.GR);
+  if (d.GSB > 0) {  // part p of bin fb
+    const int fb = blockIdx.x / d.GSB, p = blockIdx.x - fb * d.GSB;
+    a0 = (long long)fb * T + (long long)p * T / d.GSB;
+    a1 = (long long)fb * T + (long long)(p + 1) * T / d.GSB;
+  }
   for (long long i0 = a0; i0 < a1;) {
     const int f = (int)(i0 / T);
     const long long fend = min(a1, (long long)(f + 1) * T);
     const int ts = (int)(i0 - (long long)f * T), te = (int)(fend - (long long)f * T);
-    const int slot = blockIdx.x - (int)(((long long)f * T) / d.GR);
+    const int slot = d.GSB > 0 ? blockIdx.x - f * d.GSB : blockIdx.x - (int)(((long long)f * T) / d.GR);
     i0 = fend;
 
     const float* xb = reinterpret_cast<const float*>(X + (size_t)f * T * M + l * ML);
@@ -582,19 +637,30 @@ __global__ __launch_bounds__(gramd_threads<L>()) void k_gramd_f(Dims d, const cx
         for (int n = 0; n < N; ++n) la[u][n] = lb[(size_t)n * T + t];
       }
     };
-    if (ts + j < te) fetch(ts + j, xv, lam);  // the first frames' loads fly during the g below
     // g of the bin.  With an update pending (Dims::gpend), each workgroup finishes it from the
     // previous g update's partials and copy of g, neither of which this kernel writes; the
-    // workgroup holding the bin's first frame stores the result.
+    // workgroup holding the bin's first frame stores the result.  The partials are asked for
+    // first and the first frames next, so the finish waits for the partials only.
+    constexpr int NM = N * M, GE = (NM + gramd_threads<L>() - 1) / gramd_threads<L>();
+    GPre<float> gq[GE];
+    const float* gp = gpart + (size_t)f * d.GGS * 2 * NM;
+    const int gneed = g_slots(d, f);
+    if (d.gpend)
+#pragma unroll
+      for (int e = 0; e < GE; ++e) {
+        const int i = tid + e * gramd_threads<L>();
+        if (i < NM) g_preload<float>(gq[e], gp + i, gneed, NM, gsnap[(size_t)f * NM + i]);
+      }
+    if (ts + j < te) fetch(ts + j, xv, lam);  // the first frames' loads fly during the g below
     const float* gsrc = g + (size_t)f * N * M;
     if (d.gpend) {
-      constexpr int NM = N * M;
-      static_assert(NM <= gramd_threads<L>(), "one thread per g entry");
-      if (tid < NM) {
-        const float v = g_updated<float>(gpart + (size_t)f * d.GGS * 2 * NM + tid, g_slots(d, f), NM,
-                                         gsnap[(size_t)f * NM + tid], (float)d.eps);
-        sg[tid] = v;
-        if (ts == 0) g[(size_t)f * NM + tid] = v;
+#pragma unroll
+      for (int e = 0; e < GE; ++e) {
+        const int i = tid + e * gramd_threads<L>();
+        if (i >= NM) break;
+        const float v = g_finish<float>(gq[e], gp + i, gneed, NM, (float)d.eps);
+        sg[i] = v;
+        if (ts == 0) g[(size_t)f * NM + i] = v;
       }
       __syncthreads();
       gsrc = sg;
@@ -727,12 +793,17 @@ __global__ __launch_bounds__(64 * kGBW) void k_gramb_f(Dims d, const cx<float>* 
   const int wt = lane & 15, wg = lane >> 4;                   // weight stage: frame, mic group
   const int T = d.T;
   const long long total = (long long)d.F * T;
-  const long long a0 = (long long)blockIdx.x * d.GR, a1 = min(total, a0 + d.GR);
+  long long a0 = (long long)blockIdx.x * d.GR, a1 = min(total, a0 + d.GR);
+  if (d.GSB > 0) {  // part p of bin fb
+    const int fb = blockIdx.x / d.GSB, p = blockIdx.x - fb * d.GSB;
+    a0 = (long long)fb * T + (long long)p * T / d.GSB;
+    a1 = (long long)fb * T + (long long)(p + 1) * T / d.GSB;
+  }
   for (long long i0 = a0; i0 < a1;) {
     const int f = (int)(i0 / T);
     const long long fend = min(a1, (long long)(f + 1) * T);
     const int ts = (int)(i0 - (long long)f * T), te = (int)(fend - (long long)f * T);
-    const int slot = blockIdx.x - (int)(((long long)f * T) / d.GR);
+    const int slot = d.GSB > 0 ? blockIdx.x - f * d.GSB : blockIdx.x - (int)(((long long)f * T) / d.GR);
     i0 = fend;
     // g of the bin, finishing a pending g update exactly as k_gramd_f does.
     const float* gsrc = g + (size_t)f * NM;

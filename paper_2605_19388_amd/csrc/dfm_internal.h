@@ -37,6 +37,7 @@ struct Dims {
   int TP;    // frames rounded up to 16: row length of the coefficient planes (specialised kernels)
   int SG;    // partial-sum slots per bin of the covariances (S slices, or balanced ranges, below)
   int GR;    // k_gramd_f: flattened (f, t) frames per workgroup (0: per-slice partials)
+  int GSB;   // covariance workgroups per bin when every bin gets the same number (0: equal flat ranges)
   int GW;    // k_gramd_f: workgroups
   int GGR;   // k_g_f: flattened (f, t) frames per workgroup
   int GGW;   // k_g_f: workgroups
