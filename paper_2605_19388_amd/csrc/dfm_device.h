@@ -39,8 +39,10 @@ __device__ __forceinline__ cd cinv(cd a) {
   return {a.re * s, -a.im * s};
 }
 
+// The floor max(a, b) of Sec. IV-A (b = eps > 0), one max instruction; like the comparison
+// a > b ? a : b it gives b for a NaN a.
 template <typename R>
-__device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+__device__ __forceinline__ R rmax(R a, R b) { return fmax(a, b); }
 
 // ---------------------------------------------------------------------------------------
 // Packed Hermitian index j in [0, M_l^2): j < M_l is the diagonal entry (j, j) (real);

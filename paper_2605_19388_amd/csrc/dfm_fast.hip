@@ -39,6 +39,15 @@ constexpr int kHTB = 16;  // frames per activation tile
 
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// Element i of an array whose start is the same for the whole workgroup, through a 32-bit byte
+// offset: the access then takes the scalar-base-plus-vector-offset form instead of 64-bit
+// address arithmetic per lane.  Callers index within one bin's data (far below 4 GB).
+template <typename T>
+__device__ __forceinline__ T* at(T* base, uint32_t i) {
+  typedef typename std::conditional<std::is_const<T>::value, const char, char>::type C;
+  return reinterpret_cast<T*>(reinterpret_cast<C*>(base) + i * (uint32_t)sizeof(T));
+}
+
 // Reciprocal of a model variance (always >= eps > 0): the hardware estimate in FP32,
 // the correctly rounded quotient in FP64.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -1011,6 +1020,10 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
     const int i = tid + j * kT;
     if (i < N * M) gv[j] = g[(size_t)f * N * M + i];
   }
+  const R* xf = reinterpret_cast<const R*>(X + (size_t)f * T * M);  // the bin's frames
+  const R* lf[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n) lf[n] = lamin + ((size_t)f * N + n) * T;
   R xv[2][2 * M], lam[2][N];
   int tf[2];
   bool live[2];
@@ -1019,9 +1032,9 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
     const int s = 2 * blockIdx.y + u, t0 = s * d.SL;
     live[u] = s < d.S && tid < min(d.SL, T - t0);
     tf[u] = live[u] ? t0 + tid : T - 1;  // dead lanes load a valid frame and store nothing
-    load16<R, 2 * M>(xv[u], reinterpret_cast<const R*>(X + ((size_t)f * T + tf[u]) * M));
+    load16<R, 2 * M>(xv[u], at(xf, (uint32_t)tf[u] * (2 * M)));
 #pragma unroll
-    for (int n = 0; n < N; ++n) lam[u][n] = lamin[((size_t)f * N + n) * T + tf[u]];
+    for (int n = 0; n < N; ++n) lam[u][n] = *at(lf[n], (uint32_t)tf[u]);
   }
   sched_fence();
 #pragma unroll
@@ -1054,11 +1067,13 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
       for (int mu = 0; mu < ML; ++mu) {
         R zr = 0, zi = 0;
 #pragma unroll
-        for (int c = 0; c < ML; ++c) {
+        for (int c = 0; c < ML; ++c) {  // two fused multiply-adds per part
           const cx<R> q = sQ[l * ML2 + mu * ML + c];
           const R xr = xv[u][2 * (l * ML + c)], xi = xv[u][2 * (l * ML + c) + 1];
-          zr += q.re * xr - q.im * xi;
-          zi += q.re * xi + q.im * xr;
+          zr = fma(q.re, xr, zr);
+          zr = fma(-q.im, xi, zr);
+          zi = fma(q.re, xi, zi);
+          zi = fma(q.im, xr, zi);
         }
         const int m = l * ML + mu;
         const R p = zr * zr + zi * zi;
@@ -1077,10 +1092,11 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
     }
     const int t = tf[u];
     {
+      const uint32_t o = (uint32_t)ab_index(d, 0, 0, t);  // the frame's place in a bin row
 #pragma unroll
       for (int n = 0; n < N; ++n) {
-        AB[ab_index(d, n, f, t)] = a[n];
-        AB[ab_index(d, N + n, f, t)] = b[n];
+        *at(AB + ab_index(d, n, f, 0), o) = a[n];
+        *at(AB + ab_index(d, N + n, f, 0), o) = b[n];
       }
 #pragma unroll
       for (int i = 0; i < M / E; ++i) {
@@ -1098,7 +1114,7 @@ __global__ __launch_bounds__(kT) void k_pw_f(Dims d, const cx<R>* __restrict__ X
     R* pout = P + ((size_t)f * T + t0) * M;
     for (int c = tid; c < nt * (M / E); c += kT) {
       const int fr = c / (M / E), part = c - fr * (M / E);
-      *reinterpret_cast<vt*>(pout + (size_t)c * E) = *reinterpret_cast<const vt*>(sP + fr * PS + part * E);
+      *reinterpret_cast<vt*>(at(pout, (uint32_t)c * E)) = *reinterpret_cast<const vt*>(sP + fr * PS + part * E);
     }
     __syncthreads();
   }
@@ -1324,6 +1340,10 @@ __global__ __launch_bounds__(kT) void k_h_f(Dims d, const R* __restrict__ lamin,
     const int i = tid + j * kT;
     if (i < N * M) gv[j] = g[(size_t)f * N * M + i];
   }
+  const R* pf = P + (size_t)f * T * M;  // the bin's frames
+  const R* lf[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n) lf[n] = lamin + ((size_t)f * N + n) * T;
   R pv[2][M], lam[2][N];
   int tf[2];
   bool live[2];
@@ -1332,9 +1352,9 @@ __global__ __launch_bounds__(kT) void k_h_f(Dims d, const R* __restrict__ lamin,
     const int s = 2 * blockIdx.y + u, t0 = s * d.SL;
     live[u] = s < d.S && tid < min(d.SL, T - t0);
     tf[u] = live[u] ? t0 + tid : T - 1;
-    load16<R, M>(pv[u], P + ((size_t)f * T + tf[u]) * M);
+    load16<R, M>(pv[u], at(pf, (uint32_t)tf[u] * M));
 #pragma unroll
-    for (int n = 0; n < N; ++n) lam[u][n] = lamin[((size_t)f * N + n) * T + tf[u]];
+    for (int n = 0; n < N; ++n) lam[u][n] = *at(lf[n], (uint32_t)tf[u]);
   }
   sched_fence();
 #pragma unroll
@@ -1365,11 +1385,11 @@ __global__ __launch_bounds__(kT) void k_h_f(Dims d, const R* __restrict__ lamin,
         b[n] += sg[n * M + m] * iy;
       }
     }
-    const int t = tf[u];
+    const uint32_t o = (uint32_t)ab_index(d, 0, 0, tf[u]);  // the frame's place in a bin row
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-      AB[ab_index(d, n, f, t)] = a[n];
-      AB[ab_index(d, N + n, f, t)] = b[n];
+      *at(AB + ab_index(d, n, f, 0), o) = a[n];
+      *at(AB + ab_index(d, N + n, f, 0), o) = b[n];
     }
   }
 }
@@ -1710,16 +1730,18 @@ __global__ __launch_bounds__(kGT) void k_g_f(Dims d, const R* __restrict__ lamin
       num[n] = 0;
       den[n] = 0;
     }
-    const R* Pf = P + (size_t)f * T * M + m;
-    const R* Lf = lamin + (size_t)f * N * T;
+    const R* Pf = P + (size_t)f * T * M;  // the bin's frames
+    const R* Lf[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) Lf[n] = lamin + ((size_t)f * N + n) * T;
     // Loads of one batch (kGU steps); frames past the range read the range's last frame.
     auto fetch = [&](int tb, R(&pv)[kGU], R(&lv)[kGU][N]) {
 #pragma unroll
       for (int u = 0; u < kGU; ++u) {
-        const int t = min(tb + u * FS + me, t1 - 1);
-        pv[u] = Pf[(size_t)t * M];
+        const uint32_t t = (uint32_t)min(tb + u * FS + me, t1 - 1);
+        pv[u] = *at(Pf, t * M + m);
 #pragma unroll
-        for (int n = 0; n < N; ++n) lv[u][n] = Lf[(size_t)n * T + t];
+        for (int n = 0; n < N; ++n) lv[u][n] = *at(Lf[n], t);
       }
     };
     R pa[kGU], la[kGU][N], pb[kGU], lb[kGU][N];
