@@ -1212,6 +1212,14 @@ __global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restric
   const R* bn = AB + ((size_t)(N + n) * d.TBN * F + fr) * 16 + 4 * kk;
   const R* hn = H + (size_t)n * K * T;
   const size_t tstride = (size_t)F * 16;  // one 16-frame tile further
+  // The entry of W this thread updates (at most one), asked for now so that the update does not
+  // wait for it.
+  static_assert(16 * KP <= 64 * kGW, "one updated entry per thread");
+  R wold = 0;
+  {
+    const int fi = tid / KP, k = tid - fi * KP, f = f0 + fi;
+    if (tid < 16 * KP && k < K && f < F) wold = W[((size_t)n * F + f) * K + k];
+  }
 
   // Window [w0, w0 + nw) of H[n] -> sH: wave w stages rows w, w + kGW, ...; every load is
   // issued before the first LDS write.
@@ -1281,14 +1289,14 @@ __global__ __launch_bounds__(64 * kGW) void k_wgemm_f(Dims d, const R* __restric
   }
   spill_tiles<R, KT>(red, wave, lane, accN, accD);
   __syncthreads();
-  for (int e = tid; e < 16 * KP; e += 64 * kGW) {
-    const int fi = e / KP, k = e - fi * KP, f = f0 + fi;
+  if (tid < 16 * KP) {
+    const int e = tid, fi = e / KP, k = e - fi * KP, f = f0 + fi;
     R w = 0;
     if (k < K && f < F) {
       R num, den;
       sum_tiles<R, KT>(red, k >> 4, fi, k & 15, num, den);
       const size_t idx = ((size_t)n * F + f) * K + k;
-      w = W[idx] * sqrt(num / rmax(den, (R)d.eps));
+      w = wold * sqrt(num / rmax(den, (R)d.eps));
       if (d.check && !isfinite(w)) atomicOr(status, kStNonFinite);
       W[idx] = w;
     }
@@ -1440,6 +1448,11 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
   const R* bp = AB + ((size_t)(N + n) * d.TBN + tt) * F * 16 + i;
   const R* wn = W + (size_t)n * F * K;
   const bool tok = t0 + i < T;
+  // The entry of H this thread updates (at most one), asked for now so that the update does not
+  // wait for it.
+  static_assert(KP * 16 <= 64 * kGW, "one updated entry per thread");
+  R hold = 0;
+  if (tid < KP * 16 && (tid >> 4) < K && t0 + (tid & 15) < T) hold = H[((size_t)n * K + (tid >> 4)) * T + t0 + (tid & 15)];
 
   auto stage = [&](int f0, int nf) { stage_w<R, K>(sW, wn, F, f0, nf, tid); };
 
@@ -1495,14 +1508,14 @@ __global__ __launch_bounds__(64 * kGW) void k_hgemm_f(Dims d, const R* __restric
   }
   spill_tiles<R, KT>(red, wave, lane, accN, accD);
   __syncthreads();
-  for (int e = tid; e < KP * 16; e += 64 * kGW) {
-    const int k = e >> 4, tl = e & 15, t = t0 + tl;
+  if (tid < KP * 16) {
+    const int e = tid, k = e >> 4, tl = e & 15, t = t0 + tl;
     R h = 0;
     if (k < K && t < T) {
       R num, den;
       sum_tiles<R, KT>(red, k >> 4, k & 15, tl, num, den);
       const size_t idx = ((size_t)n * K + k) * T + t;
-      h = H[idx] * sqrt(num / rmax(den, (R)d.eps));
+      h = hold * sqrt(num / rmax(den, (R)d.eps));
       if (d.check && !isfinite(h)) atomicOr(status, kStNonFinite);
       H[idx] = h;
     }
