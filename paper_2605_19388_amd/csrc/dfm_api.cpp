@@ -51,7 +51,7 @@ static bool choose_fast(Dims& d, int dtype) {
   for (int l = 1; l < d.L; ++l)
     if (d.mics[l] != ml) return false;
   const int set = fast_set_index(d.N, d.K, ml, d.L);
-  if (set < 0) return false;
+  if (set < 0 || (dtype == DFM_C128 && !fast_fp64_ok(set))) return false;
   d.fast = set;
   d.ML = ml;
   for (int sl = d.tile; sl >= 16; sl /= 2) {

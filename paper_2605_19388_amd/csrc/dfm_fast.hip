@@ -1721,7 +1721,7 @@ __global__ __launch_bounds__(kGT) void k_g_f(Dims d, const R* __restrict__ lamin
   constexpr int M = ML * L;
   typedef GShape<R, N, M> G;
   constexpr int FPW = G::FPW, FS = G::FS, NM = N * M;
-  static_assert(FPW >= 1 && 2 * NM <= kGT, "shape");
+  static_assert(FPW >= 1, "shape");
   __shared__ R red[G::RED];  // [wave][2N][64]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j = lane / M, m = lane - j * M;  // frame within the wave's step, mic
@@ -1791,14 +1791,14 @@ __global__ __launch_bounds__(kGT) void k_g_f(Dims d, const R* __restrict__ lamin
     }
     __syncthreads();
     const int first = (f * T) / d.GGR;
-    if (tid < 2 * NM) {
-      const int q = tid / M, mm = tid - q * M;
+    for (int o = tid; o < 2 * NM; o += kGT) {
+      const int q = o / M, mm = o - q * M;
       R v = 0;
 #pragma unroll
       for (int w = 0; w < kGT / 64; ++w)
 #pragma unroll
         for (int jj = 0; jj < FPW; ++jj) v += red[(w * 2 * N + q) * 64 + jj * M + mm];
-      gpart[((size_t)f * d.GGS + blockIdx.x - first) * 2 * NM + tid] = v;
+      gpart[((size_t)f * d.GGS + blockIdx.x - first) * 2 * NM + o] = v;
     }
   }
 }
@@ -2007,6 +2007,8 @@ struct Set {
   // FP32 sets with M_l <= 4 sum the covariances with k_gramd_f (no dynamic LDS); every other
   // set runs k_gram_f in FP64 on the plan's inputs.
   static constexpr bool kGramD = sizeof(R) == 4 && (ML == 2 || ML == 4);
+  // k_gram_f stages a bin's g one value per thread: sets above that run in FP32 only.
+  static constexpr bool kGramOk = N * M <= kT;
   static size_t smem_gram(const Dims& d) {
     typedef GramShape<double, N, K, ML, L> G;
     return align_up(sizeof(double) * N * M, 16) + sizeof(double) * (size_t)d.SLP * (G::MP + G::OP);
@@ -2086,6 +2088,8 @@ struct Set {
           hipLaunchKernelGGL((k_gramd_f<N, K, ML, L>), dim3(d.GW), dim3(gramd_threads<L>()), 0, s, d, X,
                              static_cast<const R*>(b.lam), g, static_cast<const R*>(b.gpart),
                              static_cast<const R*>(b.gsnap), static_cast<double*>(b.Vpart));
+        } else if constexpr (!kGramOk) {
+          return hipErrorNotSupported;
         } else {
           hipLaunchKernelGGL((k_gram_f<double, R, N, K, ML, L>), dim3(d.F * d.S), dim3(kT), smem_gram(d), s, d,
                              X, static_cast<const R*>(b.lam), g, static_cast<double*>(b.Vpart));
@@ -2147,7 +2151,10 @@ struct Set {
 // Compiled sets (index, N, K, M_l, L); index = Dims::fast.
 #define DFM_FAST_SETS(X)                                                                            \
   X(0, 2, 4, 2, 2) X(1, 5, 16, 4, 4) X(2, 5, 16, 16, 1) X(3, 3, 16, 4, 2) X(4, 8, 16, 4, 3) X(5, 3, 16, 4, 3) \
-  X(6, 5, 16, 4, 2) X(7, 8, 16, 4, 2) X(8, 5, 16, 4, 3) X(9, 3, 16, 4, 4) X(10, 8, 16, 4, 4)
+  X(6, 5, 16, 4, 2) X(7, 8, 16, 4, 2) X(8, 5, 16, 4, 3) X(9, 3, 16, 4, 4) X(10, 8, 16, 4, 4)          \
+  X(11, 3, 16, 4, 5) X(12, 5, 16, 4, 5) X(13, 8, 16, 4, 5) X(14, 3, 16, 4, 6) X(15, 5, 16, 4, 6)       \
+  X(16, 8, 16, 4, 6) X(17, 3, 16, 4, 7) X(18, 5, 16, 4, 7) X(19, 8, 16, 4, 7) X(20, 3, 16, 4, 8)       \
+  X(21, 5, 16, 4, 8) X(22, 8, 16, 4, 8)
 
 hipError_t fast_finish(const Dims& d, const Buffers& b, int dtype, bool separate, void* S, hipStream_t s) {
   switch (d.fast) {
@@ -2167,6 +2174,17 @@ int fast_set_index(int N, int K, int ML, int L) {
   DFM_FAST_SETS(DFM_MATCH)
 #undef DFM_MATCH
   return -1;
+}
+
+bool fast_fp64_ok(int set) {
+  switch (set) {
+#define DFM_F64(i, n, k, ml, l) \
+  case i:                      \
+    return fast::Set<double, n, k, ml, l>::kGramOk;
+    DFM_FAST_SETS(DFM_F64)
+#undef DFM_F64
+  }
+  return false;
 }
 
 int fast_gramd_blocks_per_cu(const Dims& d) {

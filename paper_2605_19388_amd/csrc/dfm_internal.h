@@ -100,6 +100,7 @@ int iteration_kernels(const Dims& d, int* kids);         // fills kids, returns 
 
 // Shape-specialised kernel sets (dfm_fast.hip).
 int fast_set_index(int N, int K, int ML, int L);
+bool fast_fp64_ok(int set);  // the set also runs FP64 plans
 size_t fast_max_smem(const Dims& d, int dtype);
 int fast_hgemm_windows(const Dims& d, int dtype);  // LDS windows of W[n] in the H update
 int fast_gramd_blocks_per_cu(const Dims& d);  // resident k_gramd_f / k_gramb_f workgroups per CU (0: unknown)

@@ -118,6 +118,12 @@ STAGE_CASES = [
     (20, 77, (4, 4), 3, 16),
     (20, 77, (4, 4, 4), 8, 16),
     (21, 50, (4, 4, 4), 3, 16),
+    # Five to eight subarrays of 4 mics (M = 20-32): specialised in FP32; in FP64 only where a bin's
+    # N x M values of g fit the FP64 covariance kernel's staging (N M <= 128), generic otherwise.
+    (21, 120, (4,) * 6, 5, 16),
+    (13, 90, (4,) * 8, 3, 16),
+    (11, 70, (4,) * 5, 8, 16),
+    (9, 64, (4,) * 7, 5, 16),
     # W[n] over more than one LDS window in the H update (FP64 above 176 bins, FP32 above 592):
     # the bin-split H update.
     (200, 37, (4, 4, 4), 3, 16),
@@ -141,6 +147,11 @@ def test_kernel_path_selection():
     assert plan(X, (4, 4, 4, 4), 5, 16, Q, g, W, H, True).kernel_names() == FAST
     X, Q, g, W, H = _problem(4, 20, (2, 3), 5, 16, seed=1, fp32=True)
     assert plan(X, (2, 3), 5, 16, Q, g, W, H, True).kernel_names() == GENERIC
+    # Eight 4-mic subarrays, N = 8: specialised in FP32, generic in FP64 (N M = 256 > 128).
+    X, Q, g, W, H = _problem(4, 70, (4,) * 8, 8, 16, seed=1, fp32=True)
+    assert plan(X, (4,) * 8, 8, 16, Q, g, W, H, True).kernel_names() == FAST
+    X, Q, g, W, H = _problem(4, 70, (4,) * 8, 8, 16, seed=1, fp32=False)
+    assert plan(X, (4,) * 8, 8, 16, Q, g, W, H, False).kernel_names() == GENERIC
 
 
 def _run_stages(X, Q, g, W, H, mics, N, K, fp32, iters, where):
