@@ -1,18 +1,26 @@
-"""Gradient of the cost (13) after unrolled MM iterations -- TEST INFRASTRUCTURE (only
-``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline`` leg may import it).
+"""Gradient of the cost (13) after unrolled iterations -- TEST INFRASTRUCTURE (only ``tests/``,
+``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline`` leg may import it).
 
-The map differentiated: from a state (Q, g, W, H), n MM iterations of eqs. (8), (9), (10) in
-that order with Q held fixed (so P = |Q x|^2 is computed once and the model variance y is
-refreshed after each update, Sec. II-B), then the cost (13) of the final state,
+Two maps are differentiated, both ending in the cost (13) of the final state,
 
   L = sum_{f,t,m} (P / y + ln y) - 2T sum_{f,l} ln|det Q_fl|,
 
 with every Sec. IV-A floor in place (y = max(sum_n lambda g, 1e-6), the denominators of (8)-(10)
-floored at 1e-6).  The forward is written in PyTorch float64 on the CPU, step by step as the
-paper states it, and the gradient of L with respect to the initial Q, g, W and H is PyTorch's
-reverse-mode differentiation of that forward (torch.autograd), the library primitive used here;
-a floored quantity has zero derivative where the floor is active.  For complex Q the gradient is
-dL/dRe(Q) + i dL/dIm(Q), PyTorch's convention.
+and the IP normaliser of (16) floored at 1e-6):
+
+* MM iterations (``mm_unrolled_*``): n iterations of eqs. (8), (9), (10) in that order with Q held
+  fixed, so P = |Q x|^2 is computed once and the model variance y is refreshed after each update
+  (Sec. II-B);
+* full iterations (``iter_unrolled_*``): each iteration first forms the weighted covariances of
+  eq. (14) from the current model and sweeps every subarray's rows in ascending order by eqs.
+  (15)-(16), then computes P with the new Q and runs eqs. (8)-(10) -- the schedule of
+  ``oracle.dfmnmf.iterate``.
+
+The forward is written in PyTorch float64 on the CPU, step by step as the paper states it, and the
+gradient of L with respect to the initial Q, g, W and H is PyTorch's reverse-mode differentiation
+of that forward (torch.autograd), the library primitive used here; a floored quantity has zero
+derivative where the floor is active.  For complex Q the gradient is dL/dRe(Q) + i dL/dIm(Q),
+PyTorch's convention.
 """
 from __future__ import annotations
 
@@ -111,3 +119,54 @@ def mm_unrolled_state(X, Q, g, W, H, mics, n_iter, eps=EPS):
             Ht = update_H(Wt, Ht, gt, P, eps)
             gt = update_g(Wt, Ht, gt, P, eps)
     return gt.numpy(), Wt.numpy(), Ht.numpy()
+
+
+def covariances(X, y, mics):
+    """Eq. (14): per subarray l, V[f, mu] = (1/T) sum_t x^(l) x^(l)H / y_{f,t,o_l+mu}."""
+    T = X.shape[1]
+    out = []
+    for ml, (mo, _) in zip(mics, block_offsets(mics)):
+        xl = X[:, :, mo:mo + ml]
+        w = (1.0 / y[:, :, mo:mo + ml]).to(X.dtype)
+        out.append(torch.einsum("ftu,fta,ftb->fuab", w, xl, xl.conj()) / T)
+    return out
+
+
+def ip_sweep(Q, V, mics, eps):
+    """Eqs. (15)-(16) for every subarray, rows mu in ascending order: b = (Q_l V_mu)^-1 e_mu with
+    the rows already updated, b <- b / sqrt(max(b^H V_mu b, eps)), row mu of Q_l <- b^H."""
+    F = Q.shape[0]
+    blocks = []
+    for ml, (_, qo), Vl in zip(mics, block_offsets(mics), V):
+        Ql = Q[:, qo:qo + ml * ml].reshape(F, ml, ml)
+        for mu in range(ml):
+            e = torch.zeros(F, ml, 1, dtype=Q.dtype)
+            e[:, mu, 0] = 1.0
+            b = torch.linalg.solve(Ql @ Vl[:, mu], e)[..., 0]
+            s = torch.einsum("fa,fab,fb->f", b.conj(), Vl[:, mu], b).real
+            b = b / torch.sqrt(torch.clamp(s, min=eps))[:, None]
+            Ql = torch.cat([Ql[:, :mu], b.conj()[:, None, :], Ql[:, mu + 1:]], dim=1)
+        blocks.append(Ql.reshape(F, ml * ml))
+    return torch.cat(blocks, dim=1)
+
+
+def iter_unrolled_cost(X, Q, g, W, H, mics, n_iter, eps=EPS):
+    """The cost (13) after n_iter full iterations (eq. (14), eqs. (15)-(16), then (8)-(10))."""
+    for _ in range(n_iter):
+        _, y = model(W, H, g, eps)
+        Q = ip_sweep(Q, covariances(X, y, mics), mics, eps)
+        P = powers(X, Q, mics)
+        W = update_W(W, H, g, P, eps)
+        H = update_H(W, H, g, P, eps)
+        g = update_g(W, H, g, P, eps)
+    return cost(X, Q, g, W, H, mics, eps)
+
+
+def iter_unrolled_grad(X, Q, g, W, H, mics, n_iter, eps=EPS):
+    """(L, dQ, dg, dW, dH) as NumPy arrays: the cost after n_iter full iterations and its gradient
+    with respect to the initial state (dQ = dL/dRe Q + i dL/dIm Q)."""
+    Xt = _t(X)
+    Qt, gt, Wt, Ht = (_t(a, True) for a in (Q, g, W, H))
+    L = iter_unrolled_cost(Xt, Qt, gt, Wt, Ht, mics, n_iter, eps)
+    grads = torch.autograd.grad(L, (Qt, gt, Wt, Ht))
+    return (float(L.detach()),) + tuple(gr.detach().numpy() for gr in grads)

@@ -1,7 +1,9 @@
-"""Pins of the oracle's gradient of the cost after unrolled MM iterations (oracle/grad.py) --
-CPU only.
+"""Pins of the oracle's gradient of the cost after unrolled iterations (oracle/grad.py) -- CPU
+only.  MM iterations (Q fixed) and full iterations (eq. (14), the IP sweep of eqs. (15)-(16), then
+eqs. (8)-(10)):
 
-* its forward equals the NumPy oracle's MM updates and cost (two independent writings);
+* its forward equals the NumPy oracle's updates and cost (two independent writings; for full
+  iterations, ``oracle.dfmnmf.iterate`` with its own solves);
 * its gradient equals FP64 central finite differences (step 1e-6) of the NumPy oracle, for every
   parameter block and the real and imaginary parts of Q, with and without floors active;
 * at an MM fixed point (a recording with |Q x|^2 = y exactly) the gradient with respect to g, W
@@ -49,8 +51,13 @@ def test_forward_equals_numpy_oracle():
     assert abs(L - D.nll(X, Q, g, W, H, mics)) <= 1e-12 * abs(L)
 
 
-def _fd_check(X, Q, g, W, H, mics, n_iter, samples=6, seed=0, rtol=1e-5):
-    L, dQ, dg, dW, dH = G.mm_unrolled_grad(X, Q, g, W, H, mics, n_iter)
+def _numpy_iter_cost(X, Q, g, W, H, mics, n_iter):
+    return D.nll(X, *D.iterate(X, Q, g, W, H, mics, n_iter), mics)
+
+
+def _fd_check(X, Q, g, W, H, mics, n_iter, samples=6, seed=0, rtol=1e-5, full=False):
+    grad_fn, cost_fn = (G.iter_unrolled_grad, _numpy_iter_cost) if full else (G.mm_unrolled_grad, _numpy_unrolled_cost)
+    L, dQ, dg, dW, dH = grad_fn(X, Q, g, W, H, mics, n_iter)
     rng = np.random.Generator(np.random.PCG64(seed))
     params = {"Q": Q, "g": g, "W": W, "H": H}
     grads = {"Q": dQ, "g": dg, "W": dW, "H": dH}
@@ -63,12 +70,13 @@ def _fd_check(X, Q, g, W, H, mics, n_iter, samples=6, seed=0, rtol=1e-5):
                 h = 1e-6 * (abs(p[idx]) if p[idx] != 0 else 1.0)  # step 1e-6 relative to the entry
                 args = {k: v.copy() for k, v in params.items()}
                 args[name][idx] += unit * h
-                lp = _numpy_unrolled_cost(X, args["Q"], args["g"], args["W"], args["H"], mics, n_iter)
+                lp = cost_fn(X, args["Q"], args["g"], args["W"], args["H"], mics, n_iter)
                 args[name][idx] -= 2 * unit * h
-                lm = _numpy_unrolled_cost(X, args["Q"], args["g"], args["W"], args["H"], mics, n_iter)
+                lm = cost_fn(X, args["Q"], args["g"], args["W"], args["H"], mics, n_iter)
                 fd = (lp - lm) / (2 * h)
                 got = grads[name][idx].real if part == "re" else grads[name][idx].imag
-                assert abs(got - fd) <= rtol * max(abs(fd), 1e-3 * scale / p.size), (name, idx, part, got, fd)
+                noise = 64 * np.finfo(float).eps * scale / h  # rounding of the two costs, over the step
+                assert abs(got - fd) <= rtol * max(abs(fd), 1e-3 * scale / p.size) + noise, (name, idx, part, got, fd)
 
 
 @pytest.mark.parametrize("n_iter", [0, 1, 3])
@@ -113,3 +121,51 @@ def test_direct_gradient_is_den_minus_num():
     for d, terms in ((dW, D.mm_terms_W), (dH, D.mm_terms_H), (dg, D.mm_terms_g)):
         num, den = terms(W, H, g, P)
         np.testing.assert_allclose(d, den - num, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------- full iterations (IP sweep + MM)
+@pytest.mark.parametrize("mics", [(2, 1), (2, 2), (1, 1, 2)])
+def test_iter_forward_equals_numpy_oracle(mics):
+    X, Q, g, W, H = _case(F=3, T=12, mics=mics, N=2, K=2)
+    for n_iter in (0, 1, 3):
+        L, *_ = G.iter_unrolled_grad(X, Q, g, W, H, mics, n_iter)
+        ref = _numpy_iter_cost(X, Q, g, W, H, mics, n_iter)
+        assert abs(L - ref) <= 1e-12 * abs(ref), (n_iter, L, ref)
+
+
+@pytest.mark.parametrize("n_iter", [1, 2])
+def test_iter_gradient_equals_central_finite_differences(n_iter):
+    X, Q, g, W, H = _case()
+    _fd_check(X, Q, g, W, H, (2, 1), n_iter, full=True)
+
+
+def test_iter_gradient_equals_finite_differences_with_floors_active():
+    """Floors of y and of the MM denominators active (a faint recording, a small model)."""
+    X, Q, g, W, H = _case(scale=1e-3)
+    W, H = 3e-4 * W, 3e-4 * H
+    y = D.model_variance(D.source_psd(W, H), g)
+    assert np.any(y == D.EPS) and np.any(y > D.EPS)
+    _fd_check(X, Q, g, W, H, (2, 1), 1, seed=2, full=True)
+
+
+@pytest.mark.parametrize("mics", [(2, 1), (3, 2)])
+def test_iter_gradient_vanishes_on_rows_the_sweep_overwrites_first(mics):
+    """The sweep replaces row 1 of each block by a vector fixed, up to its phase, by the other rows
+    alone (Q V b = e_1 fixes b's direction through the other rows' equations; the scale is then
+    normalised away), and the cost ignores row phases; so after a full iteration the cost does not
+    depend on the first row of any block, and its gradient there is exactly zero."""
+    X, Q, g, W, H = _case(F=3, T=12, mics=mics, N=2, K=2)
+    L, dQ, *_ = G.iter_unrolled_grad(X, Q, g, W, H, mics, 1)
+    blocks = D.q_blocks(dQ, mics)
+    top = max(np.abs(b).max() for b in blocks)
+    for b in blocks:
+        assert np.abs(b[:, 0, :]).max() <= 1e-12 * top
+    assert max(np.abs(b[:, 1:, :]).max() for b in blocks if b.shape[1] > 1) > 1e-3 * top
+
+
+def test_iter_gradient_without_iterations_is_the_cost_gradient():
+    X, Q, g, W, H = _case(F=3, T=10, mics=(2, 2), N=2, K=3)
+    a = G.iter_unrolled_grad(X, Q, g, W, H, (2, 2), 0)
+    b = G.mm_unrolled_grad(X, Q, g, W, H, (2, 2), 0)
+    for u, v in zip(a[1:], b[1:]):
+        np.testing.assert_allclose(u, v, rtol=1e-13, atol=1e-15)
