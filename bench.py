@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--grad", type=int, default=0, metavar="N",
                     help="time the gradient of the cost after N unrolled MM iterations (forward with "
                          "checkpoints + hand-written reverse pass) and print its own JSON line")
+    ap.add_argument("--grad-full", action="store_true",
+                    help="with --grad: unroll full iterations (eq. (14), the IP sweep, then the MM updates) "
+                         "instead of MM iterations with Q fixed")
     ap.add_argument("--no-graph", action="store_true",
                     help="plain kernel launches instead of HIP graph replays (for comparison)")
     ap.add_argument("--cpu-threads", type=int, default=0,
@@ -275,8 +278,9 @@ def _live_kernel_times(p, one_step, steps, iters, kernels):
 
 
 def grad_timing(args):
-    """Whole-job time of the unrolled-MM gradient on the workload: reset, N MM iterations with
-    per-iteration checkpoints, the cost, the reverse pass (FP64 internally)."""
+    """Whole-job time of the unrolled-iteration gradient on the workload: reset, N MM (or, with
+    --grad-full, full) iterations with per-iteration checkpoints, the cost, the reverse pass (FP64
+    internally)."""
     import numpy as np
     import torch
 
@@ -293,9 +297,9 @@ def grad_timing(args):
     def one():
         for k, v in init.items():
             getattr(p, k).copy_(v)
-        tape = p.mm_forward(args.grad)
+        tape = p.iter_forward(args.grad) if args.grad_full else p.mm_forward(args.grad)
         cost = p.nll()
-        return cost, p.mm_backward(tape)
+        return cost, (p.iter_backward(tape) if args.grad_full else p.mm_backward(tape))
 
     for _ in range(max(args.warmup, 1)):
         one()
@@ -305,7 +309,8 @@ def grad_timing(args):
         one()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    print(json.dumps({"mode": "grad", "workload": w["name"], "mm_iterations": args.grad, "ms_per_gradient": round(1e3 * dt, 3),
+    print(json.dumps({"mode": "grad", "workload": w["name"], "map": "full iterations" if args.grad_full else "mm iterations",
+                      "iterations": args.grad, "ms_per_gradient": round(1e3 * dt, 3),
                       "gradients_per_s": round(1.0 / dt, 2), "dtype": "f32 state, f64 reverse pass"}), flush=True)
 
 

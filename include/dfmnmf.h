@@ -209,6 +209,28 @@ dfm_status dfm_mm_forward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tap
 dfm_status dfm_mm_backward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* dQ, void* dg,
                            void* dW, void* dH, void* stream);
 
+/* ---- Gradient of the cost after unrolled full iterations.
+ * The map: from the plan's state (Q, g, W, H), n_iter iterations of dfm_step's
+ * schedule -- the covariances (14) from the current model, the IP sweep (15)-(16)
+ * of every subarray's rows in ascending order, P = |Q x|^2 for the new Q, then the
+ * MM updates (8), (9), (10) -- and the cost (13) of the final state, every Sec.
+ * IV-A floor in place (the IP normaliser of (16) floored at eps too).
+ * dfm_iter_forward runs the iterations on the plan's kernels and stores the state
+ * (Q, g, W, H) before each in `tape`; dfm_iter_backward, called after it with the
+ * same n_iter and tape and with the state it left, computes by hand-written
+ * reverse-mode kernels (FP64 internally) the gradient with respect to the state
+ * before the forward, in the layouts and conventions of dfm_mm_backward.  Each
+ * iteration's sweep is recomputed in FP64 from its checkpoint and differentiated
+ * row by row; through (14) the gradient reaches g, W and H a second way.  After
+ * one or more iterations the gradient with respect to the first row of each
+ * block of Q is zero (the sweep overwrites that row first, fixed up to a phase
+ * by the other rows).  Subarrays of up to 16 mics (DFM_E_SHAPE beyond); tape
+ * caller-owned, 256-byte aligned, >= dfm_iter_tape_size bytes.  Asynchronous. */
+dfm_status dfm_iter_tape_size(const dfm_plan* plan, int32_t n_iter, size_t* bytes);
+dfm_status dfm_iter_forward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* stream);
+dfm_status dfm_iter_backward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* dQ, void* dg,
+                             void* dW, void* dH, void* stream);
+
 /* ---- Initial parameters from estimates of the source images (Sec. IV-A, steps 3, 5, 6).
  * The paper initialises from source images estimated by time-frequency masking
  * (its steps 1-2) and factorises the initial spectrograms by IS-NMF (step 4);

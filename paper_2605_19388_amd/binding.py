@@ -46,7 +46,8 @@ _lib = None
 EXPORTS = ("dfm_workspace_size", "dfm_init", "dfm_step", "dfm_substep", "dfm_nll", "dfm_nll_trace", "dfm_separate",
            "dfm_covariances", "dfm_sync_status", "dfm_kernel_times", "dfm_profile_kernel", "dfm_profile_read",
            "dfm_kernel_count", "dfm_kernel_name", "dfm_run_noalloc", "dfm_initialise_workspace_size",
-           "dfm_initialise", "dfm_mm_tape_size", "dfm_mm_forward", "dfm_mm_backward", "dfm_batch_create",
+           "dfm_initialise", "dfm_mm_tape_size", "dfm_mm_forward", "dfm_mm_backward", "dfm_iter_tape_size",
+           "dfm_iter_forward", "dfm_iter_backward", "dfm_batch_create",
            "dfm_batch_step", "dfm_batch_destroy", "dfm_destroy", "dfm_status_string")
 
 
@@ -82,6 +83,9 @@ def load(path: str = LIB_PATH):
     lib.dfm_batch_destroy.restype = None
     lib.dfm_mm_forward.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
     lib.dfm_mm_backward.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp, vp, vp, vp]
+    lib.dfm_iter_tape_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.dfm_iter_forward.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
+    lib.dfm_iter_backward.argtypes = [vp, i32, vp, ctypes.c_size_t, vp, vp, vp, vp, vp]
     lib.dfm_kernel_count.argtypes = [vp]
     lib.dfm_kernel_count.restype = i32
     lib.dfm_kernel_name.argtypes = [vp, i32]
@@ -334,27 +338,48 @@ class DistributedFastMNMF:
     def sync_status(self):
         _check(load().dfm_sync_status(self._plan, self._stream()), "dfm_sync_status")
 
-    def mm_forward(self, n_iter: int):
-        """n_iter MM iterations (8)-(10) with Q fixed, recording per-iteration checkpoints; returns
-        the tape to pass to mm_backward."""
+    def _grad_forward(self, kind: str, n_iter: int):
         torch = self._torch
         lib_ = load()
         n = ctypes.c_size_t(0)
-        _check(lib_.dfm_mm_tape_size(self._plan, int(n_iter), ctypes.byref(n)), "dfm_mm_tape_size")
+        _check(getattr(lib_, f"dfm_{kind}_tape_size")(self._plan, int(n_iter), ctypes.byref(n)),
+               f"dfm_{kind}_tape_size")
         buf = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
         ptr = buf.data_ptr() + (-buf.data_ptr()) % 256
-        _check(lib_.dfm_mm_forward(self._plan, int(n_iter), ptr, n.value, self._stream()), "dfm_mm_forward")
-        return (buf, ptr, n.value, int(n_iter))
+        _check(getattr(lib_, f"dfm_{kind}_forward")(self._plan, int(n_iter), ptr, n.value, self._stream()),
+               f"dfm_{kind}_forward")
+        return (buf, ptr, n.value, int(n_iter), kind)
+
+    def _grad_backward(self, kind: str, tape):
+        torch = self._torch
+        _, ptr, nbytes, n_iter, recorded = tape
+        if recorded != kind:
+            raise ValueError(f"tape recorded by {recorded}_forward, not {kind}_forward")
+        dQ, dg, dW, dH = (torch.empty_like(t) for t in (self.Q, self.g, self.W, self.H))
+        _check(getattr(load(), f"dfm_{kind}_backward")(self._plan, n_iter, ptr, nbytes, dQ.data_ptr(), dg.data_ptr(),
+                                                        dW.data_ptr(), dH.data_ptr(), self._stream()),
+               f"dfm_{kind}_backward")
+        return dQ, dg, dW, dH
+
+    def mm_forward(self, n_iter: int):
+        """n_iter MM iterations (8)-(10) with Q fixed, recording per-iteration checkpoints; returns
+        the tape to pass to mm_backward."""
+        return self._grad_forward("mm", n_iter)
 
     def mm_backward(self, tape):
         """Gradient of the cost after the recorded MM iterations with respect to the state before
         them: (dQ, dg, dW, dH) device tensors (dQ = dL/dRe Q + i dL/dIm Q)."""
-        torch = self._torch
-        _, ptr, nbytes, n_iter = tape
-        dQ, dg, dW, dH = (torch.empty_like(t) for t in (self.Q, self.g, self.W, self.H))
-        _check(load().dfm_mm_backward(self._plan, n_iter, ptr, nbytes, dQ.data_ptr(), dg.data_ptr(), dW.data_ptr(),
-                                      dH.data_ptr(), self._stream()), "dfm_mm_backward")
-        return dQ, dg, dW, dH
+        return self._grad_backward("mm", tape)
+
+    def iter_forward(self, n_iter: int):
+        """n_iter full iterations (eq. (14), the IP sweep (15)-(16), then (8)-(10)), recording
+        per-iteration checkpoints of (Q, g, W, H); returns the tape to pass to iter_backward."""
+        return self._grad_forward("iter", n_iter)
+
+    def iter_backward(self, tape):
+        """Gradient of the cost after the recorded full iterations with respect to the state before
+        them: (dQ, dg, dW, dH) device tensors (dQ = dL/dRe Q + i dL/dIm Q)."""
+        return self._grad_backward("iter", tape)
 
     def load_state(self, Q=None, g=None, W=None, H=None):
         """Copy new values into the state tensors in place (the plan keeps their addresses)."""

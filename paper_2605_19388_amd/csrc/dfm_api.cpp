@@ -531,43 +531,88 @@ dfm_status dfm_profile_read(dfm_plan* plan, double* avg_ms, int64_t* launches, v
   return DFM_OK;
 }
 
-dfm_status dfm_mm_tape_size(const dfm_plan* plan, int32_t n_iter, size_t* bytes) {
+namespace {
+
+dfm_status grad_tape_size(const dfm_plan* plan, int32_t n_iter, bool full, size_t* bytes) {
   if (!plan || !bytes || n_iter < 0) return DFM_E_ARG;
-  *bytes = dfm::grad_tape_bytes(plan->d, plan->dtype, n_iter);
+  if (full && plan->d.MLX > 16) return DFM_E_SHAPE;
+  *bytes = dfm::grad_tape_bytes(plan->d, plan->dtype, n_iter, full);
   return DFM_OK;
 }
 
-dfm_status dfm_mm_forward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* stream) {
-  if (!plan || n_iter < 0 || (n_iter > 0 && !tape)) return DFM_E_ARG;
-  if (reinterpret_cast<uintptr_t>(tape) % 256 != 0 || tape_bytes < dfm::grad_tape_bytes(plan->d, plan->dtype, n_iter))
+dfm_status grad_tape_ok(const dfm_plan* plan, int32_t n_iter, bool full, const void* tape, size_t tape_bytes) {
+  if (full && plan->d.MLX > 16) return DFM_E_SHAPE;
+  if (reinterpret_cast<uintptr_t>(tape) % 256 != 0 ||
+      tape_bytes < dfm::grad_tape_bytes(plan->d, plan->dtype, n_iter, full))
     return DFM_E_WORKSPACE;
+  return DFM_OK;
+}
+
+// n_iter iterations on the plan's kernels, each after storing the state it starts from in the tape;
+// full: every stage (eqs. (14)-(16), then (8)-(10)), else the MM stages with Q fixed.
+dfm_status grad_forward(dfm_plan* plan, int32_t n_iter, bool full, void* tape, size_t tape_bytes, void* stream) {
+  if (!plan || n_iter < 0 || (n_iter > 0 && !tape)) return DFM_E_ARG;
+  if (n_iter > 0) {
+    const dfm_status st = grad_tape_ok(plan, n_iter, full, tape, tape_bytes);
+    if (st != DFM_OK) return st;
+  }
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const Dims& d = plan->d;
   const size_t r = plan->dtype == DFM_C64 ? 4 : 8;
   if (n_iter > 0 && d.fast >= 0 && dfm::run_kernel(plan, dfm::kFLam, s) != hipSuccess) return DFM_E_HIP;
   for (int it = 0; it < n_iter; ++it) {
-    void *cg, *cW, *cH;
-    dfm::grad_checkpoints(d, plan->dtype, n_iter, tape, it, &cg, &cW, &cH);
+    void *cQ, *cg, *cW, *cH;
+    dfm::grad_checkpoints(d, plan->dtype, n_iter, full, tape, it, &cQ, &cg, &cW, &cH);
     if (hipMemcpyAsync(cg, plan->b.g, r * d.F * d.N * d.M, hipMemcpyDeviceToDevice, s) != hipSuccess ||
         hipMemcpyAsync(cW, plan->b.W, r * d.N * d.F * d.K, hipMemcpyDeviceToDevice, s) != hipSuccess ||
         hipMemcpyAsync(cH, plan->b.H, r * d.N * d.K * d.T, hipMemcpyDeviceToDevice, s) != hipSuccess)
       return DFM_E_HIP;
-    for (int stage = DFM_STAGE_W; stage <= DFM_STAGE_G; ++stage)
+    if (full && hipMemcpyAsync(cQ, plan->b.Q, 2 * r * d.F * d.QF, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return DFM_E_HIP;
+    for (int stage = full ? DFM_STAGE_IP : DFM_STAGE_W; stage <= DFM_STAGE_G; ++stage)
       if (dfm::run_stage(plan, stage, s) != hipSuccess) return DFM_E_HIP;
     if (dfm::g_update_deferred(d) && dfm::run_kernel(plan, dfm::kFGFin, s) != hipSuccess) return DFM_E_HIP;
   }
   return DFM_OK;
 }
 
-dfm_status dfm_mm_backward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* dQ, void* dg,
-                           void* dW, void* dH, void* stream) {
+dfm_status grad_backward(dfm_plan* plan, int32_t n_iter, bool full, void* tape, size_t tape_bytes, void* dQ,
+                         void* dg, void* dW, void* dH, void* stream) {
   if (!plan || n_iter < 0 || !tape || !dQ || !dg || !dW || !dH) return DFM_E_ARG;
-  if (reinterpret_cast<uintptr_t>(tape) % 256 != 0 || tape_bytes < dfm::grad_tape_bytes(plan->d, plan->dtype, n_iter))
-    return DFM_E_WORKSPACE;
-  if (dfm::launch_mm_backward(plan->d, plan->b, plan->dtype, n_iter, tape, dQ, dg, dW, dH,
-                              static_cast<hipStream_t>(stream)) != hipSuccess)
+  const dfm_status st = grad_tape_ok(plan, n_iter, full, tape, tape_bytes);
+  if (st != DFM_OK) return st;
+  if (dfm::launch_grad_backward(plan->d, plan->b, plan->dtype, n_iter, full, tape, dQ, dg, dW, dH,
+                                static_cast<hipStream_t>(stream)) != hipSuccess)
     return DFM_E_HIP;
   return DFM_OK;
+}
+
+}  // namespace
+
+dfm_status dfm_mm_tape_size(const dfm_plan* plan, int32_t n_iter, size_t* bytes) {
+  return grad_tape_size(plan, n_iter, false, bytes);
+}
+
+dfm_status dfm_mm_forward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* stream) {
+  return grad_forward(plan, n_iter, false, tape, tape_bytes, stream);
+}
+
+dfm_status dfm_mm_backward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* dQ, void* dg,
+                           void* dW, void* dH, void* stream) {
+  return grad_backward(plan, n_iter, false, tape, tape_bytes, dQ, dg, dW, dH, stream);
+}
+
+dfm_status dfm_iter_tape_size(const dfm_plan* plan, int32_t n_iter, size_t* bytes) {
+  return grad_tape_size(plan, n_iter, true, bytes);
+}
+
+dfm_status dfm_iter_forward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* stream) {
+  return grad_forward(plan, n_iter, true, tape, tape_bytes, stream);
+}
+
+dfm_status dfm_iter_backward(dfm_plan* plan, int32_t n_iter, void* tape, size_t tape_bytes, void* dQ, void* dg,
+                             void* dW, void* dH, void* stream) {
+  return grad_backward(plan, n_iter, true, tape, tape_bytes, dQ, dg, dW, dH, stream);
 }
 
 dfm_status dfm_initialise_workspace_size(const dfm_problem* p, size_t* bytes) {

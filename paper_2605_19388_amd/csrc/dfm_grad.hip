@@ -1,6 +1,7 @@
-// Gradient of the cost (13) after n unrolled MM iterations (eqs. (8), (9), (10) in that order,
-// Q held fixed, the Sec. IV-A floors in place) with respect to the state the iterations started
-// from: reverse-mode, hand-written, in FP64 whatever the plan's precision.
+// Gradient of the cost (13) after n unrolled iterations with respect to the state the iterations
+// started from: reverse-mode, hand-written, in FP64 whatever the plan's precision, with the Sec.
+// IV-A floors in place.  Two maps: MM iterations (eqs. (8), (9), (10) in that order, Q held fixed)
+// and full iterations (eq. (14) and the IP sweep of eqs. (15)-(16), then (8)-(10)).
 //
 // The forward iterations run on the plan's own kernels and store the state (g, W, H) before each
 // iteration in the caller's tape (per-iteration checkpoints).  The reverse pass then starts from
@@ -27,6 +28,20 @@
 //   kb_frame   per bin, frames in chunks: the per-frame adjoints of one update (or of the cost),
 //              Pbar += ..., lambdabar, and the sums over frames into g's adjoint;
 //   kb_qgrad   the gradient with respect to Q.
+//
+// Full iterations.  Iteration i maps (Q_i, g_i, W_i, H_i) to Q_{i+1} = IP(Q_i, V(y_i)), then runs
+// the MM updates against P_{i+1} = |Q_{i+1} x|^2.  Going back through iteration i: the MM part as
+// above, with the adjoint of P_{i+1} gathered afresh; Qbar_{i+1} += 2 sum_t Pbar z conj(x); then
+// the sweep in reverse row order; then the covariances back to y_i and on to (g_i, W_i, H_i).  For
+// one row (A = Q V_mu with the rows before mu already updated, b = A^-1 e_mu, s = b^H V_mu b,
+// c = max(s, eps)^-1/2, row mu <- conj(c b)), with bhbar = conj(row mu of Qbar):
+//   cbar = Re(bhbar^H b),  sbar = -cbar c^3 / 2 [s > eps],  bbar = c bhbar + 2 sbar V_mu b,
+//   gamma = A^-H bbar,  Qbar <- Qbar (row mu zeroed) - gamma (V_mu b)^H,
+//   Vbar_mu = sbar b b^H - (Q^H gamma) b^H,
+// and from V_mu = (1/T) sum_t x x^H / y_mu:  ybar_mu(t) = -Re(x^H Vbar_mu x) / (T y_mu^2).
+// Kernels: kb_y (u = sum_n lambda g), kb_cov (V by eq. (14)), kb_ipfwd (the sweep, kept for
+// P_{i+1}), kb_ipbwd (the sweep's adjoint, one thread per block), kb_vbar (ybar), and kb_frame's
+// kBackY mode (ybar on to g, lambda).
 #include <hip/hip_runtime.h>
 
 #include "dfm_device.h"
@@ -38,13 +53,13 @@ constexpr int kB = 256;
 
 __device__ __forceinline__ double dsqrt_ratio(double a, double b, double eps) { return sqrt(a / (b > eps ? b : eps)); }
 
-template <typename R>
-__global__ __launch_bounds__(kB) void kb_powers(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+template <typename R, typename RQ>
+__global__ __launch_bounds__(kB) void kb_powers(Dims d, const cx<R>* __restrict__ X, const cx<RQ>* __restrict__ Q,
                                                 double* __restrict__ P) {
   const int f = blockIdx.x, t = blockIdx.y * kB + threadIdx.x;
   if (t >= d.T) return;
   const cx<R>* x = X + ((size_t)f * d.T + t) * d.M;
-  const cx<R>* qf = Q + (size_t)f * d.QF;
+  const cx<RQ>* qf = Q + (size_t)f * d.QF;
   double* p = P + ((size_t)f * d.T + t) * d.M;
   for (int l = 0; l < d.L; ++l) {
     const int ml = d.mics[l], o = d.moff[l], q0 = d.qoff[l];
@@ -189,7 +204,7 @@ __global__ __launch_bounds__(kB) void kb_mmback(int n, const R* __restrict__ th,
 }
 
 // Modes of kb_frame.
-enum { kCost = 0, kFwdG = 1, kBackG = 2, kBackWH = 3 };
+enum { kCost = 0, kFwdG = 1, kBackG = 2, kBackWH = 3, kBackY = 4 };
 
 // One workgroup per bin, frames in chunks of CH: phase 1 one thread per frame (per-frame
 // adjoints, Pbar, lambdabar; the terms that sum over frames go to LDS), phase 2 one thread per
@@ -198,6 +213,7 @@ enum { kCost = 0, kFwdG = 1, kBackG = 2, kBackWH = 3 };
 //   kFwdG:   the sums of eq. (10): gout = sum_t lambda P / y^2, gout2 = sum_t lambda / y.
 //   kBackG:  coefficients abar, bbar [F][N][M] of eq. (10): ybar, Pbar +=, lambdabar, gout +=.
 //   kBackWH: coefficients cbar, dbar [F][T][N] of eq. (8) or (9): ybar, Pbar +=, lambdabar, gout +=.
+//   kBackY:  ybar [F][T][M] given in c1 (from the covariances): lambdabar, gout +=; P, Pbar unused.
 template <typename RW, typename RH, typename RG, int MODE>
 __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W, const RH* __restrict__ H,
                                                const RG* __restrict__ g, const double* __restrict__ P,
@@ -247,7 +263,8 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
         double u = 0.0;
         for (int n = 0; n < N; ++n) u += lam[n] * sg[n * M + m];
         const bool live = u > d.eps;
-        const double y = live ? u : d.eps, iy = 1.0 / y, pm = P[ft * M + m], py2 = pm * iy * iy;
+        const double y = live ? u : d.eps, iy = 1.0 / y, pm = MODE == kBackY ? 0.0 : P[ft * M + m],
+                     py2 = pm * iy * iy;
         double ybar = 0.0, pbar = 0.0;
         if (MODE == kCost) {
           ybar = iy - py2;
@@ -265,13 +282,15 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
             ybar += gg * (cb[n] * (-2.0 * py2 * iy) - db[n] * iy * iy);
             pbar += cb[n] * gg * iy * iy;
           }
+        } else if (MODE == kBackY) {
+          ybar = c1[ft * M + m];
         }
         const double ubar = live ? ybar : 0.0;
         if (MODE != kFwdG) {
           for (int n = 0; n < N; ++n) lb[n] += ubar * sg[n * M + m];
           if (MODE == kCost)
             Pbar[ft * M + m] = pbar;
-          else
+          else if (MODE != kBackY)
             Pbar[ft * M + m] += pbar;
         }
         su[tid * M + m] = ubar;
@@ -324,14 +343,15 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
   }
 }
 
-// dL/dRe Q + i dL/dIm Q per (f, l) block: 2 sum_t Pbar z conj(x) - 2T Q^-H; Qinv from k_qinv.
-template <typename R>
-__global__ __launch_bounds__(kB) void kb_qgrad(Dims d, const cx<R>* __restrict__ X, const cx<R>* __restrict__ Q,
+// dL/dRe Q + i dL/dIm Q per (f, l) block: 2 sum_t Pbar z conj(x) - 2T Q^-H; Qinv from k_qinv, or
+// null for the first term alone; written, or added to dQ (`accumulate`).
+template <typename R, typename RQ, typename RO>
+__global__ __launch_bounds__(kB) void kb_qgrad(Dims d, const cx<R>* __restrict__ X, const cx<RQ>* __restrict__ Q,
                                                const cd* __restrict__ Qinv, const double* __restrict__ Pbar,
-                                               cx<R>* __restrict__ dQ) {
+                                               cx<RO>* __restrict__ dQ, int accumulate) {
   const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
   const int ml = d.mics[l], o = d.moff[l], q0 = d.qoff[l];
-  const cx<R>* qf = Q + (size_t)f * d.QF + q0;
+  const cx<RQ>* qf = Q + (size_t)f * d.QF + q0;
   for (int i = tid; i < ml * ml; i += kB) {  // entry (mu, c)
     const int mu = i / ml, c = i - mu * ml;
     double ar = 0.0, ai = 0.0;
@@ -347,9 +367,245 @@ __global__ __launch_bounds__(kB) void kb_qgrad(Dims d, const cx<R>* __restrict__
       ar += pb * (zr * xr + zi * xi);  // Re(z conj(x_c))
       ai += pb * (zi * xr - zr * xi);  // Im(z conj(x_c))
     }
-    const cd qi = Qinv[(size_t)f * d.QF + q0 + c * ml + mu];  // (Q^-1)_{c mu}; (Q^-H)_{mu c} = conj
-    dQ[(size_t)f * d.QF + q0 + i] = {(R)(2.0 * ar - 2.0 * d.T * qi.re), (R)(2.0 * ai + 2.0 * d.T * qi.im)};
+    double gr = 2.0 * ar, gi = 2.0 * ai;
+    if (Qinv) {
+      const cd qi = Qinv[(size_t)f * d.QF + q0 + c * ml + mu];  // (Q^-1)_{c mu}; (Q^-H)_{mu c} = conj
+      gr -= 2.0 * d.T * qi.re;
+      gi += 2.0 * d.T * qi.im;
+    }
+    cx<RO>& out = dQ[(size_t)f * d.QF + q0 + i];
+    if (accumulate) {
+      gr += (double)out.re;
+      gi += (double)out.im;
+    }
+    out = {(RO)gr, (RO)gi};
   }
+}
+
+// ---- Full iterations.
+
+// u[f][t][m] = sum_n lambda g (unfloored) for the state (W, H, g); grid (F, T / kB).
+template <typename RW, typename RH, typename RG>
+__global__ __launch_bounds__(kB) void kb_y(Dims d, const RW* __restrict__ W, const RH* __restrict__ H,
+                                           const RG* __restrict__ g, double* __restrict__ U) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sW = reinterpret_cast<double*>(smem);
+  double* sg = sW + d.N * d.K;
+  const int f = blockIdx.x, t = blockIdx.y * kB + threadIdx.x;
+  stage_bin(d, W, g, f, sW, sg);
+  __syncthreads();
+  if (t >= d.T) return;
+  double lam[kMaxN];
+  for (int n = 0; n < d.N; ++n) lam[n] = lam_at(d, sW, H, n, t);
+  for (int m = 0; m < d.M; ++m) {
+    double u = 0.0;
+    for (int n = 0; n < d.N; ++n) u += lam[n] * sg[n * d.M + m];
+    U[((size_t)f * d.T + t) * d.M + m] = u;
+  }
+}
+
+// Eq. (14) in full complex form: V[f][voff_l + (mu M_l + a) M_l + b] =
+// (1/T) sum_t x_a conj(x_b) / max(u_mu, eps) over subarray l's mics; one workgroup per bin.
+template <typename R>
+__global__ __launch_bounds__(kB) void kb_cov(Dims d, const cx<R>* __restrict__ X, const double* __restrict__ U,
+                                             cd* __restrict__ V) {
+  const int f = blockIdx.x;
+  for (int i = threadIdx.x; i < d.VC; i += kB) {
+    const int l = subarray_of_vidx(d, i), ml = d.mics[l], o = d.moff[l], r = i - d.voff[l];
+    const int mu = r / (ml * ml), ab = r - mu * ml * ml, a = ab / ml, b = ab - a * ml;
+    double sr = 0.0, si = 0.0;
+    for (int t = 0; t < d.T; ++t) {
+      const size_t ft = (size_t)f * d.T + t;
+      const cx<R> xa = X[ft * d.M + o + a], xb = X[ft * d.M + o + b];
+      const double u = U[ft * d.M + o + mu], w = 1.0 / (u > d.eps ? u : d.eps);
+      const double ar = xa.re, ai = xa.im, br = xb.re, bi = xb.im;
+      sr += w * (ar * br + ai * bi);
+      si += w * (ai * br - ar * bi);
+    }
+    V[(size_t)f * d.VC + i] = {sr / d.T, si / d.T};
+  }
+}
+
+// LU factorisation with partial pivoting of an m x m complex A (row-major in A[MX][MX], in place):
+// at step k rows k and piv[k] are swapped, so that P A = L U with L unit lower triangular.
+template <int MX>
+__device__ void lu_factor(int m, cd (&A)[MX][MX], int (&piv)[MX]) {
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    double best = cabs2(A[k][k]);
+    for (int r = k + 1; r < m; ++r)
+      if (cabs2(A[r][k]) > best) {
+        best = cabs2(A[r][k]);
+        p = r;
+      }
+    piv[k] = p;
+    if (p != k)
+      for (int c = 0; c < m; ++c) {
+        const cd tmp = A[k][c];
+        A[k][c] = A[p][c];
+        A[p][c] = tmp;
+      }
+    const cd inv = cinv(A[k][k]);  // a zero pivot gives non-finite results
+    for (int r = k + 1; r < m; ++r) {
+      const cd fac = cmul(A[r][k], inv);
+      A[r][k] = fac;
+      for (int c = k + 1; c < m; ++c) A[r][c] = cfms(A[r][c], fac, A[k][c]);
+    }
+  }
+}
+
+// x <- A^-1 x from lu_factor's output.
+template <int MX>
+__device__ void lu_solve(int m, const cd (&A)[MX][MX], const int (&piv)[MX], cd (&x)[MX]) {
+  for (int k = 0; k < m; ++k)
+    if (piv[k] != k) {
+      const cd tmp = x[k];
+      x[k] = x[piv[k]];
+      x[piv[k]] = tmp;
+    }
+  for (int r = 1; r < m; ++r)
+    for (int c = 0; c < r; ++c) x[r] = cfms(x[r], A[r][c], x[c]);
+  for (int r = m - 1; r >= 0; --r) {
+    cd acc = x[r];
+    for (int c = r + 1; c < m; ++c) acc = cfms(acc, A[r][c], x[c]);
+    x[r] = cmul(acc, cinv(A[r][r]));
+  }
+}
+
+// x <- A^-H x from lu_factor's output: A^H = U^H L^H P, so U^H w = x, L^H v = w, x = P^T v.
+template <int MX>
+__device__ void lu_solve_h(int m, const cd (&A)[MX][MX], const int (&piv)[MX], cd (&x)[MX]) {
+  for (int r = 0; r < m; ++r) {
+    cd acc = x[r];
+    for (int c = 0; c < r; ++c) acc = cfms(acc, cconj(A[c][r]), x[c]);
+    x[r] = cmul(acc, cinv(cconj(A[r][r])));
+  }
+  for (int r = m - 2; r >= 0; --r)
+    for (int c = r + 1; c < m; ++c) x[r] = cfms(x[r], cconj(A[c][r]), x[c]);
+  for (int k = m - 1; k >= 0; --k)
+    if (piv[k] != k) {
+      const cd tmp = x[k];
+      x[k] = x[piv[k]];
+      x[piv[k]] = tmp;
+    }
+}
+
+// One row of the sweep of a block: A = Q V_mu (Q row r from Qlo for r < mu, else from Qhi; both
+// row-major m x m in global memory), factorised into LU; b = A^-1 e_mu, Vb = V_mu b,
+// s = Re(b^H V_mu b).
+template <typename RQ, int MX>
+__device__ void ip_row(int m, int mu, const cd* Qlo, const cx<RQ>* __restrict__ Qhi,
+                       const cd* __restrict__ Vm, cd (&LU)[MX][MX], int (&piv)[MX], cd (&b)[MX], cd (&Vb)[MX],
+                       double& s) {
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < m; ++c) {
+      cd acc = {0.0, 0.0};
+      for (int k = 0; k < m; ++k) {
+        const cd q = r < mu ? Qlo[r * m + k] : cd{(double)Qhi[r * m + k].re, (double)Qhi[r * m + k].im};
+        acc = cfma(acc, q, Vm[k * m + c]);
+      }
+      LU[r][c] = acc;
+    }
+  lu_factor<MX>(m, LU, piv);
+  for (int r = 0; r < m; ++r) b[r] = {r == mu ? 1.0 : 0.0, 0.0};
+  lu_solve<MX>(m, LU, piv, b);
+  s = 0.0;
+  for (int r = 0; r < m; ++r) {
+    cd acc = {0.0, 0.0};
+    for (int c = 0; c < m; ++c) acc = cfma(acc, Vm[r * m + c], b[c]);
+    Vb[r] = acc;
+    s += b[r].re * acc.re + b[r].im * acc.im;  // Re(conj(b_r) (V b)_r)
+  }
+}
+
+// The IP sweep (eqs. (15)-(16)) of block (f, l) from Q (plan precision) and V: Q1 (FP64), the
+// updated rows written as they come; one thread per block.
+template <typename RQ, int MX>
+__global__ __launch_bounds__(64) void kb_ipfwd(Dims d, const cx<RQ>* __restrict__ Q, const cd* __restrict__ V,
+                                               cd* __restrict__ Q1) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= d.F * d.L) return;
+  const int f = i / d.L, l = i - f * d.L, m = d.mics[l];
+  const size_t q0 = (size_t)f * d.QF + d.qoff[l];
+  cd LU[MX][MX], b[MX], Vb[MX];
+  int piv[MX];
+  for (int mu = 0; mu < m; ++mu) {
+    double s;
+    ip_row<RQ, MX>(m, mu, Q1 + q0, Q + q0, V + (size_t)f * d.VC + d.voff[l] + (size_t)mu * m * m, LU, piv, b, Vb,
+                   s);
+    const double c = 1.0 / sqrt(s > d.eps ? s : d.eps);
+    for (int j = 0; j < m; ++j) Q1[q0 + mu * m + j] = {c * b[j].re, -c * b[j].im};
+  }
+}
+
+// Adjoint of the sweep of block (f, l): Qbar (in: of the sweep's output Q1; out: of its input Q0,
+// updated in place) and Vbar [f][voff_l + (mu M_l + a) M_l + b]; rows in reverse order, each
+// recomputed from Q1's rows ..mu-1 and Q0's rows mu...  One thread per block.
+template <typename RQ, int MX>
+__global__ __launch_bounds__(64) void kb_ipbwd(Dims d, const cx<RQ>* __restrict__ Q0, const cd* __restrict__ Q1,
+                                               const cd* __restrict__ V, cd* __restrict__ Qbar,
+                                               cd* __restrict__ Vbar) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= d.F * d.L) return;
+  const int f = i / d.L, l = i - f * d.L, m = d.mics[l];
+  const size_t q0 = (size_t)f * d.QF + d.qoff[l];
+  cd* Qb = Qbar + q0;
+  cd LU[MX][MX], b[MX], Vb[MX], bb[MX];
+  int piv[MX];
+  for (int mu = m - 1; mu >= 0; --mu) {
+    const size_t v0 = (size_t)f * d.VC + d.voff[l] + (size_t)mu * m * m;
+    double s;
+    ip_row<RQ, MX>(m, mu, Q1 + q0, Q0 + q0, V + v0, LU, piv, b, Vb, s);
+    const bool live = s > d.eps;
+    const double c = 1.0 / sqrt(live ? s : d.eps);
+    double cbar = 0.0;  // Re(bhbar^H b), bhbar = conj(row mu of Qbar)
+    for (int j = 0; j < m; ++j) cbar += Qb[mu * m + j].re * b[j].re - Qb[mu * m + j].im * b[j].im;
+    const double sbar = live ? -0.5 * cbar * c * c * c : 0.0;
+    for (int j = 0; j < m; ++j)
+      bb[j] = {c * Qb[mu * m + j].re + 2.0 * sbar * Vb[j].re, -c * Qb[mu * m + j].im + 2.0 * sbar * Vb[j].im};
+    lu_solve_h<MX>(m, LU, piv, bb);  // gamma
+    for (int j = 0; j < m; ++j) Qb[mu * m + j] = {0.0, 0.0};
+    for (int r = 0; r < m; ++r)
+      for (int j = 0; j < m; ++j) Qb[r * m + j] = cfms(Qb[r * m + j], bb[r], cconj(Vb[j]));
+    for (int a = 0; a < m; ++a) {
+      cd qg = {0.0, 0.0};  // (Q^H gamma)_a with the Q that row mu's step saw
+      for (int r = 0; r < m; ++r) {
+        const cd q = r < mu ? Q1[q0 + r * m + a] : cd{(double)Q0[q0 + r * m + a].re, (double)Q0[q0 + r * m + a].im};
+        qg = cfmac(qg, q, bb[r]);
+      }
+      const cd coef = {sbar * b[a].re - qg.re, sbar * b[a].im - qg.im};
+      for (int j = 0; j < m; ++j) Vbar[v0 + a * m + j] = cmul(coef, cconj(b[j]));
+    }
+  }
+}
+
+// ybar[f][t][o_l + mu] = -Re(x^H Vbar_mu x) / (T y^2), zero where y is floored; grid (F, T / kB).
+template <typename R>
+__global__ __launch_bounds__(kB) void kb_vbar(Dims d, const cx<R>* __restrict__ X, const double* __restrict__ U,
+                                              const cd* __restrict__ Vbar, double* __restrict__ Ybar) {
+  const int f = blockIdx.x, t = blockIdx.y * kB + threadIdx.x;
+  if (t >= d.T) return;
+  const size_t ft = (size_t)f * d.T + t;
+  const cx<R>* x = X + ft * d.M;
+  for (int l = 0; l < d.L; ++l) {
+    const int m = d.mics[l], o = d.moff[l];
+    for (int mu = 0; mu < m; ++mu) {
+      const cd* vb = Vbar + (size_t)f * d.VC + d.voff[l] + (size_t)mu * m * m;
+      double q = 0.0;  // Re(x^H Vbar x)
+      for (int a = 0; a < m; ++a) {
+        cd row = {0.0, 0.0};
+        for (int b = 0; b < m; ++b) row = cfma(row, vb[a * m + b], cd{(double)x[o + b].re, (double)x[o + b].im});
+        q += (double)x[o + a].re * row.re + (double)x[o + a].im * row.im;
+      }
+      const double u = U[ft * d.M + o + mu];
+      Ybar[ft * d.M + o + mu] = u > d.eps ? -q / ((double)d.T * u * u) : 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kB) void kb_zero(size_t n, double* __restrict__ p) {
+  const size_t i = (size_t)blockIdx.x * kB + threadIdx.x;
+  if (i < n) p[i] = 0.0;
 }
 
 template <typename R>
@@ -365,6 +621,10 @@ struct GradTape {
   void* ckg;  // [n_iter][F N M]
   void* ckW;  // [n_iter][N F K]
   void* ckH;  // [n_iter][N K T]
+  void* ckQ;  // full iterations: [n_iter][F QF] complex
+  cd *Q1, *Qbar;                                                  // full: [F][QF]
+  cd *V, *Vbar;                                                   // full: [F][VC]
+  double *U, *Ybar;                                               // full: [F][T][M]
   double *P, *Pbar, *lbar, *c0, *d0, *c1, *d1, *cb, *db;           // [F][T][M] / [F][T][N]
   double *aW, *bW, *aWb, *bWb, *W1, *Wacc;                        // [N][F][K]
   double *aH, *bH, *aHb, *bHb, *H1, *Hacc;                        // [N][K][T]
@@ -373,8 +633,9 @@ struct GradTape {
 
 static size_t alg(size_t x) { return (x + 255) / 256 * 256; }
 
-static size_t carve_tape(const Dims& d, int dtype, int n_iter, char* base, GradTape* t) {
+static size_t carve_tape(const Dims& d, int dtype, int n_iter, bool full, char* base, GradTape* t) {
   const size_t r = dtype == DFM_C64 ? 4 : 8;
+  const size_t FQ = (size_t)d.F * d.QF, FV = (size_t)d.F * d.VC;
   const size_t NG = (size_t)d.F * d.N * d.M, NW = (size_t)d.N * d.F * d.K, NH = (size_t)d.N * d.K * d.T;
   const size_t FTM = (size_t)d.F * d.T * d.M, FTN = (size_t)d.F * d.T * d.N;
   size_t off = 0;
@@ -387,6 +648,13 @@ static size_t carve_tape(const Dims& d, int dtype, int n_iter, char* base, GradT
   tt.ckg = take(r * NG * n_iter);
   tt.ckW = take(r * NW * n_iter);
   tt.ckH = take(r * NH * n_iter);
+  tt.ckQ = take(full ? 2 * r * FQ * n_iter : 0);
+  tt.Q1 = reinterpret_cast<cd*>(take(full ? 16 * FQ : 0));
+  tt.Qbar = reinterpret_cast<cd*>(take(full ? 16 * FQ : 0));
+  tt.V = reinterpret_cast<cd*>(take(full ? 16 * FV : 0));
+  tt.Vbar = reinterpret_cast<cd*>(take(full ? 16 * FV : 0));
+  tt.U = reinterpret_cast<double*>(take(full ? 8 * FTM : 0));
+  tt.Ybar = reinterpret_cast<double*>(take(full ? 8 * FTM : 0));
   double** ftm[] = {&tt.P, &tt.Pbar};
   for (double** p : ftm) *p = reinterpret_cast<double*>(take(8 * FTM));
   double** ftn[] = {&tt.lbar, &tt.c0, &tt.d0, &tt.c1, &tt.d1, &tt.cb, &tt.db};
@@ -401,15 +669,19 @@ static size_t carve_tape(const Dims& d, int dtype, int n_iter, char* base, GradT
   return off;
 }
 
-size_t grad_tape_bytes(const Dims& d, int dtype, int n_iter) { return carve_tape(d, dtype, n_iter, nullptr, nullptr); }
+size_t grad_tape_bytes(const Dims& d, int dtype, int n_iter, bool full) {
+  return carve_tape(d, dtype, n_iter, full, nullptr, nullptr);
+}
 
-void grad_checkpoints(const Dims& d, int dtype, int n_iter, void* tape, int it, void** g, void** W, void** H) {
+void grad_checkpoints(const Dims& d, int dtype, int n_iter, bool full, void* tape, int it, void** Q, void** g,
+                      void** W, void** H) {
   GradTape t;
-  carve_tape(d, dtype, n_iter, static_cast<char*>(tape), &t);
+  carve_tape(d, dtype, n_iter, full, static_cast<char*>(tape), &t);
   const size_t r = dtype == DFM_C64 ? 4 : 8;
   *g = static_cast<char*>(t.ckg) + r * (size_t)d.F * d.N * d.M * it;
   *W = static_cast<char*>(t.ckW) + r * (size_t)d.N * d.F * d.K * it;
   *H = static_cast<char*>(t.ckH) + r * (size_t)d.N * d.K * d.T * it;
+  if (Q) *Q = full ? static_cast<char*>(t.ckQ) + 2 * r * (size_t)d.F * d.QF * it : nullptr;
 }
 
 static unsigned nblk(size_t n) { return (unsigned)((n + grad::kB - 1) / grad::kB); }
@@ -426,23 +698,103 @@ static size_t frame_smem(const Dims& d, int ch) {
   return 8 * ((size_t)d.N * d.K + 3 * (size_t)d.N * d.M + (size_t)ch * (3 * d.N + 3 * d.M));
 }
 
+// Back through the MM updates of one iteration from its checkpoint (g0, W0, H0) against t.P: on
+// entry (gacc, Wacc, Hacc) hold the adjoints of the iteration's output, on exit those of its input
+// through the updates; Pbar gathers the adjoint of P.
 template <typename R>
-static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, void* tape, void* dQ, void* dg,
-                                void* dW, void* dH, hipStream_t s) {
+static void mm_back_iteration(const Dims& d, const GradTape& t, const R* g0, const R* W0, const R* H0,
+                              hipStream_t s) {
   using namespace grad;
-  const int dtype = sizeof(R) == 4 ? DFM_C64 : DFM_C128;
-  GradTape t;
-  carve_tape(d, dtype, n_iter, static_cast<char*>(tape), &t);
-  const cx<R>* X = static_cast<const cx<R>*>(b.X);
-  const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
   const int NG = d.F * d.N * d.M, NW = d.N * d.F * d.K, NH = d.N * d.K * d.T, FTN = d.F * d.T * d.N;
   const int CH = frame_chunk(d);
   const size_t fsm = frame_smem(d, CH), csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
   const dim3 ft(d.F, (d.T + kB - 1) / kB), blk(kB);
   const dim3 gW(nblk(NW)), gH(nblk(NH)), gG(nblk(NG)), gFTN(nblk(FTN));
   const double* nul = nullptr;
-  hipLaunchKernelGGL(kb_powers<R>, ft, blk, 0, s, d, X, Q, t.P);
-  // The cost's own gradient at the final state (the plan's current g, W, H).
+  // This iteration's forward from its checkpoint, in FP64: W1 (eq. (8)), H1 (eq. (9)), the sums
+  // of eq. (10).
+  hipLaunchKernelGGL((kb_coef<R, R, R>), ft, blk, csm, s, d, W0, H0, g0, t.P, t.c0, t.d0);
+  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.c0, (const R*)nullptr, nul, t.aW, 0);
+  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.d0, (const R*)nullptr, nul, t.bW, 0);
+  hipLaunchKernelGGL(kb_apply<R>, gW, blk, 0, s, NW, W0, t.aW, t.bW, d.eps, t.W1);
+  hipLaunchKernelGGL((kb_coef<double, R, R>), ft, blk, csm, s, d, (const double*)t.W1, H0, g0, t.P, t.c1, t.d1);
+  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.c1, (const double*)nullptr, nul,
+                     t.aH, 0);
+  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.d1, (const double*)nullptr, nul,
+                     t.bH, 0);
+  hipLaunchKernelGGL(kb_apply<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.H1);
+  hipLaunchKernelGGL((kb_frame<double, double, R, kFwdG>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1,
+                     (const double*)t.H1, g0, t.P, nul, nul, (double*)nullptr, (double*)nullptr, t.ag, t.bg, CH);
+  // Back through eq. (10): g1 = g0 sqrt(ag / max(bg, eps)) with lambda2 = W1 H1.
+  hipLaunchKernelGGL(kb_mmback<R>, gG, blk, 0, s, NG, g0, t.ag, t.bg, d.eps, t.gacc, t.agb, t.bgb);
+  hipLaunchKernelGGL((kb_frame<double, double, R, kBackG>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1,
+                     (const double*)t.H1, g0, t.P, (const double*)t.agb, (const double*)t.bgb, t.Pbar, t.lbar,
+                     t.gacc, (double*)nullptr, CH);
+  hipLaunchKernelGGL(kb_sum_t<double>, gW, blk, 0, s, d, (const double*)t.H1, t.lbar, (const double*)nullptr, nul,
+                     t.Wacc, 1);
+  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
+                     t.Hacc, 1);
+  // Back through eq. (9): H1 = H0 sqrt(aH / max(bH, eps)), aH = sum_f W1 c1, bH = sum_f W1 d1.
+  hipLaunchKernelGGL(kb_mmback<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.Hacc, t.aHb, t.bHb);
+  hipLaunchKernelGGL(kb_sum_t<double>, gW, blk, 0, s, d, (const double*)t.aHb, t.c1, (const double*)t.bHb, t.d1,
+                     t.Wacc, 1);
+  hipLaunchKernelGGL((kb_cbar<double, double>), gFTN, blk, 0, s, d, (const double*)t.W1, (const double*)t.aHb,
+                     (const double*)t.W1, (const double*)t.bHb, t.cb, t.db);
+  hipLaunchKernelGGL((kb_frame<double, R, R, kBackWH>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1, H0, g0, t.P,
+                     (const double*)t.cb, (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
+  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
+  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
+                     t.Hacc, 1);
+  // Back through eq. (8): W1 = W0 sqrt(aW / max(bW, eps)), aW = sum_t H0 c0, bW = sum_t H0 d0.
+  hipLaunchKernelGGL(kb_mmback<R>, gW, blk, 0, s, NW, W0, t.aW, t.bW, d.eps, t.Wacc, t.aWb, t.bWb);
+  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.aWb, t.c0, (const double*)t.bWb, t.d0,
+                     t.Hacc, 1);
+  hipLaunchKernelGGL((kb_cbar<double, R>), gFTN, blk, 0, s, d, (const double*)t.aWb, H0, (const double*)t.bWb, H0,
+                     t.cb, t.db);
+  hipLaunchKernelGGL((kb_frame<R, R, R, kBackWH>), dim3(d.F), blk, fsm, s, d, W0, H0, g0, t.P, (const double*)t.cb,
+                     (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
+  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
+  hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
+}
+
+template <typename RQ, int MX>
+static void ip_launch(const Dims& d, const GradTape& t, const cx<RQ>* Q0, bool backward, hipStream_t s) {
+  const dim3 grid((d.F * d.L + 63) / 64), blk(64);
+  if (backward)
+    hipLaunchKernelGGL((grad::kb_ipbwd<RQ, MX>), grid, blk, 0, s, d, Q0, (const cd*)t.Q1, (const cd*)t.V, t.Qbar,
+                       t.Vbar);
+  else
+    hipLaunchKernelGGL((grad::kb_ipfwd<RQ, MX>), grid, blk, 0, s, d, Q0, (const cd*)t.V, t.Q1);
+}
+
+template <typename RQ>
+static void ip_dispatch(const Dims& d, const GradTape& t, const cx<RQ>* Q0, bool backward, hipStream_t s) {
+  if (d.MLX <= 4)
+    ip_launch<RQ, 4>(d, t, Q0, backward, s);
+  else if (d.MLX <= 8)
+    ip_launch<RQ, 8>(d, t, Q0, backward, s);
+  else
+    ip_launch<RQ, 16>(d, t, Q0, backward, s);
+}
+
+template <typename R>
+static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, bool full, void* tape, void* dQ,
+                                void* dg, void* dW, void* dH, hipStream_t s) {
+  using namespace grad;
+  const int dtype = sizeof(R) == 4 ? DFM_C64 : DFM_C128;
+  GradTape t;
+  carve_tape(d, dtype, n_iter, full, static_cast<char*>(tape), &t);
+  const cx<R>* X = static_cast<const cx<R>*>(b.X);
+  const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
+  const int NG = d.F * d.N * d.M, NW = d.N * d.F * d.K, NH = d.N * d.K * d.T;
+  const size_t FTM = (size_t)d.F * d.T * d.M;
+  const int CH = frame_chunk(d);
+  const size_t fsm = frame_smem(d, CH), csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
+  const dim3 ft(d.F, (d.T + kB - 1) / kB), blk(kB);
+  const dim3 gW(nblk(NW)), gH(nblk(NH)), gG(nblk(NG));
+  const double* nul = nullptr;
+  hipLaunchKernelGGL((kb_powers<R, R>), ft, blk, 0, s, d, X, Q, t.P);
+  // The cost's own gradient at the final state (the plan's current Q, g, W, H).
   const R* gK = static_cast<const R*>(b.g);
   const R* WK = static_cast<const R*>(b.W);
   const R* HK = static_cast<const R*>(b.H);
@@ -450,72 +802,59 @@ static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, voi
                      t.lbar, t.gacc, (double*)nullptr, CH);
   hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, HK, t.lbar, (const R*)nullptr, nul, t.Wacc, 0);
   hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, WK, t.lbar, (const R*)nullptr, nul, t.Hacc, 0);
+  // Q^-1 of the final Q by the generic elimination kernel, for the log-determinant's term.
+  hipError_t e = launch_qinv(d, b, dtype, s);
+  if (e != hipSuccess) return e;
+  const cd* Qinv = static_cast<const cd*>(b.Qinv);
+  if (full)  // Qbar of the final Q now; P's adjoint is then gathered per iteration
+    hipLaunchKernelGGL((kb_qgrad<R, R, double>), dim3(d.F, d.L), blk, 0, s, d, X, Q, Qinv, t.Pbar,
+                       reinterpret_cast<cx<double>*>(t.Qbar), 0);
   for (int it = n_iter - 1; it >= 0; --it) {
-    void *pg, *pW, *pH;
-    grad_checkpoints(d, dtype, n_iter, tape, it, &pg, &pW, &pH);
+    void *pQ, *pg, *pW, *pH;
+    grad_checkpoints(d, dtype, n_iter, full, tape, it, &pQ, &pg, &pW, &pH);
     const R* g0 = static_cast<const R*>(pg);
     const R* W0 = static_cast<const R*>(pW);
     const R* H0 = static_cast<const R*>(pH);
-    // This iteration's forward from its checkpoint, in FP64: W1 (eq. (8)), H1 (eq. (9)), the sums
-    // of eq. (10).  (gacc, Wacc, Hacc) hold the adjoints of the iteration's output (g1, W1, H1).
-    hipLaunchKernelGGL((kb_coef<R, R, R>), ft, blk, csm, s, d, W0, H0, g0, t.P, t.c0, t.d0);
-    hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.c0, (const R*)nullptr, nul, t.aW, 0);
-    hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.d0, (const R*)nullptr, nul, t.bW, 0);
-    hipLaunchKernelGGL(kb_apply<R>, gW, blk, 0, s, NW, W0, t.aW, t.bW, d.eps, t.W1);
-    hipLaunchKernelGGL((kb_coef<double, R, R>), ft, blk, csm, s, d, (const double*)t.W1, H0, g0, t.P, t.c1, t.d1);
-    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.c1, (const double*)nullptr, nul,
-                       t.aH, 0);
-    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.d1, (const double*)nullptr, nul,
-                       t.bH, 0);
-    hipLaunchKernelGGL(kb_apply<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.H1);
-    hipLaunchKernelGGL((kb_frame<double, double, R, kFwdG>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1,
-                       (const double*)t.H1, g0, t.P, nul, nul, (double*)nullptr, (double*)nullptr, t.ag, t.bg, CH);
-    // Back through eq. (10): g1 = g0 sqrt(ag / max(bg, eps)) with lambda2 = W1 H1.
-    hipLaunchKernelGGL(kb_mmback<R>, gG, blk, 0, s, NG, g0, t.ag, t.bg, d.eps, t.gacc, t.agb, t.bgb);
-    hipLaunchKernelGGL((kb_frame<double, double, R, kBackG>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1,
-                       (const double*)t.H1, g0, t.P, (const double*)t.agb, (const double*)t.bgb, t.Pbar, t.lbar,
-                       t.gacc, (double*)nullptr, CH);
-    hipLaunchKernelGGL(kb_sum_t<double>, gW, blk, 0, s, d, (const double*)t.H1, t.lbar, (const double*)nullptr, nul,
-                       t.Wacc, 1);
-    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
-                       t.Hacc, 1);
-    // Back through eq. (9): H1 = H0 sqrt(aH / max(bH, eps)), aH = sum_f W1 c1, bH = sum_f W1 d1.
-    hipLaunchKernelGGL(kb_mmback<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.Hacc, t.aHb, t.bHb);
-    hipLaunchKernelGGL(kb_sum_t<double>, gW, blk, 0, s, d, (const double*)t.aHb, t.c1, (const double*)t.bHb, t.d1,
-                       t.Wacc, 1);
-    hipLaunchKernelGGL((kb_cbar<double, double>), gFTN, blk, 0, s, d, (const double*)t.W1, (const double*)t.aHb,
-                       (const double*)t.W1, (const double*)t.bHb, t.cb, t.db);
-    hipLaunchKernelGGL((kb_frame<double, R, R, kBackWH>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1, H0, g0,
-                       t.P, (const double*)t.cb, (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
-    hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
-    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
-                       t.Hacc, 1);
-    // Back through eq. (8): W1 = W0 sqrt(aW / max(bW, eps)), aW = sum_t H0 c0, bW = sum_t H0 d0.
-    hipLaunchKernelGGL(kb_mmback<R>, gW, blk, 0, s, NW, W0, t.aW, t.bW, d.eps, t.Wacc, t.aWb, t.bWb);
-    hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.aWb, t.c0, (const double*)t.bWb, t.d0,
-                       t.Hacc, 1);
-    hipLaunchKernelGGL((kb_cbar<double, R>), gFTN, blk, 0, s, d, (const double*)t.aWb, H0, (const double*)t.bWb, H0,
-                       t.cb, t.db);
-    hipLaunchKernelGGL((kb_frame<R, R, R, kBackWH>), dim3(d.F), blk, fsm, s, d, W0, H0, g0, t.P,
-                       (const double*)t.cb, (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
-    hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
-    hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
+    const cx<R>* Q0 = static_cast<const cx<R>*>(pQ);
+    if (full) {
+      // The sweep from the checkpoint: u, V (eq. (14)), Q_{i+1} (eqs. (15)-(16)), P_{i+1}.
+      hipLaunchKernelGGL((kb_y<R, R, R>), ft, blk, csm, s, d, W0, H0, g0, t.U);
+      hipLaunchKernelGGL(kb_cov<R>, dim3(d.F), blk, 0, s, d, X, (const double*)t.U, t.V);
+      ip_dispatch<R>(d, t, Q0, false, s);
+      hipLaunchKernelGGL((kb_powers<R, double>), ft, blk, 0, s, d, X, reinterpret_cast<const cx<double>*>(t.Q1), t.P);
+      hipLaunchKernelGGL(kb_zero, dim3(nblk(FTM)), blk, 0, s, FTM, t.Pbar);
+    }
+    mm_back_iteration<R>(d, t, g0, W0, H0, s);
+    if (full) {
+      // Qbar_{i+1} += 2 sum_t Pbar z conj(x) (z = Q_{i+1} x), then back through the sweep and the
+      // covariances to (g_i, W_i, H_i).
+      hipLaunchKernelGGL((kb_qgrad<R, double, double>), dim3(d.F, d.L), blk, 0, s, d, X,
+                         reinterpret_cast<const cx<double>*>(t.Q1), (const cd*)nullptr, t.Pbar,
+                         reinterpret_cast<cx<double>*>(t.Qbar), 1);
+      ip_dispatch<R>(d, t, Q0, true, s);
+      hipLaunchKernelGGL(kb_vbar<R>, ft, blk, 0, s, d, X, (const double*)t.U, (const cd*)t.Vbar, t.Ybar);
+      hipLaunchKernelGGL((kb_frame<R, R, R, kBackY>), dim3(d.F), blk, fsm, s, d, W0, H0, g0, t.P,
+                         (const double*)t.Ybar, nul, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
+      hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
+      hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
+    }
   }
-  // The gradient with respect to Q: Q^-1 by the generic elimination kernel, then the sums over frames.
-  hipError_t e = launch_qinv(d, b, dtype, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kb_qgrad<R>, dim3(d.F, d.L), blk, 0, s, d, X, Q, static_cast<const cd*>(b.Qinv), t.Pbar,
-                     static_cast<cx<R>*>(dQ));
+  if (full)
+    hipLaunchKernelGGL(kb_store<R>, dim3(nblk(2 * (size_t)d.F * d.QF)), blk, 0, s, 2 * d.F * d.QF,
+                       (const double*)t.Qbar, static_cast<R*>(dQ));
+  else  // Q fixed: P's adjoint from every iteration and the cost gives the gradient with respect to Q
+    hipLaunchKernelGGL((kb_qgrad<R, R, R>), dim3(d.F, d.L), blk, 0, s, d, X, Q, Qinv, t.Pbar,
+                       static_cast<cx<R>*>(dQ), 0);
   hipLaunchKernelGGL(kb_store<R>, gG, blk, 0, s, NG, (const double*)t.gacc, static_cast<R*>(dg));
   hipLaunchKernelGGL(kb_store<R>, gW, blk, 0, s, NW, (const double*)t.Wacc, static_cast<R*>(dW));
   hipLaunchKernelGGL(kb_store<R>, gH, blk, 0, s, NH, (const double*)t.Hacc, static_cast<R*>(dH));
   return hipGetLastError();
 }
 
-hipError_t launch_mm_backward(const Dims& d, const Buffers& b, int dtype, int n_iter, void* tape, void* dQ,
-                              void* dg, void* dW, void* dH, hipStream_t s) {
-  return dtype == DFM_C64 ? backward_impl<float>(d, b, n_iter, tape, dQ, dg, dW, dH, s)
-                          : backward_impl<double>(d, b, n_iter, tape, dQ, dg, dW, dH, s);
+hipError_t launch_grad_backward(const Dims& d, const Buffers& b, int dtype, int n_iter, bool full, void* tape,
+                                void* dQ, void* dg, void* dW, void* dH, hipStream_t s) {
+  return dtype == DFM_C64 ? backward_impl<float>(d, b, n_iter, full, tape, dQ, dg, dW, dH, s)
+                          : backward_impl<double>(d, b, n_iter, full, tape, dQ, dg, dW, dH, s);
 }
 
 }  // namespace dfm

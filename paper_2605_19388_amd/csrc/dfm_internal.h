@@ -120,11 +120,13 @@ hipError_t launch_covariances(const Dims& d, const Buffers& b, int dtype, void* 
 
 hipError_t launch_qinv(const Dims& d, const Buffers& b, int dtype, hipStream_t s);  // Q^-1 -> b.Qinv (generic)
 
-// Gradient of the cost after unrolled MM iterations (dfm_grad.hip).
-size_t grad_tape_bytes(const Dims& d, int dtype, int n_iter);
-void grad_checkpoints(const Dims& d, int dtype, int n_iter, void* tape, int it, void** g, void** W, void** H);
-hipError_t launch_mm_backward(const Dims& d, const Buffers& b, int dtype, int n_iter, void* tape, void* dQ,
-                              void* dg, void* dW, void* dH, hipStream_t s);
+// Gradient of the cost after unrolled MM iterations (full = false) or full iterations
+// (dfm_grad.hip).  Q's checkpoint exists for full iterations only (*Q = nullptr otherwise).
+size_t grad_tape_bytes(const Dims& d, int dtype, int n_iter, bool full);
+void grad_checkpoints(const Dims& d, int dtype, int n_iter, bool full, void* tape, int it, void** Q, void** g,
+                      void** W, void** H);
+hipError_t launch_grad_backward(const Dims& d, const Buffers& b, int dtype, int n_iter, bool full, void* tape,
+                                void* dQ, void* dg, void* dW, void* dH, hipStream_t s);
 
 // Initial parameters from source-image estimates (dfm_init.hip).
 size_t initialise_workspace_bytes(const Dims& d);

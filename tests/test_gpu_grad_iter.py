@@ -1,0 +1,181 @@
+"""Gradient of the cost after unrolled full iterations (eq. (14), the IP sweep of eqs. (15)-(16),
+then eqs. (8)-(10)) on the GPU -- the library's hand-written reverse pass, dfm_iter_forward /
+dfm_iter_backward -- against the oracle's (oracle/grad.py: PyTorch float64 autograd of a plain
+forward with its own solves, pinned by finite differences of oracle/dfmnmf.py), through the C ABI
+(GPU only).
+
+Each block of the gradient is compared entry by entry relative to the block's largest entry, with
+a tolerance set by the condition number kappa of the sweep's systems (the largest cond(Q_l V_mu)
+over bins, subarrays and rows at the start state): each solve of the sweep and of its adjoint
+loses about kappa units of rounding.  FP64 plans: <= max(1e-12, 10 kappa eps64) (measured up to
+1.8 kappa eps64).  FP32 plans: the checkpoints come from the FP32 forward and the reverse pass
+recomputes in FP64 from them, so the gradient is that of a trajectory rounded to FP32 at every
+iteration; these run on recordings with a higher noise floor (sensor noise 0.1: covariances away
+from rank N, kappa <= about 1e5) against 1e-4.  Each case's errors and kappa are reported.
+Subarrays of 1 to 16 mics cover the three compiled sizes of the per-block kernels (up to 4, 8 and
+16 mics)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dfmnmf as D
+from oracle import grad as G
+from paper_2605_19388_amd import synth
+from tests.common import random_state
+from tests.gpu_common import announce, as_precision, plan, report, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu(request):
+    require_gpu()
+    announce(request.node.nodeid)
+    yield
+    torch.cuda.synchronize()
+
+
+def _problem(F, T, mics, N, K, seed, fp32, mixing="delay", noise=1e-3):
+    X = synth.mixture(F, T, mics, N, K, seed, mixing=mixing, noise=noise)
+    Q, g, W, H = random_state(F, T, mics, N, K, seed + 1)
+    return tuple(as_precision(a, fp32) for a in (X, Q, g, W, H))
+
+
+def _kappa(X, Q, g, W, H, mics):
+    """Largest condition number of the sweep's first systems Q_l V_mu (eq. (14) at the start state)."""
+    V = D.weighted_covariances(X, D.model_variance(D.source_psd(W, H), g), mics)
+    return max(float(np.linalg.cond(Ql[:, None] @ Vl).max()) for Ql, Vl in zip(D.q_blocks(Q, mics), V))
+
+
+def _block_err(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def _gpu_grad(X, Q, g, W, H, mics, N, K, fp32, n_iter):
+    p = plan(X, mics, N, K, Q, g, W, H, fp32)
+    tape = p.iter_forward(n_iter)
+    cost = p.nll()
+    grads = p.iter_backward(tape)
+    torch.cuda.synchronize()
+    return cost, [t.cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64) for t in grads]
+
+
+CASES = [(7, 40, (2, 3), 3, 4, 1e-3), (9, 50, (4, 4, 4, 4), 5, 16, 1e-3), (5, 33, (2, 1), 2, 4, 1e-3),
+         (5, 100, (8, 3), 2, 3, 0.1), (4, 160, (16,), 3, 4, 0.1), (4, 40, (16,), 3, 4, 1e-3)]  # (..., sensor noise)
+
+
+def _case_id(c):
+    return "x".join(map(str, c[2])) + f"-T{c[1]}"
+
+
+@pytest.mark.parametrize("n_iter", [0, 1, 3])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=_case_id)
+def test_gradient_matches_oracle(case, fp32, n_iter):
+    F, T, mics, N, K, noise = case
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=17, fp32=fp32, noise=0.1 if fp32 else noise)
+    kappa = _kappa(X, Q, g, W, H, mics)
+    tol = 1e-4 if fp32 else max(1e-12, 10 * kappa * np.finfo(float).eps)
+    cost, (dQ, dg, dW, dH) = _gpu_grad(X, Q, g, W, H, mics, N, K, fp32, n_iter)
+    L, rQ, rg, rW, rH = G.iter_unrolled_grad(X, Q, g, W, H, mics, n_iter)
+    errs = {k: _block_err(a, b) for k, a, b in (("Q", dQ, rQ), ("g", dg, rg), ("W", dW, rW), ("H", dH, rH))}
+    ec = abs(cost - L) / max(abs(L), F * T * sum(mics))
+    report(f"iter gradient {case} {'fp32' if fp32 else 'fp64'} n={n_iter}: kappa {kappa:.1e}, tol {tol:.1e}; "
+           f"cost {ec:.1e}; " + ", ".join(f"d{k} {v:.1e}" for k, v in errs.items()))
+    assert ec < (1e-5 if fp32 else 1e-12)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+
+
+@pytest.mark.parametrize("mics", [(4, 4, 4, 4), (2, 3), (8, 3)], ids=lambda m: "x".join(map(str, m)))
+def test_first_rows_have_zero_gradient(mics):
+    """After a full iteration the cost does not depend on the first row of any block of Q (the sweep
+    overwrites it first, by a vector that the other rows fix up to a phase, and the cost ignores row
+    phases): that part of the GPU gradient is zero to rounding, the rest is not."""
+    F, T, N, K = 6, 40, 3, 4
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=29, fp32=False)
+    _, (dQ, *_) = _gpu_grad(X, Q, g, W, H, mics, N, K, False, 2)
+    blocks = D.q_blocks(dQ, mics)
+    top = max(np.abs(b).max() for b in blocks)
+    first = max(np.abs(b[:, 0, :]).max() for b in blocks)
+    report(f"first rows {mics}: max |dQ| there / max |dQ| = {first / top:.1e}")
+    assert first <= 1e-10 * top
+    assert max(np.abs(b[:, 1:, :]).max() for b in blocks) > 1e-3 * top
+
+
+def test_autograd_function_matches_the_abi():
+    from paper_2605_19388_amd.autograd import unrolled_iter_cost
+    F, T, mics, N, K = 5, 30, (2, 3), 2, 3
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=23, fp32=False, mixing="iid")
+    dev = torch.device("cuda:0")
+    ts = {k: torch.tensor(v, device=dev, requires_grad=True) for k, v in (("Q", Q), ("g", g), ("W", W), ("H", H))}
+    n_iter = 2
+    L = unrolled_iter_cost(torch.tensor(X, device=dev), ts["Q"], ts["g"], ts["W"], ts["H"], mics, n_iter)
+    L.backward()
+    cost, ref = _gpu_grad(X, Q, g, W, H, mics, N, K, False, n_iter)
+    assert float(L.detach()) == cost
+    for t, r in zip(ts.values(), ref):
+        np.testing.assert_array_equal(t.grad.cpu().numpy(), r)
+
+
+def test_tape_kinds_are_not_interchangeable():
+    F, T, mics, N, K = 4, 20, (2, 2), 2, 2
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=3, fp32=False)
+    p = plan(X, mics, N, K, Q, g, W, H, False)
+    tape = p.mm_forward(1)
+    with pytest.raises(ValueError):
+        p.iter_backward(tape)
+
+
+def test_backward_is_deterministic():
+    F, T, mics, N, K = 9, 50, (4, 4, 4, 4), 5, 16
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=31, fp32=True)
+    _, a = _gpu_grad(X, Q, g, W, H, mics, N, K, True, 3)
+    _, b = _gpu_grad(X, Q, g, W, H, mics, N, K, True, 3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_full_size_gradient_c4():
+    """paper_4x4 (F=513, T=625, four 4-mic subarrays, N=5, K=16), 10 unrolled full iterations.  The
+    FP64 plan's gradient against FP64 central differences of the FP64 plan's forward at sampled
+    entries of every block (rows 2..4 of Q's blocks: the first rows' gradient is zero); the FP32
+    plan's gradient against the FP64 plan's, per block."""
+    w = synth.make("paper_4x4")
+    mics, N, K, n_iter = w["mics"], w["N"], w["K"], 10
+    X, Q, g, W, H = (as_precision(w[k], True) for k in ("X", "Q", "g", "W", "H"))
+    Q = as_precision(random_state(w["F"], w["T"], mics, N, K, 77)[0], True)
+    c64, (d64Q, d64g, d64W, d64H) = _gpu_grad(X, Q, g, W, H, mics, N, K, False, n_iter)
+    c32, g32 = _gpu_grad(X, Q, g, W, H, mics, N, K, True, n_iter)
+    errs = {k: _block_err(a, b) for k, a, b in zip("QgWH", g32, (d64Q, d64g, d64W, d64H))}
+    report("C4 full size, full iterations, FP32 plan vs FP64 plan gradient: " +
+           ", ".join(f"d{k} {v:.1e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= 1e-4, (k, v)  # measured 1.0e-5
+
+    def cost_at(**kw):
+        st = dict(Q=Q, g=g, W=W, H=H)
+        st.update(kw)
+        p = plan(X, mics, N, K, st["Q"], st["g"], st["W"], st["H"], False)
+        p.iter_forward(n_iter)
+        return p.nll()
+    rng = np.random.Generator(np.random.PCG64(8))
+    worst = 0.0
+    # Step 1e-3 relative, as for the MM gradient at this size: the cost's FP64 rounding over a
+    # smaller step would swamp derivatives of order 1.
+    for k, v, grad in (("Q", Q, d64Q), ("g", g, d64g), ("W", W, d64W), ("H", H, d64H)):
+        for _ in range(2):
+            idx = tuple(int(rng.integers(0, s)) for s in v.shape)
+            if k == "Q":  # a row after the first of its block
+                idx = (idx[0], 16 * int(rng.integers(0, 4)) + 4 + int(rng.integers(0, 12)))
+            for unit in ((1.0, 1j) if np.iscomplexobj(v) else (1.0,)):
+                h = 1e-3 * abs(v[idx])
+                vp, vm = v.copy(), v.copy()
+                vp[idx] += unit * h
+                vm[idx] -= unit * h
+                fd = (cost_at(**{k: vp}) - cost_at(**{k: vm})) / (2 * h)
+                got = grad[idx].real if unit == 1.0 else grad[idx].imag
+                e = abs(got - fd) / max(abs(fd), 1e-3 * np.abs(grad).max())
+                worst = max(worst, e)
+                assert e <= 5e-4, (k, idx, unit, got, fd)  # measured 5.1e-5
+    report(f"C4 full size, full iterations, FP64 plan gradient vs central differences: worst {worst:.1e}")
