@@ -53,27 +53,23 @@ constexpr int kB = 256;
 
 __device__ __forceinline__ double dsqrt_ratio(double a, double b, double eps) { return sqrt(a / (b > eps ? b : eps)); }
 
+// P[f][t][m] = |(Q x)_m|^2 in FP64; one thread per (t, m) of bin f (grid (F, T M / kB)), so that
+// the threads of one frame share its x and write P coalesced.
 template <typename R, typename RQ>
 __global__ __launch_bounds__(kB) void kb_powers(Dims d, const cx<R>* __restrict__ X, const cx<RQ>* __restrict__ Q,
                                                 double* __restrict__ P) {
-  const int f = blockIdx.x, t = blockIdx.y * kB + threadIdx.x;
-  if (t >= d.T) return;
-  const cx<R>* x = X + ((size_t)f * d.T + t) * d.M;
-  const cx<RQ>* qf = Q + (size_t)f * d.QF;
-  double* p = P + ((size_t)f * d.T + t) * d.M;
-  for (int l = 0; l < d.L; ++l) {
-    const int ml = d.mics[l], o = d.moff[l], q0 = d.qoff[l];
-    for (int mu = 0; mu < ml; ++mu) {
-      double zr = 0.0, zi = 0.0;
-      for (int c = 0; c < ml; ++c) {
-        const double qr = qf[q0 + mu * ml + c].re, qi = qf[q0 + mu * ml + c].im;
-        const double xr = x[o + c].re, xi = x[o + c].im;
-        zr += qr * xr - qi * xi;
-        zi += qr * xi + qi * xr;
-      }
-      p[o + mu] = zr * zr + zi * zi;
-    }
+  const int f = blockIdx.x, i = blockIdx.y * kB + threadIdx.x;
+  if (i >= d.T * d.M) return;
+  const int t = i / d.M, m = i - t * d.M, l = d.msub[m], ml = d.mics[l], o = d.moff[l], mu = m - o;
+  const cx<R>* x = X + ((size_t)f * d.T + t) * d.M + o;
+  const cx<RQ>* q = Q + (size_t)f * d.QF + d.qoff[l] + mu * ml;
+  double zr = 0.0, zi = 0.0;
+  for (int c = 0; c < ml; ++c) {
+    const double qr = q[c].re, qi = q[c].im, xr = x[c].re, xi = x[c].im;
+    zr += qr * xr - qi * xi;
+    zi += qr * xi + qi * xr;
   }
+  P[((size_t)f * d.T + t) * d.M + m] = zr * zr + zi * zi;
 }
 
 // lambda_n at (f, t) from W (row of bin f staged in sW [N][K]) and H [N][K][T].
@@ -127,58 +123,80 @@ __global__ __launch_bounds__(kB) void kb_coef(Dims d, const RW* __restrict__ W, 
   }
 }
 
-// out[n][f][k] (+)= sum_t A1[n][k][t] C1[f][t][n] + A2[n][k][t] C2[f][t][n]; A of type RA.
+__device__ __forceinline__ double wave_sum(double v) {  // butterfly: every lane gets the sum, same order
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// out[n][f][k] (+)= sum_t A1[n][k][t] C1[f][t][n] + A2[n][k][t] C2[f][t][n]; A of type RA.  One
+// workgroup per (n, f), one wave per k, lanes over frames (coalesced rows of A), a butterfly sum.
 template <typename RA>
 __global__ __launch_bounds__(kB) void kb_sum_t(Dims d, const RA* __restrict__ A1, const double* __restrict__ C1,
                                                const RA* __restrict__ A2, const double* __restrict__ C2,
                                                double* __restrict__ out, int accumulate) {
-  const int i = blockIdx.x * kB + threadIdx.x;
-  if (i >= d.N * d.F * d.K) return;
-  const int n = i / (d.F * d.K), r = i - n * d.F * d.K, f = r / d.K, k = r - f * d.K;
-  const RA* a1 = A1 + ((size_t)n * d.K + k) * d.T;
-  const RA* a2 = A2 ? A2 + ((size_t)n * d.K + k) * d.T : nullptr;
-  double acc = 0.0;
-  for (int t = 0; t < d.T; ++t) {
-    const size_t ci = ((size_t)f * d.T + t) * d.N + n;
-    acc += (double)a1[t] * C1[ci];
-    if (a2) acc += (double)a2[t] * C2[ci];
+  const int n = blockIdx.x / d.F, f = blockIdx.x - n * d.F, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* c1 = C1 + (size_t)f * d.T * d.N + n;
+  const double* c2 = C2 ? C2 + (size_t)f * d.T * d.N + n : nullptr;
+  for (int k = w; k < d.K; k += kB / 64) {
+    const RA* a1 = A1 + ((size_t)n * d.K + k) * d.T;
+    const RA* a2 = A2 ? A2 + ((size_t)n * d.K + k) * d.T : nullptr;
+    double acc = 0.0;
+    for (int t = lane; t < d.T; t += 64) {
+      acc += (double)a1[t] * c1[(size_t)t * d.N];
+      if (a2) acc += (double)a2[t] * c2[(size_t)t * d.N];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      double& o = out[((size_t)n * d.F + f) * d.K + k];
+      o = accumulate ? o + acc : acc;
+    }
   }
-  out[i] = accumulate ? out[i] + acc : acc;
 }
 
-// out[n][k][t] (+)= sum_f A1[n][f][k] C1[f][t][n] + A2[n][f][k] C2[f][t][n].
+// out[n][k][t] (+)= sum_f A1[n][f][k] C1[f][t][n] + A2[n][f][k] C2[f][t][n].  Grid (N K, T / 64):
+// lanes over frames, the four waves over interleaved bins, their partials added in wave order.
 template <typename RA>
 __global__ __launch_bounds__(kB) void kb_sum_f(Dims d, const RA* __restrict__ A1, const double* __restrict__ C1,
                                                const RA* __restrict__ A2, const double* __restrict__ C2,
                                                double* __restrict__ out, int accumulate) {
-  const int i = blockIdx.x * kB + threadIdx.x;
-  if (i >= d.N * d.K * d.T) return;
-  const int n = i / (d.K * d.T), r = i - n * d.K * d.T, k = r / d.T, t = r - k * d.T;
+  __shared__ double part[kB];
+  const int n = blockIdx.x / d.K, k = blockIdx.x - n * d.K, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.y * 64 + lane;
   double acc = 0.0;
-  for (int f = 0; f < d.F; ++f) {
-    const size_t ai = ((size_t)n * d.F + f) * d.K + k, ci = ((size_t)f * d.T + t) * d.N + n;
-    acc += (double)A1[ai] * C1[ci];
-    if (A2) acc += (double)A2[ai] * C2[ci];
+  if (t < d.T)
+    for (int f = w; f < d.F; f += kB / 64) {
+      const size_t ai = ((size_t)n * d.F + f) * d.K + k, ci = ((size_t)f * d.T + t) * d.N + n;
+      acc += (double)A1[ai] * C1[ci];
+      if (A2) acc += (double)A2[ai] * C2[ci];
+    }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (w == 0 && t < d.T) {
+    double s = part[lane];
+    for (int j = 1; j < kB / 64; ++j) s += part[j * 64 + lane];
+    double& o = out[((size_t)n * d.K + k) * d.T + t];
+    o = accumulate ? o + s : s;
   }
-  out[i] = accumulate ? out[i] + acc : acc;
 }
 
-// out[f][t][n] = sum_k A[n][f][k] B[n][k][t] for (A1, B1) -> out1 and (A2, B2) -> out2.
+// out[f][t][n] = sum_k A[n][f][k] B[n][k][t] for (A1, B1) -> out1 and (A2, B2) -> out2; threads
+// ordered (f, n, t) so that rows of B are read coalesced.
 template <typename RA, typename RB>
 __global__ __launch_bounds__(kB) void kb_cbar(Dims d, const RA* __restrict__ A1, const RB* __restrict__ B1,
                                               const RA* __restrict__ A2, const RB* __restrict__ B2,
                                               double* __restrict__ out1, double* __restrict__ out2) {
   const int i = blockIdx.x * kB + threadIdx.x;
   if (i >= d.F * d.T * d.N) return;
-  const int f = i / (d.T * d.N), r = i - f * d.T * d.N, t = r / d.N, n = r - t * d.N;
+  const int f = i / (d.N * d.T), r = i - f * d.N * d.T, n = r / d.T, t = r - n * d.T;
   double s1 = 0.0, s2 = 0.0;
   for (int k = 0; k < d.K; ++k) {
     const size_t ai = ((size_t)n * d.F + f) * d.K + k, bi = ((size_t)n * d.K + k) * d.T + t;
     s1 += (double)A1[ai] * (double)B1[bi];
     s2 += (double)A2[ai] * (double)B2[bi];
   }
-  out1[i] = s1;
-  out2[i] = s2;
+  const size_t o = ((size_t)f * d.T + t) * d.N + n;
+  out1[o] = s1;
+  out2[o] = s2;
 }
 
 // theta1 = theta sqrt(a / max(b, eps)).
@@ -214,7 +232,7 @@ enum { kCost = 0, kFwdG = 1, kBackG = 2, kBackWH = 3, kBackY = 4 };
 //   kBackG:  coefficients abar, bbar [F][N][M] of eq. (10): ybar, Pbar +=, lambdabar, gout +=.
 //   kBackWH: coefficients cbar, dbar [F][T][N] of eq. (8) or (9): ybar, Pbar +=, lambdabar, gout +=.
 //   kBackY:  ybar [F][T][M] given in c1 (from the covariances): lambdabar, gout +=; P, Pbar unused.
-template <typename RW, typename RH, typename RG, int MODE>
+template <typename RW, typename RH, typename RG, int MODE, int NX>
 __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W, const RH* __restrict__ H,
                                                const RG* __restrict__ g, const double* __restrict__ P,
                                                const double* __restrict__ c1, const double* __restrict__ c2,
@@ -250,7 +268,7 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
     if (tid < nt) {
       const int t = t0 + tid;
       const size_t ft = (size_t)f * d.T + t;
-      double lam[kMaxN], lb[kMaxN], cb[kMaxN], db[kMaxN];
+      double lam[NX], lb[NX], cb[NX], db[NX];  // N <= NX
       for (int n = 0; n < N; ++n) {
         lam[n] = lam_at(d, sW, H, n, t);
         lb[n] = 0.0;
@@ -312,6 +330,7 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
       if (i >= N * M) break;
       const int n = i / M, m = i - n * M;
       double s1 = 0.0, s2 = 0.0;
+#pragma unroll 2
       for (int j = 0; j < nt; ++j) {
         const double lam = sl[j * N + n];
         if (MODE == kFwdG) {
@@ -344,41 +363,59 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
 }
 
 // dL/dRe Q + i dL/dIm Q per (f, l) block: 2 sum_t Pbar z conj(x) - 2T Q^-H; Qinv from k_qinv, or
-// null for the first term alone; written, or added to dQ (`accumulate`).
+// null for the first term alone; written, or added to dQ (`accumulate`).  Grid (F, L): where the
+// block's M_l^2 entries leave threads over, the frames are split into kB / M_l^2 interleaved
+// slices whose partials are added in slice order.
 template <typename R, typename RQ, typename RO>
 __global__ __launch_bounds__(kB) void kb_qgrad(Dims d, const cx<R>* __restrict__ X, const cx<RQ>* __restrict__ Q,
                                                const cd* __restrict__ Qinv, const double* __restrict__ Pbar,
                                                cx<RO>* __restrict__ dQ, int accumulate) {
+  __shared__ double part[2 * kB];
   const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
-  const int ml = d.mics[l], o = d.moff[l], q0 = d.qoff[l];
+  const int ml = d.mics[l], o = d.moff[l], q0 = d.qoff[l], E = ml * ml;
+  const int S = E <= kB ? kB / E : 1;  // frame slices
   const cx<RQ>* qf = Q + (size_t)f * d.QF + q0;
-  for (int i = tid; i < ml * ml; i += kB) {  // entry (mu, c)
-    const int mu = i / ml, c = i - mu * ml;
+  for (int i0 = 0; i0 < E; i0 += kB) {  // one pass unless M_l^2 > kB
+    const int e = S > 1 ? tid % E : i0 + tid, sl = S > 1 ? tid / E : 0;
     double ar = 0.0, ai = 0.0;
-    for (int t = 0; t < d.T; ++t) {
-      const cx<R>* x = X + ((size_t)f * d.T + t) * d.M + o;
-      double zr = 0.0, zi = 0.0;
-      for (int b = 0; b < ml; ++b) {
-        const double qr = qf[mu * ml + b].re, qi = qf[mu * ml + b].im, xr = x[b].re, xi = x[b].im;
-        zr += qr * xr - qi * xi;
-        zi += qr * xi + qi * xr;
+    if (e < E && sl < S) {
+      const int mu = e / ml, c = e - mu * ml;
+      for (int t = sl; t < d.T; t += S) {
+        const cx<R>* x = X + ((size_t)f * d.T + t) * d.M + o;
+        double zr = 0.0, zi = 0.0;
+        for (int b = 0; b < ml; ++b) {
+          const double qr = qf[mu * ml + b].re, qi = qf[mu * ml + b].im, xr = x[b].re, xi = x[b].im;
+          zr += qr * xr - qi * xi;
+          zi += qr * xi + qi * xr;
+        }
+        const double pb = Pbar[((size_t)f * d.T + t) * d.M + o + mu], xr = x[c].re, xi = x[c].im;
+        ar += pb * (zr * xr + zi * xi);  // Re(z conj(x_c))
+        ai += pb * (zi * xr - zr * xi);  // Im(z conj(x_c))
       }
-      const double pb = Pbar[((size_t)f * d.T + t) * d.M + o + mu], xr = x[c].re, xi = x[c].im;
-      ar += pb * (zr * xr + zi * xi);  // Re(z conj(x_c))
-      ai += pb * (zi * xr - zr * xi);  // Im(z conj(x_c))
     }
-    double gr = 2.0 * ar, gi = 2.0 * ai;
-    if (Qinv) {
-      const cd qi = Qinv[(size_t)f * d.QF + q0 + c * ml + mu];  // (Q^-1)_{c mu}; (Q^-H)_{mu c} = conj
-      gr -= 2.0 * d.T * qi.re;
-      gi += 2.0 * d.T * qi.im;
+    part[tid] = ar;
+    part[kB + tid] = ai;
+    __syncthreads();
+    if (sl == 0 && e < E) {
+      for (int j = 1; j < S; ++j) {
+        ar += part[tid + j * E];
+        ai += part[kB + tid + j * E];
+      }
+      const int mu = e / ml, c = e - mu * ml;
+      double gr = 2.0 * ar, gi = 2.0 * ai;
+      if (Qinv) {
+        const cd qi = Qinv[(size_t)f * d.QF + q0 + c * ml + mu];  // (Q^-1)_{c mu}; (Q^-H)_{mu c} = conj
+        gr -= 2.0 * d.T * qi.re;
+        gi += 2.0 * d.T * qi.im;
+      }
+      cx<RO>& out = dQ[(size_t)f * d.QF + q0 + e];
+      if (accumulate) {
+        gr += (double)out.re;
+        gi += (double)out.im;
+      }
+      out = {(RO)gr, (RO)gi};
     }
-    cx<RO>& out = dQ[(size_t)f * d.QF + q0 + i];
-    if (accumulate) {
-      gr += (double)out.re;
-      gi += (double)out.im;
-    }
-    out = {(RO)gr, (RO)gi};
+    __syncthreads();
   }
 }
 
@@ -579,28 +616,33 @@ __global__ __launch_bounds__(64) void kb_ipbwd(Dims d, const cx<RQ>* __restrict_
   }
 }
 
-// ybar[f][t][o_l + mu] = -Re(x^H Vbar_mu x) / (T y^2), zero where y is floored; grid (F, T / kB).
-template <typename R>
+// ybar[f][t][o_l + mu] = -Re(x^H Vbar_mu x) / (T y^2), zero where y is floored; one thread per
+// (t, m) of bin f (grid (F, T M / kB)); with LDS, the bin's Vbar is staged there first.
+template <typename R, bool LDS>
 __global__ __launch_bounds__(kB) void kb_vbar(Dims d, const cx<R>* __restrict__ X, const double* __restrict__ U,
                                               const cd* __restrict__ Vbar, double* __restrict__ Ybar) {
-  const int f = blockIdx.x, t = blockIdx.y * kB + threadIdx.x;
-  if (t >= d.T) return;
-  const size_t ft = (size_t)f * d.T + t;
-  const cx<R>* x = X + ft * d.M;
-  for (int l = 0; l < d.L; ++l) {
-    const int m = d.mics[l], o = d.moff[l];
-    for (int mu = 0; mu < m; ++mu) {
-      const cd* vb = Vbar + (size_t)f * d.VC + d.voff[l] + (size_t)mu * m * m;
-      double q = 0.0;  // Re(x^H Vbar x)
-      for (int a = 0; a < m; ++a) {
-        cd row = {0.0, 0.0};
-        for (int b = 0; b < m; ++b) row = cfma(row, vb[a * m + b], cd{(double)x[o + b].re, (double)x[o + b].im});
-        q += (double)x[o + a].re * row.re + (double)x[o + a].im * row.im;
-      }
-      const double u = U[ft * d.M + o + mu];
-      Ybar[ft * d.M + o + mu] = u > d.eps ? -q / ((double)d.T * u * u) : 0.0;
-    }
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int f = blockIdx.x, i = blockIdx.y * kB + threadIdx.x;
+  const cd* vf = Vbar + (size_t)f * d.VC;
+  if (LDS) {
+    cd* sv = reinterpret_cast<cd*>(smem);
+    for (int j = threadIdx.x; j < d.VC; j += kB) sv[j] = vf[j];
+    __syncthreads();
+    vf = sv;
   }
+  if (i >= d.T * d.M) return;
+  const int t = i / d.M, m = i - t * d.M, l = d.msub[m], ml = d.mics[l], o = d.moff[l], mu = m - o;
+  const size_t ft = (size_t)f * d.T + t;
+  const cx<R>* x = X + ft * d.M + o;
+  const cd* vb = vf + d.voff[l] + (size_t)mu * ml * ml;
+  double q = 0.0;  // Re(x^H Vbar x)
+  for (int a = 0; a < ml; ++a) {
+    cd row = {0.0, 0.0};
+    for (int b = 0; b < ml; ++b) row = cfma(row, vb[a * ml + b], cd{(double)x[b].re, (double)x[b].im});
+    q += (double)x[a].re * row.re + (double)x[a].im * row.im;
+  }
+  const double u = U[ft * d.M + m];
+  Ybar[ft * d.M + m] = u > d.eps ? -q / ((double)d.T * u * u) : 0.0;
 }
 
 __global__ __launch_bounds__(kB) void kb_zero(size_t n, double* __restrict__ p) {
@@ -698,6 +740,18 @@ static size_t frame_smem(const Dims& d, int ch) {
   return 8 * ((size_t)d.N * d.K + 3 * (size_t)d.N * d.M + (size_t)ch * (3 * d.N + 3 * d.M));
 }
 
+// kb_frame with per-thread arrays sized for N (8 or 16 sources): one workgroup per bin.
+template <typename RW, typename RH, typename RG, int MODE>
+static void frame(const Dims& d, size_t fsm, hipStream_t s, const RW* W, const RH* H, const RG* g, const double* P,
+                  const double* c1, const double* c2, double* Pbar, double* lbar, double* gout, double* gout2, int CH) {
+  if (d.N <= 8)
+    hipLaunchKernelGGL((grad::kb_frame<RW, RH, RG, MODE, 8>), dim3(d.F), dim3(grad::kB), fsm, s, d, W, H, g, P, c1,
+                       c2, Pbar, lbar, gout, gout2, CH);
+  else
+    hipLaunchKernelGGL((grad::kb_frame<RW, RH, RG, MODE, kMaxN>), dim3(d.F), dim3(grad::kB), fsm, s, d, W, H, g, P,
+                       c1, c2, Pbar, lbar, gout, gout2, CH);
+}
+
 // Back through the MM updates of one iteration from its checkpoint (g0, W0, H0) against t.P: on
 // entry (gacc, Wacc, Hacc) hold the adjoints of the iteration's output, on exit those of its input
 // through the updates; Pbar gathers the adjoint of P.
@@ -710,51 +764,52 @@ static void mm_back_iteration(const Dims& d, const GradTape& t, const R* g0, con
   const size_t fsm = frame_smem(d, CH), csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
   const dim3 ft(d.F, (d.T + kB - 1) / kB), blk(kB);
   const dim3 gW(nblk(NW)), gH(nblk(NH)), gG(nblk(NG)), gFTN(nblk(FTN));
+  const dim3 gSt(d.N * d.F), gSf(d.N * d.K, (d.T + 63) / 64);
   const double* nul = nullptr;
   // This iteration's forward from its checkpoint, in FP64: W1 (eq. (8)), H1 (eq. (9)), the sums
   // of eq. (10).
   hipLaunchKernelGGL((kb_coef<R, R, R>), ft, blk, csm, s, d, W0, H0, g0, t.P, t.c0, t.d0);
-  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.c0, (const R*)nullptr, nul, t.aW, 0);
-  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.d0, (const R*)nullptr, nul, t.bW, 0);
+  hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, H0, t.c0, (const R*)nullptr, nul, t.aW, 0);
+  hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, H0, t.d0, (const R*)nullptr, nul, t.bW, 0);
   hipLaunchKernelGGL(kb_apply<R>, gW, blk, 0, s, NW, W0, t.aW, t.bW, d.eps, t.W1);
   hipLaunchKernelGGL((kb_coef<double, R, R>), ft, blk, csm, s, d, (const double*)t.W1, H0, g0, t.P, t.c1, t.d1);
-  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.c1, (const double*)nullptr, nul,
+  hipLaunchKernelGGL(kb_sum_f<double>, gSf, blk, 0, s, d, (const double*)t.W1, t.c1, (const double*)nullptr, nul,
                      t.aH, 0);
-  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.d1, (const double*)nullptr, nul,
+  hipLaunchKernelGGL(kb_sum_f<double>, gSf, blk, 0, s, d, (const double*)t.W1, t.d1, (const double*)nullptr, nul,
                      t.bH, 0);
   hipLaunchKernelGGL(kb_apply<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.H1);
-  hipLaunchKernelGGL((kb_frame<double, double, R, kFwdG>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1,
+  frame<double, double, R, kFwdG>(d, fsm, s, (const double*)t.W1,
                      (const double*)t.H1, g0, t.P, nul, nul, (double*)nullptr, (double*)nullptr, t.ag, t.bg, CH);
   // Back through eq. (10): g1 = g0 sqrt(ag / max(bg, eps)) with lambda2 = W1 H1.
   hipLaunchKernelGGL(kb_mmback<R>, gG, blk, 0, s, NG, g0, t.ag, t.bg, d.eps, t.gacc, t.agb, t.bgb);
-  hipLaunchKernelGGL((kb_frame<double, double, R, kBackG>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1,
+  frame<double, double, R, kBackG>(d, fsm, s, (const double*)t.W1,
                      (const double*)t.H1, g0, t.P, (const double*)t.agb, (const double*)t.bgb, t.Pbar, t.lbar,
                      t.gacc, (double*)nullptr, CH);
-  hipLaunchKernelGGL(kb_sum_t<double>, gW, blk, 0, s, d, (const double*)t.H1, t.lbar, (const double*)nullptr, nul,
+  hipLaunchKernelGGL(kb_sum_t<double>, gSt, blk, 0, s, d, (const double*)t.H1, t.lbar, (const double*)nullptr, nul,
                      t.Wacc, 1);
-  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
+  hipLaunchKernelGGL(kb_sum_f<double>, gSf, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
                      t.Hacc, 1);
   // Back through eq. (9): H1 = H0 sqrt(aH / max(bH, eps)), aH = sum_f W1 c1, bH = sum_f W1 d1.
   hipLaunchKernelGGL(kb_mmback<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.Hacc, t.aHb, t.bHb);
-  hipLaunchKernelGGL(kb_sum_t<double>, gW, blk, 0, s, d, (const double*)t.aHb, t.c1, (const double*)t.bHb, t.d1,
+  hipLaunchKernelGGL(kb_sum_t<double>, gSt, blk, 0, s, d, (const double*)t.aHb, t.c1, (const double*)t.bHb, t.d1,
                      t.Wacc, 1);
   hipLaunchKernelGGL((kb_cbar<double, double>), gFTN, blk, 0, s, d, (const double*)t.W1, (const double*)t.aHb,
                      (const double*)t.W1, (const double*)t.bHb, t.cb, t.db);
-  hipLaunchKernelGGL((kb_frame<double, R, R, kBackWH>), dim3(d.F), blk, fsm, s, d, (const double*)t.W1, H0, g0, t.P,
+  frame<double, R, R, kBackWH>(d, fsm, s, (const double*)t.W1, H0, g0, t.P,
                      (const double*)t.cb, (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
-  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
-  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
+  hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
+  hipLaunchKernelGGL(kb_sum_f<double>, gSf, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
                      t.Hacc, 1);
   // Back through eq. (8): W1 = W0 sqrt(aW / max(bW, eps)), aW = sum_t H0 c0, bW = sum_t H0 d0.
   hipLaunchKernelGGL(kb_mmback<R>, gW, blk, 0, s, NW, W0, t.aW, t.bW, d.eps, t.Wacc, t.aWb, t.bWb);
-  hipLaunchKernelGGL(kb_sum_f<double>, gH, blk, 0, s, d, (const double*)t.aWb, t.c0, (const double*)t.bWb, t.d0,
+  hipLaunchKernelGGL(kb_sum_f<double>, gSf, blk, 0, s, d, (const double*)t.aWb, t.c0, (const double*)t.bWb, t.d0,
                      t.Hacc, 1);
   hipLaunchKernelGGL((kb_cbar<double, R>), gFTN, blk, 0, s, d, (const double*)t.aWb, H0, (const double*)t.bWb, H0,
                      t.cb, t.db);
-  hipLaunchKernelGGL((kb_frame<R, R, R, kBackWH>), dim3(d.F), blk, fsm, s, d, W0, H0, g0, t.P, (const double*)t.cb,
+  frame<R, R, R, kBackWH>(d, fsm, s, W0, H0, g0, t.P, (const double*)t.cb,
                      (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
-  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
-  hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
+  hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
+  hipLaunchKernelGGL(kb_sum_f<R>, gSf, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
 }
 
 template <typename RQ, int MX>
@@ -790,18 +845,19 @@ static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, boo
   const size_t FTM = (size_t)d.F * d.T * d.M;
   const int CH = frame_chunk(d);
   const size_t fsm = frame_smem(d, CH), csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
-  const dim3 ft(d.F, (d.T + kB - 1) / kB), blk(kB);
+  const dim3 ft(d.F, (d.T + kB - 1) / kB), blk(kB), ftm(d.F, (d.T * d.M + kB - 1) / kB);
   const dim3 gW(nblk(NW)), gH(nblk(NH)), gG(nblk(NG));
+  const dim3 gSt(d.N * d.F), gSf(d.N * d.K, (d.T + 63) / 64);
   const double* nul = nullptr;
-  hipLaunchKernelGGL((kb_powers<R, R>), ft, blk, 0, s, d, X, Q, t.P);
+  hipLaunchKernelGGL((kb_powers<R, R>), ftm, blk, 0, s, d, X, Q, t.P);
   // The cost's own gradient at the final state (the plan's current Q, g, W, H).
   const R* gK = static_cast<const R*>(b.g);
   const R* WK = static_cast<const R*>(b.W);
   const R* HK = static_cast<const R*>(b.H);
-  hipLaunchKernelGGL((kb_frame<R, R, R, kCost>), dim3(d.F), blk, fsm, s, d, WK, HK, gK, t.P, nul, nul, t.Pbar,
+  frame<R, R, R, kCost>(d, fsm, s, WK, HK, gK, t.P, nul, nul, t.Pbar,
                      t.lbar, t.gacc, (double*)nullptr, CH);
-  hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, HK, t.lbar, (const R*)nullptr, nul, t.Wacc, 0);
-  hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, WK, t.lbar, (const R*)nullptr, nul, t.Hacc, 0);
+  hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, HK, t.lbar, (const R*)nullptr, nul, t.Wacc, 0);
+  hipLaunchKernelGGL(kb_sum_f<R>, gSf, blk, 0, s, d, WK, t.lbar, (const R*)nullptr, nul, t.Hacc, 0);
   // Q^-1 of the final Q by the generic elimination kernel, for the log-determinant's term.
   hipError_t e = launch_qinv(d, b, dtype, s);
   if (e != hipSuccess) return e;
@@ -821,7 +877,8 @@ static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, boo
       hipLaunchKernelGGL((kb_y<R, R, R>), ft, blk, csm, s, d, W0, H0, g0, t.U);
       hipLaunchKernelGGL(kb_cov<R>, dim3(d.F), blk, 0, s, d, X, (const double*)t.U, t.V);
       ip_dispatch<R>(d, t, Q0, false, s);
-      hipLaunchKernelGGL((kb_powers<R, double>), ft, blk, 0, s, d, X, reinterpret_cast<const cx<double>*>(t.Q1), t.P);
+      hipLaunchKernelGGL((kb_powers<R, double>), ftm, blk, 0, s, d, X, reinterpret_cast<const cx<double>*>(t.Q1),
+                         t.P);
       hipLaunchKernelGGL(kb_zero, dim3(nblk(FTM)), blk, 0, s, FTM, t.Pbar);
     }
     mm_back_iteration<R>(d, t, g0, W0, H0, s);
@@ -832,11 +889,15 @@ static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, boo
                          reinterpret_cast<const cx<double>*>(t.Q1), (const cd*)nullptr, t.Pbar,
                          reinterpret_cast<cx<double>*>(t.Qbar), 1);
       ip_dispatch<R>(d, t, Q0, true, s);
-      hipLaunchKernelGGL(kb_vbar<R>, ft, blk, 0, s, d, X, (const double*)t.U, (const cd*)t.Vbar, t.Ybar);
-      hipLaunchKernelGGL((kb_frame<R, R, R, kBackY>), dim3(d.F), blk, fsm, s, d, W0, H0, g0, t.P,
+      if ((size_t)d.VC * sizeof(cd) <= 64 * 1024)
+        hipLaunchKernelGGL((kb_vbar<R, true>), ftm, blk, (size_t)d.VC * sizeof(cd), s, d, X, (const double*)t.U,
+                           (const cd*)t.Vbar, t.Ybar);
+      else
+        hipLaunchKernelGGL((kb_vbar<R, false>), ftm, blk, 0, s, d, X, (const double*)t.U, (const cd*)t.Vbar, t.Ybar);
+      frame<R, R, R, kBackY>(d, fsm, s, W0, H0, g0, t.P,
                          (const double*)t.Ybar, nul, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
-      hipLaunchKernelGGL(kb_sum_t<R>, gW, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
-      hipLaunchKernelGGL(kb_sum_f<R>, gH, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
+      hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
+      hipLaunchKernelGGL(kb_sum_f<R>, gSf, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
     }
   }
   if (full)
