@@ -224,9 +224,10 @@ __global__ __launch_bounds__(kB) void kb_mmback(int n, const R* __restrict__ th,
 // Modes of kb_frame.
 enum { kCost = 0, kFwdG = 1, kBackG = 2, kBackWH = 3, kBackY = 4 };
 
-// One workgroup per bin, frames in chunks of CH: phase 1 one thread per frame (per-frame
-// adjoints, Pbar, lambdabar; the terms that sum over frames go to LDS), phase 2 one thread per
-// (n, m) adding the chunk's terms in frame order.
+// One workgroup per (bin, slice of CH frames) (grid (F, ceil(T / CH))): phase 1 one thread per
+// frame (per-frame adjoints, Pbar, lambdabar; the terms that sum over frames go to LDS), phase 2
+// one thread per (n, m) adding the slice's terms in frame order into part[f][slice][2][N][M];
+// kb_gsum then adds the slices in order into gout (and gout2).
 //   kCost:   L's own gradient: ybar = 1/y - P/y^2, Pbar = 1/y (written), lambdabar, gout = g's.
 //   kFwdG:   the sums of eq. (10): gout = sum_t lambda P / y^2, gout2 = sum_t lambda / y.
 //   kBackG:  coefficients abar, bbar [F][N][M] of eq. (10): ybar, Pbar +=, lambdabar, gout +=.
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
                                                const RG* __restrict__ g, const double* __restrict__ P,
                                                const double* __restrict__ c1, const double* __restrict__ c2,
                                                double* __restrict__ Pbar, double* __restrict__ lbar,
-                                               double* __restrict__ gout, double* __restrict__ gout2, int CH) {
+                                               double* __restrict__ part, int CH) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = d.N, M = d.M, f = blockIdx.x, tid = threadIdx.x;
   double* sW = reinterpret_cast<double*>(smem);  // [N][K]
@@ -263,8 +264,8 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
   }
   double acc1[4] = {0, 0, 0, 0}, acc2[4] = {0, 0, 0, 0};  // phase 2: this thread's (n, m) entries
   __syncthreads();
-  for (int t0 = 0; t0 < d.T; t0 += CH) {
-    const int nt = min(CH, d.T - t0);
+  {
+    const int t0 = blockIdx.y * CH, nt = min(CH, d.T - t0);
     if (tid < nt) {
       const int t = t0 + tid;
       const size_t ft = (size_t)f * d.T + t;
@@ -345,20 +346,37 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
       acc1[e] += s1;
       acc2[e] += s2;
     }
-    __syncthreads();
   }
+  double* pf = part + ((size_t)f * gridDim.y + blockIdx.y) * 2 * N * M;
   for (int e = 0; e < 4; ++e) {
     const int i = tid + e * kB;
     if (i >= N * M) break;
-    const size_t o = (size_t)f * N * M + i;
-    if (MODE == kFwdG) {
-      gout[o] = acc1[e];
-      gout2[o] = acc2[e];
-    } else if (MODE == kCost) {
-      gout[o] = acc1[e];
-    } else {
-      gout[o] += acc1[e];
-    }
+    pf[i] = acc1[e];
+    if (MODE == kFwdG) pf[N * M + i] = acc2[e];
+  }
+}
+
+// The slices' partial sums of kb_frame, added in slice order: gout (and gout2 for kFwdG) written
+// (kCost, kFwdG) or added to.
+template <int MODE>
+__global__ __launch_bounds__(kB) void kb_gsum(Dims d, int S, const double* __restrict__ part,
+                                              double* __restrict__ gout, double* __restrict__ gout2) {
+  const int i = blockIdx.x * kB + threadIdx.x, NM = d.N * d.M;
+  if (i >= d.F * NM) return;
+  const int f = i / NM, e = i - f * NM;
+  const double* pf = part + (size_t)f * S * 2 * NM + e;
+  double s1 = 0.0, s2 = 0.0;
+  for (int s = 0; s < S; ++s) {
+    s1 += pf[(size_t)s * 2 * NM];
+    if (MODE == kFwdG) s2 += pf[(size_t)s * 2 * NM + NM];
+  }
+  if (MODE == kFwdG) {
+    gout[i] = s1;
+    gout2[i] = s2;
+  } else if (MODE == kCost) {
+    gout[i] = s1;
+  } else {
+    gout[i] += s1;
   }
 }
 
@@ -442,24 +460,41 @@ __global__ __launch_bounds__(kB) void kb_y(Dims d, const RW* __restrict__ W, con
 }
 
 // Eq. (14) in full complex form: V[f][voff_l + (mu M_l + a) M_l + b] =
-// (1/T) sum_t x_a conj(x_b) / max(u_mu, eps) over subarray l's mics; one workgroup per bin.
+// (1/T) sum_t x_a conj(x_b) / max(u_mu, eps) over subarray l's mics; one workgroup of kCovB threads
+// per bin.  Where the bin's entries leave threads over, the frames are split into kCovB / VC
+// interleaved slices whose partials are added in slice order.
+constexpr int kCovB = 1024;
 template <typename R>
-__global__ __launch_bounds__(kB) void kb_cov(Dims d, const cx<R>* __restrict__ X, const double* __restrict__ U,
-                                             cd* __restrict__ V) {
-  const int f = blockIdx.x;
-  for (int i = threadIdx.x; i < d.VC; i += kB) {
-    const int l = subarray_of_vidx(d, i), ml = d.mics[l], o = d.moff[l], r = i - d.voff[l];
-    const int mu = r / (ml * ml), ab = r - mu * ml * ml, a = ab / ml, b = ab - a * ml;
+__global__ __launch_bounds__(kCovB) void kb_cov(Dims d, const cx<R>* __restrict__ X, const double* __restrict__ U,
+                                                cd* __restrict__ V) {
+  __shared__ cd part[kCovB];
+  const int f = blockIdx.x, tid = threadIdx.x, E = d.VC;
+  const int S = E <= kCovB ? kCovB / E : 1;
+  for (int i0 = 0; i0 < E; i0 += kCovB) {  // one pass unless VC > kCovB
+    const int i = S > 1 ? tid % E : i0 + tid, sl = S > 1 ? tid / E : 0;
     double sr = 0.0, si = 0.0;
-    for (int t = 0; t < d.T; ++t) {
-      const size_t ft = (size_t)f * d.T + t;
-      const cx<R> xa = X[ft * d.M + o + a], xb = X[ft * d.M + o + b];
-      const double u = U[ft * d.M + o + mu], w = 1.0 / (u > d.eps ? u : d.eps);
-      const double ar = xa.re, ai = xa.im, br = xb.re, bi = xb.im;
-      sr += w * (ar * br + ai * bi);
-      si += w * (ai * br - ar * bi);
+    if (i < E && sl < S) {
+      const int l = subarray_of_vidx(d, i), ml = d.mics[l], o = d.moff[l], r = i - d.voff[l];
+      const int mu = r / (ml * ml), ab = r - mu * ml * ml, a = ab / ml, b = ab - a * ml;
+      for (int t = sl; t < d.T; t += S) {
+        const size_t ft = (size_t)f * d.T + t;
+        const cx<R> xa = X[ft * d.M + o + a], xb = X[ft * d.M + o + b];
+        const double u = U[ft * d.M + o + mu], w = 1.0 / (u > d.eps ? u : d.eps);
+        const double ar = xa.re, ai = xa.im, br = xb.re, bi = xb.im;
+        sr += w * (ar * br + ai * bi);
+        si += w * (ai * br - ar * bi);
+      }
     }
-    V[(size_t)f * d.VC + i] = {sr / d.T, si / d.T};
+    part[tid] = {sr, si};
+    __syncthreads();
+    if (sl == 0 && i < E) {
+      for (int j = 1; j < S; ++j) {
+        sr += part[tid + j * E].re;
+        si += part[tid + j * E].im;
+      }
+      V[(size_t)f * d.VC + i] = {sr / d.T, si / d.T};
+    }
+    __syncthreads();
   }
 }
 
@@ -617,24 +652,28 @@ __global__ __launch_bounds__(64) void kb_ipbwd(Dims d, const cx<RQ>* __restrict_
 }
 
 // ybar[f][t][o_l + mu] = -Re(x^H Vbar_mu x) / (T y^2), zero where y is floored; one thread per
-// (t, m) of bin f (grid (F, T M / kB)); with LDS, the bin's Vbar is staged there first.
+// (t, m) of bin f (grid (F, T M / kB)).  With LDS the bin's Vbar is staged there first, each
+// (l, mu) block followed by one pad entry: the block of mic m then starts at voff_l + m + mu M_l^2,
+// so the lanes of one frame, which read the same entry of their blocks, fall in distinct banks.
 template <typename R, bool LDS>
 __global__ __launch_bounds__(kB) void kb_vbar(Dims d, const cx<R>* __restrict__ X, const double* __restrict__ U,
                                               const cd* __restrict__ Vbar, double* __restrict__ Ybar) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int f = blockIdx.x, i = blockIdx.y * kB + threadIdx.x;
   const cd* vf = Vbar + (size_t)f * d.VC;
+  cd* sv = reinterpret_cast<cd*>(smem);
   if (LDS) {
-    cd* sv = reinterpret_cast<cd*>(smem);
-    for (int j = threadIdx.x; j < d.VC; j += kB) sv[j] = vf[j];
+    for (int j = threadIdx.x; j < d.VC; j += kB) {
+      const int l = subarray_of_vidx(d, j), ml2 = d.mics[l] * d.mics[l], r = j - d.voff[l], mu = r / ml2;
+      sv[j + d.moff[l] + mu] = vf[j];
+    }
     __syncthreads();
-    vf = sv;
   }
   if (i >= d.T * d.M) return;
   const int t = i / d.M, m = i - t * d.M, l = d.msub[m], ml = d.mics[l], o = d.moff[l], mu = m - o;
   const size_t ft = (size_t)f * d.T + t;
   const cx<R>* x = X + ft * d.M + o;
-  const cd* vb = vf + d.voff[l] + (size_t)mu * ml * ml;
+  const cd* vb = LDS ? sv + d.voff[l] + m + (size_t)mu * ml * ml : vf + d.voff[l] + (size_t)mu * ml * ml;
   double q = 0.0;  // Re(x^H Vbar x)
   for (int a = 0; a < ml; ++a) {
     cd row = {0.0, 0.0};
@@ -671,9 +710,24 @@ struct GradTape {
   double *aW, *bW, *aWb, *bWb, *W1, *Wacc;                        // [N][F][K]
   double *aH, *bH, *aHb, *bHb, *H1, *Hacc;                        // [N][K][T]
   double *ag, *bg, *agb, *bgb, *gacc;                             // [F][N][M]
+  double* fpart;                                                  // [F][ceil(T / CH)][2][N][M] (kb_frame)
 };
 
 static size_t alg(size_t x) { return (x + 255) / 256 * 256; }
+
+// Frames per kb_frame workgroup: as many as fit 48 KB of LDS next to the bin's W, g, abar, bbar,
+// at most 128.
+static int frame_chunk(const Dims& d) {
+  const size_t fixed = 8 * ((size_t)d.N * d.K + 3 * (size_t)d.N * d.M);
+  const size_t per = 8 * (3 * (size_t)d.N + 3 * (size_t)d.M);
+  size_t ch = fixed < 48 * 1024 ? (48 * 1024 - fixed) / per : 1;
+  if (ch > 128) ch = 128;
+  return ch < 1 ? 1 : (int)ch;
+}
+static int frame_slices(const Dims& d) { return (d.T + frame_chunk(d) - 1) / frame_chunk(d); }
+static size_t frame_smem(const Dims& d, int ch) {
+  return 8 * ((size_t)d.N * d.K + 3 * (size_t)d.N * d.M + (size_t)ch * (3 * d.N + 3 * d.M));
+}
 
 static size_t carve_tape(const Dims& d, int dtype, int n_iter, bool full, char* base, GradTape* t) {
   const size_t r = dtype == DFM_C64 ? 4 : 8;
@@ -707,6 +761,7 @@ static size_t carve_tape(const Dims& d, int dtype, int n_iter, bool full, char* 
   for (double** p : nh) *p = reinterpret_cast<double*>(take(8 * NH));
   double** ng[] = {&tt.ag, &tt.bg, &tt.agb, &tt.bgb, &tt.gacc};
   for (double** p : ng) *p = reinterpret_cast<double*>(take(8 * NG));
+  tt.fpart = reinterpret_cast<double*>(take(8 * 2 * NG * (size_t)frame_slices(d)));
   if (t) *t = tt;
   return off;
 }
@@ -728,28 +783,23 @@ void grad_checkpoints(const Dims& d, int dtype, int n_iter, bool full, void* tap
 
 static unsigned nblk(size_t n) { return (unsigned)((n + grad::kB - 1) / grad::kB); }
 
-// Chunk of frames of kb_frame: as many as fit 48 KB of LDS next to the bin's W, g, abar, bbar.
-static int frame_chunk(const Dims& d) {
-  const size_t fixed = 8 * ((size_t)d.N * d.K + 3 * (size_t)d.N * d.M);
-  const size_t per = 8 * (3 * (size_t)d.N + 3 * (size_t)d.M);
-  size_t ch = fixed < 48 * 1024 ? (48 * 1024 - fixed) / per : 1;
-  if (ch > (size_t)grad::kB) ch = grad::kB;
-  return ch < 1 ? 1 : (int)ch;
-}
-static size_t frame_smem(const Dims& d, int ch) {
-  return 8 * ((size_t)d.N * d.K + 3 * (size_t)d.N * d.M + (size_t)ch * (3 * d.N + 3 * d.M));
-}
 
-// kb_frame with per-thread arrays sized for N (8 or 16 sources): one workgroup per bin.
+// kb_frame (per-thread arrays sized for N: 8 or 16 sources) over (bin, slice), then kb_gsum.
 template <typename RW, typename RH, typename RG, int MODE>
-static void frame(const Dims& d, size_t fsm, hipStream_t s, const RW* W, const RH* H, const RG* g, const double* P,
-                  const double* c1, const double* c2, double* Pbar, double* lbar, double* gout, double* gout2, int CH) {
+static void frame(const Dims& d, const GradTape& t, hipStream_t s, const RW* W, const RH* H, const RG* g,
+                  const double* P, const double* c1, const double* c2, double* Pbar, double* lbar, double* gout,
+                  double* gout2) {
+  const int CH = frame_chunk(d), S = frame_slices(d);
+  const size_t fsm = frame_smem(d, CH);
+  const dim3 grid(d.F, S), blk(grad::kB);
   if (d.N <= 8)
-    hipLaunchKernelGGL((grad::kb_frame<RW, RH, RG, MODE, 8>), dim3(d.F), dim3(grad::kB), fsm, s, d, W, H, g, P, c1,
-                       c2, Pbar, lbar, gout, gout2, CH);
+    hipLaunchKernelGGL((grad::kb_frame<RW, RH, RG, MODE, 8>), grid, blk, fsm, s, d, W, H, g, P, c1, c2, Pbar, lbar,
+                       t.fpart, CH);
   else
-    hipLaunchKernelGGL((grad::kb_frame<RW, RH, RG, MODE, kMaxN>), dim3(d.F), dim3(grad::kB), fsm, s, d, W, H, g, P,
-                       c1, c2, Pbar, lbar, gout, gout2, CH);
+    hipLaunchKernelGGL((grad::kb_frame<RW, RH, RG, MODE, kMaxN>), grid, blk, fsm, s, d, W, H, g, P, c1, c2, Pbar,
+                       lbar, t.fpart, CH);
+  hipLaunchKernelGGL(grad::kb_gsum<MODE>, dim3(nblk((size_t)d.F * d.N * d.M)), blk, 0, s, d, S,
+                     (const double*)t.fpart, gout, gout2);
 }
 
 // Back through the MM updates of one iteration from its checkpoint (g0, W0, H0) against t.P: on
@@ -760,8 +810,7 @@ static void mm_back_iteration(const Dims& d, const GradTape& t, const R* g0, con
                               hipStream_t s) {
   using namespace grad;
   const int NG = d.F * d.N * d.M, NW = d.N * d.F * d.K, NH = d.N * d.K * d.T, FTN = d.F * d.T * d.N;
-  const int CH = frame_chunk(d);
-  const size_t fsm = frame_smem(d, CH), csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
+  const size_t csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
   const dim3 ft(d.F, (d.T + kB - 1) / kB), blk(kB);
   const dim3 gW(nblk(NW)), gH(nblk(NH)), gG(nblk(NG)), gFTN(nblk(FTN));
   const dim3 gSt(d.N * d.F), gSf(d.N * d.K, (d.T + 63) / 64);
@@ -778,13 +827,13 @@ static void mm_back_iteration(const Dims& d, const GradTape& t, const R* g0, con
   hipLaunchKernelGGL(kb_sum_f<double>, gSf, blk, 0, s, d, (const double*)t.W1, t.d1, (const double*)nullptr, nul,
                      t.bH, 0);
   hipLaunchKernelGGL(kb_apply<R>, gH, blk, 0, s, NH, H0, t.aH, t.bH, d.eps, t.H1);
-  frame<double, double, R, kFwdG>(d, fsm, s, (const double*)t.W1,
-                     (const double*)t.H1, g0, t.P, nul, nul, (double*)nullptr, (double*)nullptr, t.ag, t.bg, CH);
+  frame<double, double, R, kFwdG>(d, t, s, (const double*)t.W1,
+                     (const double*)t.H1, g0, t.P, nul, nul, (double*)nullptr, (double*)nullptr, t.ag, t.bg);
   // Back through eq. (10): g1 = g0 sqrt(ag / max(bg, eps)) with lambda2 = W1 H1.
   hipLaunchKernelGGL(kb_mmback<R>, gG, blk, 0, s, NG, g0, t.ag, t.bg, d.eps, t.gacc, t.agb, t.bgb);
-  frame<double, double, R, kBackG>(d, fsm, s, (const double*)t.W1,
+  frame<double, double, R, kBackG>(d, t, s, (const double*)t.W1,
                      (const double*)t.H1, g0, t.P, (const double*)t.agb, (const double*)t.bgb, t.Pbar, t.lbar,
-                     t.gacc, (double*)nullptr, CH);
+                     t.gacc, (double*)nullptr);
   hipLaunchKernelGGL(kb_sum_t<double>, gSt, blk, 0, s, d, (const double*)t.H1, t.lbar, (const double*)nullptr, nul,
                      t.Wacc, 1);
   hipLaunchKernelGGL(kb_sum_f<double>, gSf, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
@@ -795,8 +844,8 @@ static void mm_back_iteration(const Dims& d, const GradTape& t, const R* g0, con
                      t.Wacc, 1);
   hipLaunchKernelGGL((kb_cbar<double, double>), gFTN, blk, 0, s, d, (const double*)t.W1, (const double*)t.aHb,
                      (const double*)t.W1, (const double*)t.bHb, t.cb, t.db);
-  frame<double, R, R, kBackWH>(d, fsm, s, (const double*)t.W1, H0, g0, t.P,
-                     (const double*)t.cb, (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
+  frame<double, R, R, kBackWH>(d, t, s, (const double*)t.W1, H0, g0, t.P,
+                     (const double*)t.cb, (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr);
   hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
   hipLaunchKernelGGL(kb_sum_f<double>, gSf, blk, 0, s, d, (const double*)t.W1, t.lbar, (const double*)nullptr, nul,
                      t.Hacc, 1);
@@ -806,8 +855,8 @@ static void mm_back_iteration(const Dims& d, const GradTape& t, const R* g0, con
                      t.Hacc, 1);
   hipLaunchKernelGGL((kb_cbar<double, R>), gFTN, blk, 0, s, d, (const double*)t.aWb, H0, (const double*)t.bWb, H0,
                      t.cb, t.db);
-  frame<R, R, R, kBackWH>(d, fsm, s, W0, H0, g0, t.P, (const double*)t.cb,
-                     (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
+  frame<R, R, R, kBackWH>(d, t, s, W0, H0, g0, t.P, (const double*)t.cb,
+                     (const double*)t.db, t.Pbar, t.lbar, t.gacc, (double*)nullptr);
   hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
   hipLaunchKernelGGL(kb_sum_f<R>, gSf, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
 }
@@ -843,8 +892,7 @@ static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, boo
   const cx<R>* Q = static_cast<const cx<R>*>(b.Q);
   const int NG = d.F * d.N * d.M, NW = d.N * d.F * d.K, NH = d.N * d.K * d.T;
   const size_t FTM = (size_t)d.F * d.T * d.M;
-  const int CH = frame_chunk(d);
-  const size_t fsm = frame_smem(d, CH), csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
+  const size_t csm = 8 * ((size_t)d.N * d.K + (size_t)d.N * d.M);
   const dim3 ft(d.F, (d.T + kB - 1) / kB), blk(kB), ftm(d.F, (d.T * d.M + kB - 1) / kB);
   const dim3 gW(nblk(NW)), gH(nblk(NH)), gG(nblk(NG));
   const dim3 gSt(d.N * d.F), gSf(d.N * d.K, (d.T + 63) / 64);
@@ -854,8 +902,8 @@ static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, boo
   const R* gK = static_cast<const R*>(b.g);
   const R* WK = static_cast<const R*>(b.W);
   const R* HK = static_cast<const R*>(b.H);
-  frame<R, R, R, kCost>(d, fsm, s, WK, HK, gK, t.P, nul, nul, t.Pbar,
-                     t.lbar, t.gacc, (double*)nullptr, CH);
+  frame<R, R, R, kCost>(d, t, s, WK, HK, gK, t.P, nul, nul, t.Pbar,
+                     t.lbar, t.gacc, (double*)nullptr);
   hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, HK, t.lbar, (const R*)nullptr, nul, t.Wacc, 0);
   hipLaunchKernelGGL(kb_sum_f<R>, gSf, blk, 0, s, d, WK, t.lbar, (const R*)nullptr, nul, t.Hacc, 0);
   // Q^-1 of the final Q by the generic elimination kernel, for the log-determinant's term.
@@ -875,7 +923,7 @@ static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, boo
     if (full) {
       // The sweep from the checkpoint: u, V (eq. (14)), Q_{i+1} (eqs. (15)-(16)), P_{i+1}.
       hipLaunchKernelGGL((kb_y<R, R, R>), ft, blk, csm, s, d, W0, H0, g0, t.U);
-      hipLaunchKernelGGL(kb_cov<R>, dim3(d.F), blk, 0, s, d, X, (const double*)t.U, t.V);
+      hipLaunchKernelGGL(kb_cov<R>, dim3(d.F), dim3(kCovB), 0, s, d, X, (const double*)t.U, t.V);
       ip_dispatch<R>(d, t, Q0, false, s);
       hipLaunchKernelGGL((kb_powers<R, double>), ftm, blk, 0, s, d, X, reinterpret_cast<const cx<double>*>(t.Q1),
                          t.P);
@@ -889,13 +937,13 @@ static hipError_t backward_impl(const Dims& d, const Buffers& b, int n_iter, boo
                          reinterpret_cast<const cx<double>*>(t.Q1), (const cd*)nullptr, t.Pbar,
                          reinterpret_cast<cx<double>*>(t.Qbar), 1);
       ip_dispatch<R>(d, t, Q0, true, s);
-      if ((size_t)d.VC * sizeof(cd) <= 64 * 1024)
-        hipLaunchKernelGGL((kb_vbar<R, true>), ftm, blk, (size_t)d.VC * sizeof(cd), s, d, X, (const double*)t.U,
-                           (const cd*)t.Vbar, t.Ybar);
+      if ((size_t)(d.VC + d.M) * sizeof(cd) <= 64 * 1024)
+        hipLaunchKernelGGL((kb_vbar<R, true>), ftm, blk, (size_t)(d.VC + d.M) * sizeof(cd), s, d, X,
+                           (const double*)t.U, (const cd*)t.Vbar, t.Ybar);
       else
         hipLaunchKernelGGL((kb_vbar<R, false>), ftm, blk, 0, s, d, X, (const double*)t.U, (const cd*)t.Vbar, t.Ybar);
-      frame<R, R, R, kBackY>(d, fsm, s, W0, H0, g0, t.P,
-                         (const double*)t.Ybar, nul, t.Pbar, t.lbar, t.gacc, (double*)nullptr, CH);
+      frame<R, R, R, kBackY>(d, t, s, W0, H0, g0, t.P,
+                         (const double*)t.Ybar, nul, t.Pbar, t.lbar, t.gacc, (double*)nullptr);
       hipLaunchKernelGGL(kb_sum_t<R>, gSt, blk, 0, s, d, H0, t.lbar, (const R*)nullptr, nul, t.Wacc, 1);
       hipLaunchKernelGGL(kb_sum_f<R>, gSf, blk, 0, s, d, W0, t.lbar, (const R*)nullptr, nul, t.Hacc, 1);
     }
