@@ -49,7 +49,8 @@ def _gpu_grad(X, Q, g, W, H, mics, N, K, fp32, n_iter):
     return cost, [t.cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64) for t in grads]
 
 
-CASES = [(7, 40, (2, 3), 3, 4), (9, 50, (4, 4, 4, 4), 5, 16), (5, 33, (2, 2), 2, 4), (4, 30, (16,), 3, 4)]
+CASES = [(7, 40, (2, 3), 3, 4), (9, 50, (4, 4, 4, 4), 5, 16), (5, 33, (2, 2), 2, 4), (4, 30, (16,), 3, 4),
+         (5, 60, (3, 3, 4), 9, 3)]  # N = 9: the frame kernel's 16-source form
 
 
 @pytest.mark.parametrize("n_iter", [0, 1, 3])
@@ -120,7 +121,7 @@ def test_autograd_function_and_finite_differences():
                 vm[idx] -= unit * h
                 fd = (cost_at(**{k: vp}) - cost_at(**{k: vm})) / (2 * h)
                 got = grad[idx].real if unit == 1.0 else grad[idx].imag
-                assert abs(got - fd) <= 1e-5 * max(abs(fd), 1e-3 * abs(float(L)) / v.size), (k, idx, unit, got, fd)
+                assert abs(got - fd) <= 1e-5 * max(abs(fd), 1e-3 * abs(float(L.detach())) / v.size), (k, idx, unit, got, fd)
 
 
 def test_backward_is_deterministic():

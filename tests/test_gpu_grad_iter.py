@@ -61,7 +61,8 @@ def _gpu_grad(X, Q, g, W, H, mics, N, K, fp32, n_iter):
 
 
 CASES = [(7, 40, (2, 3), 3, 4, 1e-3), (9, 50, (4, 4, 4, 4), 5, 16, 1e-3), (5, 33, (2, 1), 2, 4, 1e-3),
-         (5, 100, (8, 3), 2, 3, 0.1), (4, 160, (16,), 3, 4, 0.1), (4, 40, (16,), 3, 4, 1e-3)]  # (..., sensor noise)
+         (5, 100, (8, 3), 2, 3, 0.1), (4, 160, (16,), 3, 4, 0.1), (4, 40, (16,), 3, 4, 1e-3),
+         (5, 60, (3, 3, 4), 9, 3, 0.1)]  # (F, T, mics, N, K, sensor noise); N = 9: the 16-source frame kernel
 
 
 def _case_id(c):
@@ -116,6 +117,19 @@ def test_autograd_function_matches_the_abi():
     assert float(L.detach()) == cost
     for t, r in zip(ts.values(), ref):
         np.testing.assert_array_equal(t.grad.cpu().numpy(), r)
+
+
+def test_subarrays_beyond_16_mics_are_refused():
+    """The sweep's adjoint keeps one block's LU per thread, sized for at most 16 mics: a 17-mic
+    subarray is refused (DFM_E_SHAPE) before anything runs; the MM-only gradient still runs."""
+    from paper_2605_19388_amd.binding import DFMError
+    F, T, mics, N, K = 2, 40, (17,), 2, 2
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=5, fp32=False, noise=0.1)
+    p = plan(X, mics, N, K, Q, g, W, H, False)
+    with pytest.raises(DFMError) as e:
+        p.iter_forward(1)
+    assert e.value.status == 2  # DFM_E_SHAPE
+    p.mm_backward(p.mm_forward(1))
 
 
 def test_tape_kinds_are_not_interchangeable():
