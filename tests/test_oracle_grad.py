@@ -148,6 +148,27 @@ def test_iter_gradient_equals_finite_differences_with_floors_active():
     _fd_check(X, Q, g, W, H, (2, 1), 1, seed=2, full=True)
 
 
+def test_iter_gradient_with_the_normaliser_floor_active():
+    """A loud recording with a model that keeps y unfloored: V is so large that b^H V b < 1e-6 for
+    every first row of the sweep, so the normaliser of eq. (16) is floored there.  The forward
+    still equals the NumPy oracle's (whose floor is pinned on its own) and the gradient its central
+    differences (the floored normaliser has zero derivative)."""
+    mics = (2, 1)
+    X, Q, g, W, H = _case(F=3, T=12, mics=mics, N=2, K=2, scale=1e5)
+    W, H = 1e-3 * W, 1e-3 * H
+    y = D.model_variance(D.source_psd(W, H), g)
+    assert np.all(y > D.EPS)
+    V = D.weighted_covariances(X, y, mics)
+    s = [float((b.conj() @ Vl[f, 0] @ b).real)
+         for Ql, Vl, ml in zip(D.q_blocks(Q, mics), V, mics) for f in range(3)
+         for b in [np.linalg.solve(Ql[f] @ Vl[f, 0], np.eye(ml)[:, 0])]]
+    assert max(s) < D.EPS
+    L, *_ = G.iter_unrolled_grad(X, Q, g, W, H, mics, 1)
+    ref = _numpy_iter_cost(X, Q, g, W, H, mics, 1)
+    assert abs(L - ref) <= 1e-12 * abs(ref)
+    _fd_check(X, Q, g, W, H, mics, 1, seed=4, full=True)
+
+
 @pytest.mark.parametrize("mics", [(2, 1), (3, 2)])
 def test_iter_gradient_vanishes_on_rows_the_sweep_overwrites_first(mics):
     """The sweep replaces row 1 of each block by a vector fixed, up to its phase, by the other rows
