@@ -119,6 +119,41 @@ def test_autograd_function_matches_the_abi():
         np.testing.assert_array_equal(t.grad.cpu().numpy(), r)
 
 
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_gradient_with_floors_active(fp32):
+    """Two floored regimes of Sec. IV-A against the oracle: a faint recording with a small model (y
+    and the MM denominators floored) through two full iterations, and a loud one (b^H V b of eq.
+    (16) floored on the sweep's first rows, y not) through one.  (After that floored sweep the loud
+    recording's state has y floored everywhere and rows of Q near 1e-9: the cost then changes by
+    less than its own rounding under any relative change of Q, so a second iteration's gradient
+    in Q is rounding noise in both implementations, and is not compared.)"""
+    F, T, mics, N, K = 5, 40, (2, 3), 2, 3
+    for name, xs, ws, n_iter in (("faint", 1e-3, 3e-4, 2), ("loud", 1e5, 1e-3, 1)):
+        X, Q, g, W, H = _problem(F, T, mics, N, K, seed=41, fp32=False)
+        X, W, H = (as_precision(a, fp32) for a in (xs * X, ws * W, ws * H))
+        Q, g = as_precision(Q, fp32), as_precision(g, fp32)
+        y = D.model_variance(D.source_psd(W, H), g)
+        V = D.weighted_covariances(X, y, mics)
+        s_first = max(float((b.conj() @ Vl[f, 0] @ b).real) for Ql, Vl, ml in zip(D.q_blocks(Q, mics), V, mics)
+                      for f in range(F) for b in [np.linalg.solve(Ql[f] @ Vl[f, 0], np.eye(ml)[:, 0])])
+        if name == "faint":
+            assert np.mean(y == D.EPS) > 0.5
+        else:
+            assert s_first < D.EPS and np.all(y > D.EPS)
+        kappa = _kappa(X, Q, g, W, H, mics)
+        cost, (dQ, dg, dW, dH) = _gpu_grad(X, Q, g, W, H, mics, N, K, fp32, n_iter)
+        L, rQ, rg, rW, rH = G.iter_unrolled_grad(X, Q, g, W, H, mics, n_iter)
+        errs = {k: _block_err(a, b) for k, a, b in (("Q", dQ, rQ), ("g", dg, rg), ("W", dW, rW), ("H", dH, rH))}
+        ec = abs(cost - L) / max(abs(L), F * T * sum(mics))
+        report(f"iter gradient, floors active ({name}, n={n_iter}, y floored {np.mean(y == D.EPS):.2f}) "
+               f"{'fp32' if fp32 else 'fp64'}: kappa {kappa:.1e}; cost {ec:.1e}; "
+               + ", ".join(f"d{k} {v:.1e}" for k, v in errs.items()))
+        tol = 1e-4 if fp32 else max(1e-12, 10 * kappa * np.finfo(float).eps)
+        assert ec < (1e-5 if fp32 else 1e-12)
+        for k, v in errs.items():
+            assert v <= tol, (name, k, v)
+
+
 def test_subarrays_beyond_16_mics_are_refused():
     """The sweep's adjoint keeps one block's LU per thread, sized for at most 16 mics: a 17-mic
     subarray is refused (DFM_E_SHAPE) before anything runs; the MM-only gradient still runs."""
