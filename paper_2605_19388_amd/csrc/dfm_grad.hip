@@ -651,6 +651,221 @@ __global__ __launch_bounds__(64) void kb_ipbwd(Dims d, const cx<RQ>* __restrict_
   }
 }
 
+// ---- The sweep and its adjoint for subarrays of at most 4 mics, in registers: every block is
+// padded to 4 x 4 with the identity (Q and V_mu block-diagonal with I in the unused rows and
+// columns), which leaves the used part of A = Q V_mu, b, s, the rows and every adjoint unchanged
+// (the padded entries of b, V b, bbar and gamma stay zero), so that all loop bounds and indices
+// are compile-time constants.  Row exchanges are selects, not indexed moves.
+constexpr int kPad = 4;
+
+struct Pad4 {
+  cd a[kPad][kPad];
+};
+
+__device__ __forceinline__ void pad_lu(Pad4& A, int (&piv)[kPad]) {
+#pragma unroll
+  for (int k = 0; k < kPad; ++k) {
+    int p = k;
+    double best = cabs2(A.a[k][k]);
+#pragma unroll
+    for (int r = k + 1; r < kPad; ++r) {
+      const double v = cabs2(A.a[r][k]);
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    piv[k] = p;
+#pragma unroll
+    for (int r = k + 1; r < kPad; ++r) {
+      const bool sw = p == r;
+#pragma unroll
+      for (int c = 0; c < kPad; ++c) {
+        const cd tk = A.a[k][c], tr = A.a[r][c];
+        A.a[k][c] = sw ? tr : tk;
+        A.a[r][c] = sw ? tk : tr;
+      }
+    }
+    const cd inv = cinv(A.a[k][k]);
+#pragma unroll
+    for (int r = k + 1; r < kPad; ++r) {
+      const cd fac = cmul(A.a[r][k], inv);
+      A.a[r][k] = fac;
+#pragma unroll
+      for (int c = k + 1; c < kPad; ++c) A.a[r][c] = cfms(A.a[r][c], fac, A.a[k][c]);
+    }
+  }
+}
+
+__device__ __forceinline__ void pad_swap(const int (&piv)[kPad], cd (&x)[kPad], bool reverse) {
+#pragma unroll
+  for (int i = 0; i < kPad; ++i) {
+    const int k = reverse ? kPad - 1 - i : i;
+#pragma unroll
+    for (int r = k + 1; r < kPad; ++r) {
+      const bool sw = piv[k] == r;
+      const cd tk = x[k], tr = x[r];
+      x[k] = sw ? tr : tk;
+      x[r] = sw ? tk : tr;
+    }
+  }
+}
+
+__device__ __forceinline__ void pad_solve(const Pad4& A, const int (&piv)[kPad], cd (&x)[kPad]) {
+  pad_swap(piv, x, false);
+#pragma unroll
+  for (int r = 1; r < kPad; ++r)
+#pragma unroll
+    for (int c = 0; c < r; ++c) x[r] = cfms(x[r], A.a[r][c], x[c]);
+#pragma unroll
+  for (int r = kPad - 1; r >= 0; --r) {
+    cd acc = x[r];
+#pragma unroll
+    for (int c = r + 1; c < kPad; ++c) acc = cfms(acc, A.a[r][c], x[c]);
+    x[r] = cmul(acc, cinv(A.a[r][r]));
+  }
+}
+
+__device__ __forceinline__ void pad_solve_h(const Pad4& A, const int (&piv)[kPad], cd (&x)[kPad]) {
+#pragma unroll
+  for (int r = 0; r < kPad; ++r) {
+    cd acc = x[r];
+#pragma unroll
+    for (int c = 0; c < r; ++c) acc = cfms(acc, cconj(A.a[c][r]), x[c]);
+    x[r] = cmul(acc, cinv(cconj(A.a[r][r])));
+  }
+#pragma unroll
+  for (int r = kPad - 2; r >= 0; --r)
+#pragma unroll
+    for (int c = r + 1; c < kPad; ++c) x[r] = cfms(x[r], cconj(A.a[c][r]), x[c]);
+  pad_swap(piv, x, true);
+}
+
+// Padded block (r, c) of an m x m row-major block in global memory.
+__device__ __forceinline__ cd pad_at(const cd* p, int m, int r, int c) {
+  return r < m && c < m ? p[r * m + c] : cd{r == c ? 1.0 : 0.0, 0.0};
+}
+template <typename RQ>
+__device__ __forceinline__ cd pad_at(const cx<RQ>* p, int m, int r, int c) {
+  return r < m && c < m ? cd{(double)p[r * m + c].re, (double)p[r * m + c].im} : cd{r == c ? 1.0 : 0.0, 0.0};
+}
+
+// One row of the sweep, padded: Q (rows from Qlo before mu, else from Qhi), V_mu from Vm.
+template <typename RQ>
+__device__ __forceinline__ void pad_row(int m, int mu, const cd* Qlo, const cx<RQ>* Qhi, const cd* Vm, Pad4& LU,
+                                        int (&piv)[kPad], cd (&b)[kPad], cd (&Vb)[kPad], double& s) {
+  cd V[kPad][kPad];
+#pragma unroll
+  for (int k = 0; k < kPad; ++k)
+#pragma unroll
+    for (int c = 0; c < kPad; ++c) V[k][c] = pad_at(Vm, m, k, c);
+#pragma unroll
+  for (int r = 0; r < kPad; ++r) {
+    cd q[kPad];
+#pragma unroll
+    for (int k = 0; k < kPad; ++k) q[k] = r < mu ? pad_at(Qlo, m, r, k) : pad_at(Qhi, m, r, k);
+#pragma unroll
+    for (int c = 0; c < kPad; ++c) {
+      cd acc = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < kPad; ++k) acc = cfma(acc, q[k], V[k][c]);
+      LU.a[r][c] = acc;
+    }
+  }
+  pad_lu(LU, piv);
+#pragma unroll
+  for (int r = 0; r < kPad; ++r) b[r] = {r == mu ? 1.0 : 0.0, 0.0};
+  pad_solve(LU, piv, b);
+  s = 0.0;
+#pragma unroll
+  for (int r = 0; r < kPad; ++r) {
+    cd acc = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < kPad; ++c) acc = cfma(acc, V[r][c], b[c]);
+    Vb[r] = acc;
+    s += b[r].re * acc.re + b[r].im * acc.im;
+  }
+}
+
+template <typename RQ>
+__global__ __launch_bounds__(64) void kb_ipfwd4(Dims d, const cx<RQ>* __restrict__ Q, const cd* __restrict__ V,
+                                                cd* __restrict__ Q1) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= d.F * d.L) return;
+  const int f = i / d.L, l = i - f * d.L, m = d.mics[l];
+  const size_t q0 = (size_t)f * d.QF + d.qoff[l];
+  Pad4 LU;
+  cd b[kPad], Vb[kPad];
+  int piv[kPad];
+#pragma unroll
+  for (int mu = 0; mu < kPad; ++mu) {
+    if (mu >= m) break;
+    double s;
+    pad_row<RQ>(m, mu, Q1 + q0, Q + q0, V + (size_t)f * d.VC + d.voff[l] + (size_t)mu * m * m, LU, piv, b, Vb, s);
+    const double c = 1.0 / sqrt(s > d.eps ? s : d.eps);
+#pragma unroll
+    for (int j = 0; j < kPad; ++j)
+      if (j < m) Q1[q0 + mu * m + j] = {c * b[j].re, -c * b[j].im};
+  }
+}
+
+template <typename RQ>
+__global__ __launch_bounds__(64) void kb_ipbwd4(Dims d, const cx<RQ>* __restrict__ Q0, const cd* __restrict__ Q1,
+                                                const cd* __restrict__ V, cd* __restrict__ Qbar,
+                                                cd* __restrict__ Vbar) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= d.F * d.L) return;
+  const int f = i / d.L, l = i - f * d.L, m = d.mics[l];
+  const size_t q0 = (size_t)f * d.QF + d.qoff[l];
+  cd Qb[kPad][kPad];  // zero outside the block
+#pragma unroll
+  for (int r = 0; r < kPad; ++r)
+#pragma unroll
+    for (int c = 0; c < kPad; ++c) Qb[r][c] = r < m && c < m ? Qbar[q0 + r * m + c] : cd{0.0, 0.0};
+  Pad4 LU;
+  cd b[kPad], Vb[kPad], bb[kPad];
+  int piv[kPad];
+#pragma unroll
+  for (int mu = kPad - 1; mu >= 0; --mu) {
+    if (mu >= m) continue;
+    const size_t v0 = (size_t)f * d.VC + d.voff[l] + (size_t)mu * m * m;
+    double s;
+    pad_row<RQ>(m, mu, Q1 + q0, Q0 + q0, V + v0, LU, piv, b, Vb, s);
+    const bool live = s > d.eps;
+    const double c = 1.0 / sqrt(live ? s : d.eps);
+    double cbar = 0.0;
+#pragma unroll
+    for (int j = 0; j < kPad; ++j) cbar += Qb[mu][j].re * b[j].re - Qb[mu][j].im * b[j].im;
+    const double sbar = live ? -0.5 * cbar * c * c * c : 0.0;
+#pragma unroll
+    for (int j = 0; j < kPad; ++j)
+      bb[j] = {c * Qb[mu][j].re + 2.0 * sbar * Vb[j].re, -c * Qb[mu][j].im + 2.0 * sbar * Vb[j].im};
+    pad_solve_h(LU, piv, bb);  // gamma
+#pragma unroll
+    for (int j = 0; j < kPad; ++j) Qb[mu][j] = {0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kPad; ++r)
+#pragma unroll
+      for (int j = 0; j < kPad; ++j) Qb[r][j] = cfms(Qb[r][j], bb[r], cconj(Vb[j]));
+#pragma unroll
+    for (int a = 0; a < kPad; ++a) {
+      if (a >= m) break;
+      cd qg = {0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < kPad; ++r) qg = cfmac(qg, r < mu ? pad_at(Q1 + q0, m, r, a) : pad_at(Q0 + q0, m, r, a), bb[r]);
+      const cd coef = {sbar * b[a].re - qg.re, sbar * b[a].im - qg.im};
+#pragma unroll
+      for (int j = 0; j < kPad; ++j)
+        if (j < m) Vbar[v0 + a * m + j] = cmul(coef, cconj(b[j]));
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kPad; ++r)
+#pragma unroll
+    for (int c = 0; c < kPad; ++c)
+      if (r < m && c < m) Qbar[q0 + r * m + c] = Qb[r][c];
+}
+
 // ybar[f][t][o_l + mu] = -Re(x^H Vbar_mu x) / (T y^2), zero where y is floored; one thread per
 // (t, m) of bin f (grid (F, T M / kB)).  With LDS the bin's Vbar is staged there first, each
 // (l, mu) block followed by one pad entry: the block of mic m then starts at voff_l + m + mu M_l^2,
@@ -873,9 +1088,13 @@ static void ip_launch(const Dims& d, const GradTape& t, const cx<RQ>* Q0, bool b
 
 template <typename RQ>
 static void ip_dispatch(const Dims& d, const GradTape& t, const cx<RQ>* Q0, bool backward, hipStream_t s) {
-  if (d.MLX <= 4)
-    ip_launch<RQ, 4>(d, t, Q0, backward, s);
-  else if (d.MLX <= 8)
+  const dim3 grid((d.F * d.L + 63) / 64), blk(64);
+  if (d.MLX <= grad::kPad) {  // registers
+    if (backward)
+      hipLaunchKernelGGL(grad::kb_ipbwd4<RQ>, grid, blk, 0, s, d, Q0, (const cd*)t.Q1, (const cd*)t.V, t.Qbar, t.Vbar);
+    else
+      hipLaunchKernelGGL(grad::kb_ipfwd4<RQ>, grid, blk, 0, s, d, Q0, (const cd*)t.V, t.Q1);
+  } else if (d.MLX <= 8)
     ip_launch<RQ, 8>(d, t, Q0, backward, s);
   else
     ip_launch<RQ, 16>(d, t, Q0, backward, s);
