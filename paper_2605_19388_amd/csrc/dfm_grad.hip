@@ -3,8 +3,8 @@
 // IV-A floors in place.  Two maps: MM iterations (eqs. (8), (9), (10) in that order, Q held fixed)
 // and full iterations (eq. (14) and the IP sweep of eqs. (15)-(16), then (8)-(10)).
 //
-// The forward iterations run on the plan's own kernels and store the state (g, W, H) before each
-// iteration in the caller's tape (per-iteration checkpoints).  The reverse pass then starts from
+// The forward iterations run on the plan's own kernels and store the state (g, W, H; and Q for
+// full iterations) before each iteration in the caller's tape (per-iteration checkpoints).  The reverse pass then starts from
 // the cost's gradient at the final state and walks the iterations backwards; for each it
 // recomputes, from that iteration's checkpoint, the intermediate sums of (8)-(10) and goes back
 // through the g, H and W updates in turn.  With theta' = theta sqrt(a / max(b, eps)) (a, b the
@@ -13,8 +13,8 @@
 //   thetabar (direct) = theta'bar sqrt(a / max(b, eps)),
 // and the sums carry abar, bbar back to the per-frame quantities: y (through P / y^2 and 1 / y;
 // y = max(u, eps), u = sum_n lambda g, has zero derivative where floored), P, lambda = W H and g.
-// The adjoint of P accumulates over all iterations (Q is fixed, so P is one quantity), and the
-// gradient with respect to Q comes last:
+// For MM iterations the adjoint of P accumulates over all iterations (Q is fixed, so P is one
+// quantity), and the gradient with respect to Q comes last:
 //   dL/dRe Q + i dL/dIm Q = 2 sum_t Pbar z conj(x) - 2T Q^-H  (per block, z = Q x).
 //
 // Kernels (one workgroup per bin where a bin's frames are reduced, so every sum has a fixed
@@ -25,8 +25,9 @@
 //   kb_sum_f   out[n][k][t] (+)= sum_f A1[n][f][k] C1[f][t][n] + A2 C2;
 //   kb_cbar    out[f][t][n] = sum_k A1[n][f][k] B1[n][k][t] (and a second pair);
 //   kb_apply / kb_mmback  the update theta' and its adjoint split (elementwise);
-//   kb_frame   per bin, frames in chunks: the per-frame adjoints of one update (or of the cost),
-//              Pbar += ..., lambdabar, and the sums over frames into g's adjoint;
+//   kb_frame   per (bin, slice of frames): the per-frame adjoints of one update (or of the cost),
+//              Pbar += ..., lambdabar, and the slice's sums over frames for g's adjoint, which
+//              kb_gsum adds in slice order;
 //   kb_qgrad   the gradient with respect to Q.
 //
 // Full iterations.  Iteration i maps (Q_i, g_i, W_i, H_i) to Q_{i+1} = IP(Q_i, V(y_i)), then runs
@@ -40,8 +41,9 @@
 //   Vbar_mu = sbar b b^H - (Q^H gamma) b^H,
 // and from V_mu = (1/T) sum_t x x^H / y_mu:  ybar_mu(t) = -Re(x^H Vbar_mu x) / (T y_mu^2).
 // Kernels: kb_y (u = sum_n lambda g), kb_cov (V by eq. (14)), kb_ipfwd (the sweep, kept for
-// P_{i+1}), kb_ipbwd (the sweep's adjoint, one thread per block), kb_vbar (ybar), and kb_frame's
-// kBackY mode (ybar on to g, lambda).
+// P_{i+1}), kb_ipbwd (the sweep's adjoint; both one thread per block, in registers for blocks of
+// up to 4 mics: kb_ipfwd4, kb_ipbwd4), kb_vbar (ybar), and kb_frame's kBackY mode (ybar on to g,
+// lambda).
 #include <hip/hip_runtime.h>
 
 #include "dfm_device.h"
