@@ -88,6 +88,35 @@ def test_gradient_matches_oracle(case, fp32, n_iter):
         assert v <= tol, (k, v)
 
 
+@pytest.mark.parametrize("case", [(1, 3, (1,), 2, 1), (2, 5, (3,), 2, 2), (3, 7, (1, 2, 1), 3, 2), (2, 130, (2, 2), 2, 3)],
+                         ids=lambda c: "x".join(map(str, c[2])) + f"-F{c[0]}-T{c[1]}")
+def test_gradient_at_edge_shapes(case):
+    """One bin, a handful of frames, one-mic subarrays, frames just past a 128-frame slice: both maps
+    against the oracle in FP64 through two iterations.  Each block's error is taken relative to its
+    largest entry, or, where that is below 1e-8 of the block's natural scale |L| / max |theta|, to
+    that scale: with one mic per subarray the full iterations leave the cost independent of Q (the
+    sweep keeps only a phase of Q, which the cost ignores), so dQ is zero up to rounding on both
+    sides."""
+    F, T, mics, N, K = case
+    X, Q, g, W, H = _problem(F, T, mics, N, K, seed=13, fp32=False, noise=0.1)
+    kappa = _kappa(X, Q, g, W, H, mics)
+    tol = max(1e-12, 10 * kappa * np.finfo(float).eps)
+    for kind, ref_fn in (("iter", G.iter_unrolled_grad), ("mm", G.mm_unrolled_grad)):
+        p = plan(X, mics, N, K, Q, g, W, H, False)
+        tape = getattr(p, f"{kind}_forward")(2)
+        cost = p.nll()
+        got = [t.cpu().numpy() for t in getattr(p, f"{kind}_backward")(tape)]
+        torch.cuda.synchronize()
+        L, *ref = ref_fn(X, Q, g, W, H, mics, 2)
+        scales = [abs(L) / np.abs(th).max() for th in (Q, g, W, H)]
+        errs = [float(np.abs(a - b).max() / (np.abs(b).max() if np.abs(b).max() > 1e-8 * sc else sc))
+                for a, b, sc in zip(got, ref, scales)]
+        report(f"{kind} gradient at edge shape {case}: kappa {kappa:.1e}; cost {abs(cost - L) / abs(L):.1e}; "
+               + ", ".join(f"{e:.1e}" for e in errs))
+        assert abs(cost - L) <= 1e-12 * max(abs(L), F * T * sum(mics))
+        assert max(errs) <= tol, (kind, errs)
+
+
 @pytest.mark.parametrize("mics", [(4, 4, 4, 4), (2, 3), (8, 3)], ids=lambda m: "x".join(map(str, m)))
 def test_first_rows_have_zero_gradient(mics):
     """After a full iteration the cost does not depend on the first row of any block of Q (the sweep
