@@ -264,6 +264,7 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
       sb[i] = c2[(size_t)f * N * M + i];
     }
   }
+  __shared__ double gpart2[2 * kB];  // phase 2: the thread groups' partial sums
   double acc1[4] = {0, 0, 0, 0}, acc2[4] = {0, 0, 0, 0};  // phase 2: this thread's (n, m) entries
   __syncthreads();
   {
@@ -328,13 +329,13 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
       }
     }
     __syncthreads();
-    for (int e = 0; e < 4; ++e) {  // (n, m) entries tid, tid + kB, ... (N M <= 4 kB)
-      const int i = tid + e * kB;
-      if (i >= N * M) break;
+    // Phase 2: the slice's sum over frames of each (n, m) entry.  With N M <= kB the entries are
+    // dealt to G = kB / (N M) thread groups, group q taking frames q, q + G, ..., and the groups'
+    // partials are added in group order; otherwise one thread per entry (N M <= 4 kB).
+    auto frame_sum = [&](int i, int j0, int js, double& s1, double& s2) {
       const int n = i / M, m = i - n * M;
-      double s1 = 0.0, s2 = 0.0;
 #pragma unroll 2
-      for (int j = 0; j < nt; ++j) {
+      for (int j = j0; j < nt; j += js) {
         const double lam = sl[j * N + n];
         if (MODE == kFwdG) {
           s1 += lam * sp[j * M + m];
@@ -345,8 +346,32 @@ __global__ __launch_bounds__(kB) void kb_frame(Dims d, const RW* __restrict__ W,
           s1 += su[j * M + m] * lam;
         }
       }
-      acc1[e] += s1;
-      acc2[e] += s2;
+    };
+    const int E = N * M;
+    if (E <= kB) {
+      const int G = kB / E, i = tid % E, q = tid / E;
+      double s1 = 0.0, s2 = 0.0;
+      if (q < G) frame_sum(i, q, G, s1, s2);
+      gpart2[tid] = s1;
+      gpart2[kB + tid] = s2;
+      __syncthreads();
+      if (q == 0) {
+        for (int r = 1; r < G; ++r) {
+          s1 += gpart2[r * E + i];
+          s2 += gpart2[kB + r * E + i];
+        }
+        acc1[0] = s1;
+        acc2[0] = s2;
+      }
+    } else {
+      for (int e = 0; e < 4; ++e) {  // entries tid, tid + kB, ...
+        const int i = tid + e * kB;
+        if (i >= E) break;
+        double s1 = 0.0, s2 = 0.0;
+        frame_sum(i, 0, 1, s1, s2);
+        acc1[e] = s1;
+        acc2[e] = s2;
+      }
     }
   }
   double* pf = part + ((size_t)f * gridDim.y + blockIdx.y) * 2 * N * M;
