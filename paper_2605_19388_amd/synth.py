@@ -24,6 +24,8 @@ Workloads (names are what they are, sizes in the name):
 * ``table2`` -- the shape of the paper's runtime comparison (Sec. IV, Table II):
   F=2049 (4096-point STFT), T=157, three subarrays of four mics (M=12), N=3,
   K=16, 200 iterations; mixing as ``paper_4x4``.
+* ``table2_12`` -- the same recording with one 12-mic block: the method that
+  Table II compares against (all subarrays' mics as one array).
 
 Sources: s_ftn ~ CN(0, (W*_n H*_n)_ft) with W*_n ~ Gamma(1,1)[F,K] and
 H*_n ~ Gamma(1,1)[K,T]; x_ft = sum_n a_fn s_ftn + CN(0, 1e-3 I).
@@ -74,6 +76,8 @@ WORKLOADS = {
                          mixing="delay", seed=1, iters=100, extra={"data_mics": (4, 4, 4, 4)}),
     "table2": Workload("table2", F=2049, T=157, mics=(4, 4, 4), N=3, K=16,
                        mixing="delay", seed=5, iters=200),
+    "table2_12": Workload("table2_12", F=2049, T=157, mics=(12,), N=3, K=16,
+                          mixing="delay", seed=5, iters=200, extra={"data_mics": (4, 4, 4)}),
 }
 
 

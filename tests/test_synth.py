@@ -1,5 +1,6 @@
 """Seeded input generator: determinism, shapes and the statistics of the recipe (CPU only)."""
 import numpy as np
+import pytest
 
 from paper_2605_19388_amd import synth
 
@@ -50,11 +51,13 @@ def test_delay_mixing_is_unit_modulus_times_gain():
     assert np.allclose(r.imag, 0.0, atol=1e-9)
 
 
-def test_conventional_workload_shares_the_recording():
-    """paper_16 separates the very recording of paper_4x4 with one 16-mic block (L = 1)."""
-    a = synth.make("paper_4x4", T=40, F=33)
-    b = synth.make("paper_16", T=40, F=33)
+@pytest.mark.parametrize("dist, conv, m", [("paper_4x4", "paper_16", 16), ("table2", "table2_12", 12)])
+def test_conventional_workload_shares_the_recording(dist, conv, m):
+    """paper_16 and table2_12 separate the very recordings of paper_4x4 and table2 with one block
+    of all the mics (L = 1)."""
+    a = synth.make(dist, T=40, F=33)
+    b = synth.make(conv, T=40, F=33)
     assert np.array_equal(a["X"], b["X"])
-    assert b["mics"] == (16,) and b["Q"].shape == (33, 256)
-    assert np.array_equal(b["Q"][:, ::17], np.ones((33, 16)))  # identity block
+    assert b["mics"] == (m,) and b["Q"].shape == (33, m * m)
+    assert np.array_equal(b["Q"][:, ::m + 1], np.ones((33, m)))  # identity block
     assert np.array_equal(a["W"], b["W"]) and np.array_equal(a["H"], b["H"])
