@@ -105,7 +105,7 @@ static void choose_tiles(Dims& d, int dtype) {
   int sl = d.tile;
   for (; sl > 8; sl /= 2) {
     const size_t gram = r * (d.N * d.K + d.N * d.M + sl * d.M) + 16 + c * sl * d.M;
-    const size_t pw = c * d.QF + 16 + r * (d.N * d.K + d.N * d.M + sl * d.N * 2);
+    const size_t pw = c * d.QF + 16 + r * (d.N * d.K + d.N * d.M + sl * (3 * d.N + 2 * d.M));
     const size_t gg = r * (d.N * d.K + d.N * d.M + sl * d.N + sl * d.M * 2);
     if (gram <= budget && pw <= budget && gg <= budget) break;
   }

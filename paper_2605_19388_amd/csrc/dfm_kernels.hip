@@ -5,7 +5,8 @@
 //   P [F][T][M] real (workspace): powers |(Q_fl x_ft^(l))_mu|^2 of the latest W sub-step.
 //
 // Streaming kernels work on tiles (f, time slice) of d.SL frames with 256 threads:
-// phase 1 puts one frame per thread and writes per-frame quantities to LDS; phase 2
+// phase 1 puts one frame (in k_pw, one (frame, source) or (frame, mic) pair) per thread
+// and writes per-frame quantities to LDS; phase 2
 // puts one output per thread and contracts over the slice's frames from LDS, so no
 // cross-lane reductions are needed.  Per-frequency sums over slices (and the
 // activation update's sum over frequency tiles) are finished by small "apply"
@@ -221,61 +222,65 @@ __global__ __launch_bounds__(kBlock) void k_pw(Dims d, const cx<R>* __restrict__
   const int f = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
   const int t0 = s * d.SL;
   const int nt = min(d.SL, d.T - t0);
+  const int N = d.N, M = d.M;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<R>* sQ = reinterpret_cast<cx<R>*>(smem);
   R* sW = reinterpret_cast<R*>(smem + align_up(sizeof(cx<R>) * d.QF, 16));
-  R* sg = sW + d.N * d.K;
-  R* sab = sg + d.N * d.M;  // [SL][N][2]
+  R* sg = sW + N * d.K;
+  R* sab = sg + N * M;       // [SL][N][2]
+  R* slam = sab + d.SL * N * 2;  // [SL][N]: lambda
+  R* sp = slam + d.SL * N;   // [SL][M]: P / y^2
+  R* sy = sp + d.SL * M;     // [SL][M]: 1 / y
 
   for (int i = tid; i < d.QF; i += kBlock) sQ[i] = Q[(size_t)f * d.QF + i];
-  for (int i = tid; i < d.N * d.K; i += kBlock) {
+  for (int i = tid; i < N * d.K; i += kBlock) {
     const int n = i / d.K, k = i - n * d.K;
     sW[i] = W[((size_t)n * d.F + f) * d.K + k];
   }
-  for (int i = tid; i < d.N * d.M; i += kBlock) sg[i] = g[(size_t)f * d.N * d.M + i];
+  for (int i = tid; i < N * M; i += kBlock) sg[i] = g[(size_t)f * N * M + i];
   __syncthreads();
 
-  for (int tl = tid; tl < nt; tl += kBlock) {
-    const int t = t0 + tl;
-    R lam[kMaxN], a[kMaxN], b[kMaxN];
-    source_psd(d, sW, d.K, H, t, lam);
-#pragma unroll
-    for (int n = 0; n < kMaxN; ++n) {
-      a[n] = 0;
-      b[n] = 0;
+  // lambda per (frame, source).
+  for (int i = tid; i < nt * N; i += kBlock) {
+    const int tl = i / N, n = i - tl * N;
+    const R* hn = H + (size_t)n * d.K * d.T + t0 + tl;
+    R acc = 0;
+    for (int k = 0; k < d.K; ++k) acc += sW[n * d.K + k] * hn[(size_t)k * d.T];
+    slam[i] = acc;
+  }
+  __syncthreads();
+  // P = |Q x|^2, 1 / y and P / y^2 per (frame, mic): the threads of one frame share its x and
+  // write its row of P together.
+  for (int i = tid; i < nt * M; i += kBlock) {
+    const int tl = i / M, m = i - tl * M, l = d.msub[m], Ml = d.mics[l], o = d.moff[l], mu = m - o;
+    const size_t ft = (size_t)f * d.T + t0 + tl;
+    const cx<R>* xr = X + ft * M + o;
+    const cx<R>* qr = sQ + d.qoff[l] + mu * Ml;
+    R zr = 0, zi = 0;
+    for (int c = 0; c < Ml; ++c) {
+      const cx<R> q = qr[c], x = xr[c];
+      zr += q.re * x.re - q.im * x.im;
+      zi += q.re * x.im + q.im * x.re;
     }
-    const cx<R>* xr = X + ((size_t)f * d.T + t) * d.M;
-    R* pr = P + ((size_t)f * d.T + t) * d.M;
-    for (int l = 0; l < d.L; ++l) {
-      const int Ml = d.mics[l], o = d.moff[l];
-      const cx<R>* qb = sQ + d.qoff[l];
-      for (int mu = 0; mu < Ml; ++mu) {
-        R zr = 0, zi = 0;
-        for (int c = 0; c < Ml; ++c) {
-          const cx<R> q = qb[mu * Ml + c];
-          const cx<R> x = xr[o + c];
-          zr += q.re * x.re - q.im * x.im;
-          zi += q.re * x.im + q.im * x.re;
-        }
-        const R p = zr * zr + zi * zi;
-        const int m = o + mu;
-        pr[m] = p;
-        const R iy = (R)1 / model_var(d, lam, sg, m);
-        const R piy2 = p * iy * iy;
-#pragma unroll
-        for (int n = 0; n < kMaxN; ++n)
-          if (n < d.N) {
-            a[n] += sg[n * d.M + m] * piy2;
-            b[n] += sg[n * d.M + m] * iy;
-          }
-      }
+    const R p = zr * zr + zi * zi;
+    P[ft * M + m] = p;
+    R y = 0;
+    for (int n = 0; n < N; ++n) y += slam[tl * N + n] * sg[n * M + m];
+    const R iy = (R)1 / rmax(y, (R)d.eps);
+    sp[i] = p * iy * iy;
+    sy[i] = iy;
+  }
+  __syncthreads();
+  // The per-frame coefficients of eq. (8): a_n = sum_m g P / y^2, b_n = sum_m g / y.
+  for (int i = tid; i < nt * N; i += kBlock) {
+    const int tl = i / N, n = i - tl * N;
+    R a = 0, b = 0;
+    for (int m = 0; m < M; ++m) {
+      a += sg[n * M + m] * sp[tl * M + m];
+      b += sg[n * M + m] * sy[tl * M + m];
     }
-#pragma unroll
-    for (int n = 0; n < kMaxN; ++n)
-      if (n < d.N) {
-        sab[(tl * d.N + n) * 2 + 0] = a[n];
-        sab[(tl * d.N + n) * 2 + 1] = b[n];
-      }
+    sab[i * 2 + 0] = a;
+    sab[i * 2 + 1] = b;
   }
   __syncthreads();
 
@@ -659,7 +664,7 @@ static size_t smem_gram(const Dims& d) {
 }
 template <typename R>
 static size_t smem_pw(const Dims& d) {
-  return align_up(sizeof(cx<R>) * d.QF, 16) + sizeof(R) * (d.N * d.K + d.N * d.M + d.SL * d.N * 2);
+  return align_up(sizeof(cx<R>) * d.QF, 16) + sizeof(R) * (d.N * d.K + d.N * d.M + d.SL * (3 * d.N + 2 * d.M));
 }
 template <typename R>
 static size_t smem_g(const Dims& d) {
