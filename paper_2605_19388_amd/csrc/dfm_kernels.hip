@@ -53,25 +53,48 @@ __global__ __launch_bounds__(kBlock) void k_gram(Dims d, const cx<R>* __restrict
 
   // Sums in FP64 of exact products (the solve of eq. (15) amplifies summation error by
   // cond(V), which is large for nearly rank-deficient mixing).
+  // One work item per (subarray, pair of rows mu, mic pair a <= b): per frame it forms both
+  // parts of x_a conj(x_b) once and adds them into both rows' sums.
   double* out = Vpart + ((size_t)f * d.S + s) * d.VF;
-  for (int idx = tid; idx < d.VF; idx += kBlock) {
-    const int l = subarray_of_vidx(d, idx);
-    const int Ml = d.mics[l];
-    const int r = idx - d.voff[l];
-    const int mu = r / (Ml * Ml);
+  int items = 0;
+  for (int l = 0; l < d.L; ++l) items += (d.mics[l] + 1) / 2 * (d.mics[l] * (d.mics[l] + 1) / 2);
+  for (int it = tid; it < items; it += kBlock) {
+    int l = 0, i = it;
+    for (;; ++l) {
+      const int n = (d.mics[l] + 1) / 2 * (d.mics[l] * (d.mics[l] + 1) / 2);
+      if (i < n) break;
+      i -= n;
+    }
+    const int Ml = d.mics[l], npair = Ml * (Ml + 1) / 2, q = i / npair, pi = i - q * npair;
+    const int mu0 = 2 * q, mu1 = mu0 + 1 < Ml ? mu0 + 1 : -1;
+    const int jre = pi < Ml ? pi : Ml + 2 * (pi - Ml);  // packed index of (a, b) (real part)
     int a, b, part;
-    packed_pair(Ml, r - mu * Ml * Ml, a, b, part);
+    packed_pair(Ml, jre, a, b, part);
+    const bool diag = a == b;
     const int o = d.moff[l];
-    double acc = 0.0;
+    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
     for (int tl = 0; tl < nt; ++tl) {
-      const double w = sinv[tl * d.M + o + mu];
       const cx<R> xa = sx[tl * d.M + o + a];
       const cx<R> xb = sx[tl * d.M + o + b];
       const double ar = xa.re, ai = xa.im, br = xb.re, bi = xb.im;
-      const double v = part == 0 ? ar * br + ai * bi : ai * br - ar * bi;
-      acc += w * v;
+      const double vr = ar * br + ai * bi, vi = ai * br - ar * bi;
+      const double w0 = sinv[tl * d.M + o + mu0];
+      re0 += w0 * vr;
+      im0 += w0 * vi;
+      if (mu1 >= 0) {
+        const double w1 = sinv[tl * d.M + o + mu1];
+        re1 += w1 * vr;
+        im1 += w1 * vi;
+      }
     }
-    out[idx] = acc;
+    double* o0 = out + d.voff[l] + (size_t)mu0 * Ml * Ml + jre;
+    o0[0] = re0;
+    if (!diag) o0[1] = im0;
+    if (mu1 >= 0) {
+      double* o1 = out + d.voff[l] + (size_t)mu1 * Ml * Ml + jre;
+      o1[0] = re1;
+      if (!diag) o1[1] = im1;
+    }
   }
 }
 
