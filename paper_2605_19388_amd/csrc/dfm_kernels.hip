@@ -392,15 +392,29 @@ __global__ __launch_bounds__(kBlock) void k_h(Dims d, const R* __restrict__ W, c
 }
 
 template <typename R>
-__global__ void k_happly(Dims d, R* __restrict__ H, const R* __restrict__ Hpart, int* __restrict__ status) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_happly(Dims d, R* __restrict__ H, const R* __restrict__ Hpart,
+                                                   int* __restrict__ status) {
+  // kHaG thread groups per block of kBlock / kHaG entries: group q adds the frequency tiles
+  // q, q + kHaG, ... of its entry, and the groups' partials are added in group order.
+  constexpr int kHaG = 8, kHaE = kBlock / kHaG;
+  __shared__ R part[2][kHaG][kHaE];
+  const int e = threadIdx.x % kHaE, q = threadIdx.x / kHaE;
+  const int idx = blockIdx.x * kHaE + e;
   const int total = d.N * d.K * d.T;
-  if (idx >= total) return;
   R num = 0, den = 0;
-  for (int fs = 0; fs < d.FS; ++fs) {
-    const R* pp = Hpart + ((size_t)fs * total + idx) * 2;
-    num += pp[0];
-    den += pp[1];
+  if (idx < total)
+    for (int fs = q; fs < d.FS; fs += kHaG) {
+      const R* pp = Hpart + ((size_t)fs * total + idx) * 2;
+      num += pp[0];
+      den += pp[1];
+    }
+  part[0][q][e] = num;
+  part[1][q][e] = den;
+  __syncthreads();
+  if (q != 0 || idx >= total) return;
+  for (int j = 1; j < kHaG; ++j) {
+    num += part[0][j][e];
+    den += part[1][j][e];
   }
   const R v = H[idx] * sqrt(num / rmax(den, (R)d.eps));
   if (d.check && !isfinite(v)) atomicOr(status, kStNonFinite);
@@ -745,7 +759,7 @@ static hipError_t kernel_impl(const Dims& d, const Buffers& b, int kid, hipStrea
                          static_cast<R*>(b.Hpart));
       break;
     case kKHApply:
-      hipLaunchKernelGGL(k_happly<R>, dim3(cdiv((size_t)d.N * d.K * d.T, kBlock)), dim3(kBlock), 0, s, d, H,
+      hipLaunchKernelGGL(k_happly<R>, dim3(cdiv((size_t)d.N * d.K * d.T, kBlock / 8)), dim3(kBlock), 0, s, d, H,
                          static_cast<const R*>(b.Hpart), b.status);
       break;
     case kKG:
