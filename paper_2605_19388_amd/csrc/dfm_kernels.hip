@@ -236,6 +236,150 @@ __global__ __launch_bounds__(kBlock) void k_ip(Dims d, const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------------------
+// The same sweep for subarrays of at most kIpvMax mics, with the V_mu inverted up front: the
+// M_l covariances of the block do not depend on the sweep, so all of them are inverted together
+// in LDS (Gauss-Jordan in place, without pivoting: V_mu is Hermitian positive definite), one
+// elimination step for all of them at once.  Row mu then takes b = V_mu^{-1} c (c = Q^{-1} e_mu),
+// the scaling of eq. (16), the new row and the rank-1 update of Q^{-1}, as in k_ip: four barriers
+// per row instead of one per elimination step.
+constexpr int kIpvMax = 12;
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_ipv(Dims d, const double* __restrict__ Vpart, cx<R>* __restrict__ Q,
+                                                double* __restrict__ logdet, int* __restrict__ status) {
+  const int f = blockIdx.x, l = blockIdx.y, tid = threadIdx.x, bd = blockDim.x;
+  const int Ml = d.mics[l], l2 = 2 * Ml, M2 = Ml * Ml, M3 = M2 * Ml;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int mx = d.MLX;
+  cd* sQ = reinterpret_cast<cd*>(smem);  // Q, rows replaced as the sweep goes [mx * mx]
+  cd* sI = sQ + mx * mx;                  // [Q | I] -> columns Ml .. 2 Ml - 1: Q^{-1} [mx * 2 mx]
+  cd* sV = sI + 2 * mx * mx;              // V_mu -> V_mu^{-1}, [mu][r][c] [mx^3]
+  cd* sp = sV + mx * mx * mx;             // pivot inverses of the current step [mx]
+  cd* sc = sp + mx;                       // [mx] each
+  cd* sb = sc + mx;
+  cd* su = sb + mx;
+  __shared__ double s_logabs, s_w2;
+  __shared__ int s_sing, s_ok, s_vok;
+
+  cx<R>* qb = Q + (size_t)f * d.QF + d.qoff[l];
+  for (int i = tid; i < Ml * l2; i += bd) {
+    const int r = i / l2, c = i - r * l2;
+    const cd q = c < Ml ? cd{(double)qb[r * Ml + c].re, (double)qb[r * Ml + c].im} : cd{c - Ml == r ? 1.0 : 0.0, 0.0};
+    sI[i] = q;
+    if (c < Ml) sQ[r * Ml + c] = q;
+  }
+  {
+    const double* vp = Vpart + (size_t)f * d.SG * d.VF + d.voff[l];
+    const int ns = cov_slots(d, f);
+    const double invT = 1.0 / d.T;
+    for (int i = tid; i < M3; i += bd) {
+      const int mu = i / M2, rc = i - mu * M2, r = rc / Ml, c = rc - r * Ml;
+      const int a = r < c ? r : c, b = r < c ? c : r;  // packed entry of (a, b), a <= b
+      const int pj = a == b ? a : Ml + 2 * (a * Ml - a * (a + 1) / 2 + (b - a - 1));
+      double re = 0.0, im = 0.0;
+      for (int s = 0; s < ns; ++s) {
+        re += vp[(size_t)s * d.VF + mu * M2 + pj];
+        if (a != b) im += vp[(size_t)s * d.VF + mu * M2 + pj + 1];
+      }
+      sV[i] = {re * invT, (r < c ? im : -im) * invT};
+    }
+  }
+  if (tid == 0) s_vok = 0;  // bit mu: V_mu had a zero pivot
+  __syncthreads();
+  eliminate(sI, l2, Ml, l2, &s_logabs, &s_sing);
+  if (s_sing) {  // Q itself singular: keep it, report it (uniform: read after the last barrier)
+    if (tid == 0) {
+      atomicOr(status, kStSingular);
+      logdet[(size_t)f * d.L + l] = -INFINITY;
+    }
+    return;
+  }
+  for (int c = tid; c < Ml; c += bd)
+    for (int r = Ml - 1; r >= 0; --r) {
+      cd acc = sI[r * l2 + Ml + c];
+      for (int j = r + 1; j < Ml; ++j) acc = csub(acc, cmul(sI[r * l2 + j], sI[j * l2 + Ml + c]));
+      sI[r * l2 + Ml + c] = cabs2(sI[r * l2 + r]) == 0.0 ? cd{0.0, 0.0} : cmul(acc, cinv(sI[r * l2 + r]));
+    }
+  // All V_mu^{-1} in place.  Step p: the pivots' inverses; every entry outside row and column p,
+  // A_rc -= A_rp A_pc / A_pp; then row p (A_pc / A_pp), column p (-A_rp / A_pp) and A_pp <- 1 / A_pp.
+  for (int p = 0; p < Ml; ++p) {
+    for (int mu = tid; mu < Ml; mu += bd) {
+      const cd pv = sV[mu * M2 + p * Ml + p];
+      const bool zero = cabs2(pv) == 0.0;
+      if (zero) atomicOr(&s_vok, 1 << mu);
+      sp[mu] = zero ? cd{0.0, 0.0} : cinv(pv);
+    }
+    __syncthreads();
+    for (int i = tid; i < M3; i += bd) {
+      const int mu = i / M2, rc = i - mu * M2, r = rc / Ml, c = rc - r * Ml;
+      if (r == p || c == p) continue;
+      const cd* A = sV + mu * M2;
+      sV[i] = csub(sV[i], cmul(cmul(A[r * Ml + p], sp[mu]), A[p * Ml + c]));
+    }
+    __syncthreads();
+    for (int i = tid; i < Ml * (2 * Ml - 1); i += bd) {
+      const int mu = i / (2 * Ml - 1), k = i - mu * (2 * Ml - 1);
+      cd* A = sV + mu * M2;
+      if (k < Ml) {  // row p, column k
+        A[p * Ml + k] = k == p ? sp[mu] : cmul(A[p * Ml + k], sp[mu]);
+      } else {  // column p, row k - Ml (skipping p)
+        const int r = k - Ml < p ? k - Ml : k - Ml + 1;
+        A[r * Ml + p] = cmul(cd{-A[r * Ml + p].re, -A[r * Ml + p].im}, sp[mu]);
+      }
+    }
+    __syncthreads();
+  }
+  auto qinv = [&](int r, int c) -> cd& { return sI[r * l2 + Ml + c]; };
+
+  for (int mu = 0; mu < Ml; ++mu) {
+    // b = V_mu^{-1} c with c = Q^{-1} e_mu.
+    for (int r = tid; r < Ml; r += bd) {
+      const cd* A = sV + mu * M2 + r * Ml;
+      cd acc = {0.0, 0.0};
+      for (int k = 0; k < Ml; ++k) acc = cfma(acc, A[k], qinv(k, mu));
+      sb[r] = acc;
+      sc[r] = qinv(r, mu);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      bool ok = !((s_vok >> mu) & 1);
+      if (ok) {
+        cd bc = {0.0, 0.0};
+        for (int r = 0; r < Ml; ++r) bc = cadd(bc, cmul(cconj(sb[r]), sc[r]));
+        const double scl = 1.0 / sqrt(bc.re > d.eps ? bc.re : d.eps);
+        for (int r = 0; r < Ml; ++r) sb[r] = {sb[r].re * scl, sb[r].im * scl};
+        s_w2 = cabs2(bc) * scl * scl;  // |b^H c|^2 after the scaling
+        ok = s_w2 > 0.0;
+      }
+      s_ok = ok;
+      if (!ok) atomicOr(status, kStSingular);  // row kept; reported as DFM_E_SINGULAR
+    }
+    __syncthreads();
+    if (!s_ok) continue;
+    for (int c = tid; c < Ml; c += bd) {
+      sQ[mu * Ml + c] = cconj(sb[c]);
+      cd acc = {0.0, 0.0};  // u_c = (b^H Q^{-1})_c
+      for (int k = 0; k < Ml; ++k) acc = cadd(acc, cmul(cconj(sb[k]), qinv(k, c)));
+      su[c] = acc;
+    }
+    __syncthreads();
+    const cd winv = cinv(su[mu]);  // 1 / (b^H c)
+    for (int i = tid; i < M2; i += bd) {
+      const int r = i / Ml, c = i - r * Ml;
+      const cd uc = c == mu ? csub(su[c], cd{1.0, 0.0}) : su[c];
+      qinv(r, c) = csub(qinv(r, c), cmul(sc[r], cmul(uc, winv)));
+    }
+    if (tid == 0) s_logabs += 0.5 * log(s_w2);
+    __syncthreads();
+  }
+  for (int i = tid; i < M2; i += bd) {
+    qb[i].re = (R)sQ[i].re;
+    qb[i].im = (R)sQ[i].im;
+  }
+  if (tid == 0) logdet[(size_t)f * d.L + l] = s_logabs;
+}
+
+// ---------------------------------------------------------------------------------------
 // Powers P = |Q x|^2 and the slice sums of eq. (8):
 //   num_W[n][k] = sum_t H[n][k][t] sum_m g P / y^2,  den_W[n][k] = sum_t H sum_m g / y.
 template <typename R>
@@ -717,6 +861,10 @@ static size_t ip_smem(const Dims& d) {
   const size_t m = d.MLX;
   return sizeof(cd) * (m * m + 2 * m * m + m * (m + 1) + 3 * m);
 }
+static size_t ipv_smem(const Dims& d) {
+  const size_t m = d.MLX;
+  return sizeof(cd) * (3 * m * m + m * m * m + 4 * m);
+}
 static size_t logdet_smem(const Dims& d) { return sizeof(cd) * d.MLX * d.MLX; }
 static size_t qinv_smem(const Dims& d) { return sizeof(cd) * 2 * d.MLX * d.MLX; }
 
@@ -743,8 +891,12 @@ static hipError_t kernel_impl(const Dims& d, const Buffers& b, int kid, hipStrea
                          static_cast<double*>(b.Vpart));
       break;
     case kKIp:
-      hipLaunchKernelGGL(k_ip<R>, dim3(d.F, d.L), dim3(ip_threads(d)), ip_smem(d), s, d,
-                         static_cast<const double*>(b.Vpart), Q, b.logdet, b.status);
+      if (d.MLX > 4 && d.MLX <= kIpvMax)
+        hipLaunchKernelGGL(k_ipv<R>, dim3(d.F, d.L), dim3(kBlock), ipv_smem(d), s, d,
+                           static_cast<const double*>(b.Vpart), Q, b.logdet, b.status);
+      else
+        hipLaunchKernelGGL(k_ip<R>, dim3(d.F, d.L), dim3(ip_threads(d)), ip_smem(d), s, d,
+                           static_cast<const double*>(b.Vpart), Q, b.logdet, b.status);
       break;
     case kKPw:
       hipLaunchKernelGGL(k_pw<R>, tiles, dim3(kBlock), smem_pw<R>(d), s, d, X, Q, W, H, g, P,

@@ -111,6 +111,10 @@ STAGE_CASES = [
     (37, 301, (2, 3, 1), 3, 4),
     (5, 260, (16,), 2, 3),
     (3, 40, (1, 1, 1, 1), 2, 2),
+    # Subarrays of 5 to 12 mics: the IP sweep with the covariances inverted up front.
+    (13, 140, (8, 3), 3, 4),
+    (7, 157, (12,), 3, 16),
+    (5, 90, (5, 7), 2, 3),
     # Shape-specialised kernels, one case per compiled (N, K, M_l) set.
     (9, 97, (4, 4, 4, 4), 5, 16),
     (37, 301, (4, 4, 4, 4), 5, 16),
