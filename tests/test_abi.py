@@ -132,7 +132,23 @@ def test_null_arguments_are_rejected(lib):
     assert lib.dfm_separate(None, fake, None) == 1
     assert lib.dfm_covariances(None, fake, None) == 1
     assert lib.dfm_sync_status(None, None) == 1
+    for kind in ("mm", "iter"):  # the gradients' entries
+        assert getattr(lib, f"dfm_{kind}_tape_size")(None, 1, ctypes.byref(n)) == 1
+        assert getattr(lib, f"dfm_{kind}_forward")(None, 1, fake, 1 << 20, None) == 1
+        assert getattr(lib, f"dfm_{kind}_backward")(None, 1, fake, 1 << 20, fake, fake, fake, fake, None) == 1
     lib.dfm_destroy(None)
+
+
+def test_gradient_tape_kind_is_checked_before_any_launch():
+    """A tape recorded by the MM-only forward is refused by the full-iteration backward (and the
+    other way round) in the binding, before the library is called."""
+    import types
+    import torch
+    from paper_2605_19388_amd.binding import DistributedFastMNMF
+    fake_plan = types.SimpleNamespace(_torch=torch)
+    for kind, recorded in (("iter", "mm"), ("mm", "iter")):
+        with pytest.raises(ValueError):
+            DistributedFastMNMF._grad_backward(fake_plan, kind, (None, 0x1000, 1 << 20, 1, recorded))
 
 
 def test_status_strings(lib):
